@@ -1,0 +1,38 @@
+"""CPU FP64 oracle of the filtered time-domain Krylov eigensolver.
+
+TEST INFRASTRUCTURE.  This package is a plain, slow, obviously correct
+implementation of what the GPU library computes, written from the paper
+(Nannen & Wess, "A Krylov Eigenvalue Solver Based on Filtered Time Domain
+Solutions") in FP64 with NumPy/SciPy.  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the product path never
+does, and it shares no code with the GPU path (the seeded input generators in
+``synth`` are the only common dependency, and they hold none of the method's
+arithmetic).
+
+Modules and the passages they follow:
+
+* ``weights``   - truncated inverse-Fourier weight (Section 2.2, eq. weightf)
+                  and the rectangle-rule coefficients tau*alpha(l*tau)
+                  (Section 2.3, eq. disc_filtercoeff).
+* ``filter``    - scalar recurrence q_l (Section 2.3, def. scalartimestep) and
+                  the fully discrete filter function (Lemma 2.3).
+* ``timestep``  - the operator C: explicit two-step scheme (eq. 2stepmethod)
+                  with y_{-1} = y_0 = r, weighted by the rectangle rule
+                  (Algorithm 2.5, time loop).
+* ``power``     - power iteration for the largest eigenvalue and the time
+                  step / step count rule used by the workloads.
+* ``krylov``    - Algorithm 2.5 (Krylov loop), the projected pencil
+                  (eq. projevp), residuals (eq. res) and acceptance; both the
+                  paper's literal Euclidean-MGS variant and the M-inner CGS2
+                  block variant the GPU library implements.
+
+Parity status: every function is pinned by CPU tests against closed forms,
+invariants or brute force (see ``tests/test_oracle_*.py``); none is
+"parity unpinned".
+"""
+
+from .weights import alpha, discrete_weights  # noqa: F401
+from .filter import q_sequence, beta_tilde  # noqa: F401
+from .timestep import apply_filter  # noqa: F401
+from .power import power_lambda_max, time_step_rule  # noqa: F401
+from .krylov import krylov_basis_paper, krylov_solve, rayleigh_ritz, KrylovResult  # noqa: F401
