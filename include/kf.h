@@ -1,0 +1,190 @@
+/*
+ * kf.h - filtered time-domain Krylov eigensolver for S v = omega^2 M v on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Nannen & Wess, "A Krylov Eigenvalue Solver Based on Filtered Time
+ * Domain Solutions"):
+ *   - Section 2 (eq. def:basisMatrixEVP): S symmetric positive semi-definite,
+ *     M symmetric positive definite; Remark 2.1: M is diagonal (mass lumping),
+ *     passed here as the vector m_diag.
+ *   - Section 2.3 (eq. 2stepmethod, eq. disc_filtercoeff): the operator
+ *     C r = sum_{l=0}^{L-1} tau*alpha(l*tau) y_l with y_{-1} = y_0 = r and
+ *     y_{l+1} = -tau^2 M^{-1} S y_l + 2 y_l - y_{l-1}.
+ *   - Section 2.2 (eq. weightf): the default weights alpha are the truncated
+ *     inverse cosine transform of the indicator of [omega_min, omega_max],
+ *     with T = L*tau.
+ *   - Algorithm 2.5 and Section 2.1 (eq. projevp): Krylov space of C,
+ *     projection of the pencil onto it; Section 2.4 (eq. res): residuals and
+ *     acceptance.
+ *
+ * Conventions for every entry point:
+ *   - All functions return KF_OK (0) or a positive KF_E* code; on error
+ *     kf_last_error() returns a message for the calling thread, and no output
+ *     argument is written except where stated.
+ *   - Matrices are CSR with int32 row pointers and column indices (sorted,
+ *     in range, no duplicates) and float64 values.  Dense blocks are N x b
+ *     row-major float64 unless stated.
+ *   - Host pointers are read during the call only.  Device pointers (flag
+ *     on_device, or where stated) must stay valid for the call; the library
+ *     keeps its own device copies of everything it needs afterwards.
+ *   - Work is issued on kf_options.stream (a hipStream_t; NULL = the legacy
+ *     default stream) and functions return after it has completed, unless
+ *     stated otherwise.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently
+ *     from different threads.
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum kf_status {
+  KF_OK = 0,
+  KF_EINVAL = 1,      /* invalid argument (shape, range, NaN, unsorted CSR, ...) */
+  KF_ENOMEM = 2,      /* device or host allocation failed */
+  KF_EHIP = 3,        /* a HIP runtime call failed */
+  KF_EUNSTABLE = 4,   /* time stepping diverged: tau violates tau < 2/omega_max
+                         (Section 2.3, CFL condition), or a non-finite value */
+  KF_EBREAKDOWN = 5,  /* informational: the Krylov space became invariant
+                         (Algorithm 2.5, zero vector); results are valid */
+  KF_ENOTCONV = 6     /* informational: m_max / max_iters reached before the
+                         target count was accepted; results are valid */
+};
+
+enum kf_precision {
+  KF_FP64 = 0,  /* time stepping, accumulation and projection in float64 */
+  KF_MIXED = 1  /* time stepping and the filter sum in float32;
+                   orthogonalisation, Rayleigh-Ritz and residuals in float64 */
+};
+
+typedef struct kf_csr {
+  int32_t n;             /* number of rows = columns = DOFs, >= 1 */
+  int64_t nnz;           /* number of stored entries, rowptr[n] */
+  const int32_t* rowptr; /* n+1 entries, rowptr[0] = 0, non-decreasing */
+  const int32_t* col;    /* nnz column indices, strictly increasing per row */
+  const double* val;     /* nnz values, finite */
+  int32_t on_device;     /* 0: the three arrays (and m_diag) are host memory;
+                            1: they are device memory */
+} kf_csr;
+
+typedef struct kf_options {
+  int32_t precision;     /* kf_precision */
+  int32_t check_every;   /* Rayleigh-Ritz every this many Krylov iterations
+                            (>= 1); the final state is always checked */
+  int32_t target;        /* stop once this many pairs are accepted (0: never) */
+  int32_t max_iters;     /* cap on filter applications (0: none) */
+  double drop_tol;       /* a new column whose M-norm after orthogonalisation
+                            is <= drop_tol times its M-norm before is dropped
+                            (breakdown test of Algorithm 2.5 with a tolerance);
+                            0 selects 1e-10 */
+  int32_t refine;        /* KF_MIXED only: one float64 filter application and
+                            Rayleigh-Ritz on the near-interval Ritz block */
+  int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
+  int32_t index_bytes;   /* column-index width of the device operator:
+                            0 = automatic (2 when every |col - row| < 32768),
+                            2 or 4 */
+  int32_t xcd_remap;     /* 1: map consecutive row slices to the same XCD */
+  void* stream;          /* hipStream_t */
+} kf_options;
+
+typedef struct kf_problem kf_problem; /* opaque */
+
+typedef struct kf_result {
+  int64_t n;              /* DOFs */
+  int32_t n_pairs;        /* accepted eigenpairs */
+  double* omega2;         /* [n_pairs] accepted eigenvalues omega^2, ascending */
+  double* omega;          /* [n_pairs] sqrt(omega2) */
+  double* residual;       /* [n_pairs] ||S v - omega^2 M v||_2 / ||S v||_2 */
+  double* vectors;        /* [n x n_pairs] column-major, M-normalised Ritz
+                             vectors, or NULL unless want_vectors */
+  int32_t n_ritz;         /* size of the projected pencil at the last check */
+  double* ritz;           /* [n_ritz] all Ritz values omega^2, ascending */
+  int32_t krylov_steps;   /* filter applications performed */
+  int32_t basis_size;     /* columns of the Krylov basis B */
+  int32_t breakdown;      /* 1 when the space became invariant */
+  int32_t status;         /* KF_OK, KF_EBREAKDOWN or KF_ENOTCONV */
+  int64_t leapfrog_vector_steps; /* sum over filter applications of b*(L-1) */
+  double t_total;         /* seconds, whole kf_solve */
+  double t_leapfrog;      /* seconds in the fused time-stepping kernels */
+  double t_gs;            /* seconds in orthogonalisation */
+  double t_rr;            /* seconds in projection updates, eigensolves and
+                             residuals */
+  double t_refine;        /* seconds in the mixed-mode refinement */
+  double orth_error;      /* max |B^T M B - I| over the columns checked */
+} kf_result;
+
+/* Fill *opt with defaults: KF_FP64, check_every 1, no target, no cap,
+ * drop_tol 1e-10, refine 1, no vectors, automatic index width, XCD remap on,
+ * default stream. */
+void kf_default_options(kf_options* opt);
+
+/* Thread-local message describing the last error (never NULL). */
+const char* kf_last_error(void);
+
+/* Build a problem for the pencil (S, diag(m_diag)), the interval
+ * [omega_min, omega_max] (0 <= omega_min < omega_max), time step tau > 0 and
+ * L >= 1 rectangle-rule nodes (T = L*tau).  Copies and validates the inputs,
+ * builds the scaled operator A = tau^2 M^{-1} S on the device (float64, plus a
+ * float32 copy in KF_MIXED) and sets the default weights of eq. weightf.
+ * opt may be NULL (defaults).  *out receives a handle owned by the caller,
+ * released with kf_destroy. */
+int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double omega_max,
+              double tau, int32_t L, const kf_options* opt, kf_problem** out);
+
+/* Release a handle and all its device memory.  NULL is accepted. */
+int kf_destroy(kf_problem* p);
+
+/* Replace the L filter coefficients w_l = tau*alpha(l*tau) (host array of
+ * exactly L finite values; Section 2.2 allows any weight function). */
+int kf_set_weights(kf_problem* p, const double* w, int32_t L);
+
+/* Copy the current L filter coefficients to the host array w_out[L]. */
+int kf_get_weights(const kf_problem* p, double* w_out);
+
+/* Largest eigenvalue estimate of M^{-1} S by `iters` power iterations from the
+ * start vector x0[n] (host, or device when S->on_device), normalised in the
+ * M-norm each iteration; *out = Rayleigh quotient x^T S x / x^T M x of the
+ * last iterate.  Runs on `stream` (NULL = default). */
+int kf_estimate_lambda_max(const kf_csr* S, const double* m_diag, int32_t iters, const double* x0,
+                           void* stream, double* out);
+
+/* The time-step rule used with the estimate: tau = safety*2/sqrt(lambda_est)
+ * (CFL condition tau < 2/omega of Section 2.3) and L = ceil(2*pi/(omega_min*tau)),
+ * i.e. T covers one period of the lowest sought frequency.  Host arithmetic. */
+int kf_time_step_rule(double lambda_est, double omega_min, double safety, double* tau, int32_t* L);
+
+/* Discrete filter function of Lemma 2.3, beta~(omega) = sum_l w_l q_l(omega),
+ * at n points omega[n] (host) into beta_out[n] (host). */
+int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, double* beta_out);
+
+/* y = C x for a block of b columns (1 <= b <= 16): x and y are DEVICE
+ * pointers to n x b row-major float64 blocks (they may not overlap).  The time
+ * stepping runs in the problem's precision.  Asynchronous on the problem's
+ * stream: returns after enqueueing. */
+int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b);
+
+/* Run the eigensolver from the host start block start[n x b] (row-major,
+ * 1 <= b <= 16) until opt.target pairs are accepted (residual <= tol), the
+ * basis reaches m_max columns, opt.max_iters filter applications, or
+ * breakdown.  *out receives a library-owned result released with
+ * kf_result_free.  Synchronous. */
+int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol,
+             kf_result** out);
+
+/* Release a result (NULL accepted). */
+int kf_result_free(kf_result* r);
+
+/* Copy up to max_cols columns of the current Krylov basis B (n x k,
+ * M-orthonormal) to host memory out[n x max_cols] column-major; *ncols
+ * receives the number copied. */
+int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H */

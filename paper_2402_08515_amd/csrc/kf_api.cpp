@@ -1,0 +1,820 @@
+// C ABI and host driver of the filtered time-domain Krylov eigensolver.
+//
+// The driver follows Algorithm 2.5 (Krylov loop around the time loop) with
+// the readings adopted for this library: block of b start vectors, M-inner
+// classical Gram-Schmidt applied twice, a relative drop test instead of an
+// exact zero (breakdown), and Rayleigh-Ritz on the projected pencil of eq.
+// projevp with the residual acceptance of Section 2.4 (eq. res).  Every step
+// on vectors of length n runs in the device kernels; the host only decides
+// control flow from a few scalars per iteration.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kf.h"
+#include "kf_internal.h"
+
+namespace kf {
+
+static thread_local std::string g_err = "no error";
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace kf
+
+using namespace kf;
+
+struct kf_problem {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  double omega_min = 0, omega_max = 0, tau = 0;
+  int32_t L = 0;
+  kf_options opt{};
+  hipStream_t st = nullptr;
+  std::vector<double> w;  // filter coefficients w_l = tau*alpha(l*tau)
+
+  double* d_m = nullptr;  // lumped mass
+  SellOp A;               // tau^2 M^{-1} S in the stepping precision
+  SellOp A64;             // float64 copy for the mixed-mode refinement
+  SellOp S;               // S in float64 (projection, residuals)
+
+  // time-stepping buffers (n x bk in the stepping precision)
+  void* Y0 = nullptr;
+  void* Y1 = nullptr;
+  void* R = nullptr;
+  int ycap = 0;       // block width the buffers hold
+  int yvb = 0;        // value bytes of the buffers
+  // Krylov basis and projected pencil
+  double* B = nullptr;
+  int64_t ldb = 0;
+  int bcap = 0;       // basis columns allocated
+  double* H = nullptr;
+  double* G = nullptr;
+  int hcap = 0;
+  double* T = nullptr;  // (bcap x 32) coefficients
+  double* W = nullptr;  // n x 16 scratch (S Q)
+  double* V = nullptr;  // n x 64 Ritz vectors
+  double* SV = nullptr; // n x 64
+  double* small = nullptr;  // device scalars
+  int32_t* flags = nullptr;
+  GemvTWork gw;
+  GemvTWork rw;
+  EigWork ew;
+  int basis_cols = 0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int kSmall = 4096;
+
+int pow2ceil(int b) {
+  int p = 1;
+  while (p < b) p <<= 1;
+  return p;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+std::vector<double> fourier_weights(double omin, double omax, double tau, int L) {
+  // eq. weightf sampled on the left rectangle nodes l*tau, l < L (T = L*tau)
+  std::vector<double> w((size_t)L);
+  const double pi = 3.14159265358979323846;
+  for (int l = 0; l < L; ++l) {
+    const double t = l * tau;
+    const double a = (l == 0) ? 2.0 * (omax - omin) / pi
+                              : 4.0 / (pi * t) * std::sin(0.5 * t * (omax - omin)) * std::cos(0.5 * t * (omax + omin));
+    w[(size_t)l] = tau * a;
+  }
+  return w;
+}
+
+int validate_csr_host(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col, const double* val,
+                      const double* m) {
+  if (n < 1) return fail(KF_EINVAL, "kf: n must be >= 1");
+  if (nnz < 0) return fail(KF_EINVAL, "kf: nnz must be >= 0");
+  if (rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) return fail(KF_EINVAL, "kf: rowptr[0] must be 0 and rowptr[n] = nnz");
+  for (int32_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return fail(KF_EINVAL, "kf: rowptr must be non-decreasing");
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      if (col[q] < 0 || col[q] >= n) return fail(KF_EINVAL, "kf: column index out of range in row " + std::to_string(i));
+      if (q > rowptr[i] && col[q] <= col[q - 1])
+        return fail(KF_EINVAL, "kf: column indices must be strictly increasing within row " + std::to_string(i));
+      if (!std::isfinite(val[q])) return fail(KF_EINVAL, "kf: non-finite matrix value in row " + std::to_string(i));
+    }
+  }
+  for (int32_t i = 0; i < n; ++i)
+    if (!(m[i] > 0.0) || !std::isfinite(m[i])) return fail(KF_EINVAL, "kf: m_diag must be positive and finite");
+  return KF_OK;
+}
+
+// Host copies of a CSR (pulls device arrays back for validation).
+struct HostCsr {
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val, m;
+};
+
+int fetch_csr(const kf_csr* S, const double* m_diag, HostCsr& h) {
+  if (!S || !m_diag) return fail(KF_EINVAL, "kf: NULL matrix or mass");
+  if (S->n < 1 || S->nnz < 0) return fail(KF_EINVAL, "kf: n must be >= 1 and nnz >= 0");
+  if (!S->rowptr || (S->nnz > 0 && (!S->col || !S->val))) return fail(KF_EINVAL, "kf: NULL CSR array");
+  const size_t n = (size_t)S->n, nnz = (size_t)S->nnz;
+  try {
+    h.rowptr.resize(n + 1);
+    h.col.resize(nnz);
+    h.val.resize(nnz);
+    h.m.resize(n);
+  } catch (const std::bad_alloc&) {
+    return fail(KF_ENOMEM, "kf: host allocation failed");
+  }
+  if (S->on_device) {
+    KF_HIP(hipMemcpy(h.rowptr.data(), S->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (nnz) {
+      KF_HIP(hipMemcpy(h.col.data(), S->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+      KF_HIP(hipMemcpy(h.val.data(), S->val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
+    KF_HIP(hipMemcpy(h.m.data(), m_diag, sizeof(double) * n, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(h.rowptr.data(), S->rowptr, sizeof(int32_t) * (n + 1));
+    if (nnz) {
+      std::memcpy(h.col.data(), S->col, sizeof(int32_t) * nnz);
+      std::memcpy(h.val.data(), S->val, sizeof(double) * nnz);
+    }
+    std::memcpy(h.m.data(), m_diag, sizeof(double) * n);
+  }
+  return validate_csr_host(S->n, S->nnz, h.rowptr.data(), h.col.data(), h.val.data(), h.m.data());
+}
+
+struct DevCsr {
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  ~DevCsr() {
+    if (rowptr) (void)hipFree(rowptr);
+    if (col) (void)hipFree(col);
+    if (val) (void)hipFree(val);
+  }
+};
+
+int upload_csr(const HostCsr& h, int32_t n, int64_t nnz, hipStream_t st, DevCsr& d) {
+  const size_t nz = std::max<int64_t>(nnz, 1);
+  if (hipMalloc(&d.rowptr, sizeof(int32_t) * (n + 1)) != hipSuccess || hipMalloc(&d.col, sizeof(int32_t) * nz) != hipSuccess ||
+      hipMalloc(&d.val, sizeof(double) * nz) != hipSuccess)
+    return fail(KF_ENOMEM, "kf: device allocation for the CSR copy failed");
+  KF_HIP(hipMemcpyAsync(d.rowptr, h.rowptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+  if (nnz) {
+    KF_HIP(hipMemcpyAsync(d.col, h.col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+    KF_HIP(hipMemcpyAsync(d.val, h.val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  }
+  KF_HIP(hipStreamSynchronize(st));
+  return KF_OK;
+}
+
+template <typename Tp>
+int dalloc(Tp** p, size_t count) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, sizeof(Tp) * std::max<size_t>(count, 1)) != hipSuccess) {
+    *p = nullptr;
+    return fail(KF_ENOMEM, "kf: device allocation of " + std::to_string(sizeof(Tp) * count) + " bytes failed");
+  }
+  return KF_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int ensure_step_buffers(kf_problem* p, int bk) {
+  const int vb = p->A.val_bytes;
+  if (p->ycap >= bk && p->yvb == vb) return KF_OK;
+  dfree(p->Y0);
+  dfree(p->Y1);
+  dfree(p->R);
+  p->Y0 = p->Y1 = p->R = nullptr;
+  p->ycap = 0;
+  const size_t bytes = (size_t)p->n * bk * vb;
+  if (hipMalloc(&p->Y0, bytes) != hipSuccess || hipMalloc(&p->Y1, bytes) != hipSuccess ||
+      hipMalloc(&p->R, bytes) != hipSuccess)
+    return fail(KF_ENOMEM, "kf: time-stepping buffers");
+  p->ycap = bk;
+  p->yvb = vb;
+  return KF_OK;
+}
+
+// C applied to bsrc columns of src (strides srs between rows, scs between
+// columns; float64) with kernel block width bk; the first bout columns of the
+// result go to dst (strides drs, dcs).  Asynchronous.
+int run_filter(kf_problem* p, const SellOp& A, const double* src, int64_t srs, int64_t scs, int bsrc, int bk,
+               double* dst, int64_t drs, int64_t dcs, int bout, const std::vector<double>& w) {
+  const int L = (int)w.size();
+  hipStream_t st = p->st;
+  if (L == 1) return launch_scale_copy(p->n, bout, std::min(bsrc, bout), src, srs, scs, w[0], dst, drs, dcs, st);
+  KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, p->Y1, st));
+  void* Y[2] = {p->Y0, p->Y1};
+  for (int l = 1; l < L; ++l) {
+    int mode = (l == 1) ? kFirst : kMid;
+    if (l == L - 1) mode |= kLast;
+    void* cur = Y[l & 1];
+    void* nxt = Y[(l + 1) & 1];
+    KF_TRY(launch_leapfrog(A, bk, mode, cur, nxt, nxt, p->R, dst, drs, dcs, bout, w[0], w[(size_t)l],
+                           p->opt.xcd_remap, st));
+  }
+  return KF_OK;
+}
+
+int ensure_basis(kf_problem* p, int cols) {
+  if (p->bcap >= cols) return KF_OK;
+  dfree(p->B);
+  dfree(p->H);
+  dfree(p->G);
+  dfree(p->T);
+  p->B = p->H = p->G = p->T = nullptr;
+  p->bcap = p->hcap = 0;
+  p->basis_cols = 0;
+  p->ldb = ((int64_t)p->n + 63) / 64 * 64;
+  KF_TRY(dalloc(&p->B, (size_t)p->ldb * cols));
+  KF_TRY(dalloc(&p->H, (size_t)cols * cols));
+  KF_TRY(dalloc(&p->G, (size_t)cols * cols));
+  KF_TRY(dalloc(&p->T, (size_t)cols * 32));
+  p->bcap = cols;
+  p->hcap = cols;
+  return KF_OK;
+}
+
+int ensure_misc(kf_problem* p) {
+  if (p->W) return KF_OK;
+  KF_TRY(dalloc(&p->W, (size_t)p->n * 16));
+  KF_TRY(dalloc(&p->V, (size_t)p->n * 64));
+  KF_TRY(dalloc(&p->SV, (size_t)p->n * 64));
+  KF_TRY(dalloc(&p->small, kSmall));
+  KF_TRY(dalloc(&p->flags, 64));
+  return KF_OK;
+}
+
+// Orthonormalise columns [c0, c0+nb) of B against B[:, 0:kb) and among
+// themselves (M inner product, CGS applied twice at both levels), drop
+// columns that lose more than drop_tol of their M-norm, compact the kept
+// columns to [c0, c0+kept).  ref_out receives the pre-orthogonalisation
+// M-norms.  Synchronises the stream.
+int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
+               hipEvent_t done = nullptr) {
+  hipStream_t st = p->st;
+  const int32_t n = p->n;
+  const int64_t ldb = p->ldb;
+  double* X = p->B + (int64_t)c0 * ldb;
+  double* Tref = p->small;           // nb x nb Gram matrix of the block (before)
+  double* post = p->small + 256;     // nb post norms
+  double* nrm2 = p->small + 512;     // nb squared norms
+  double* coef = p->T;               // kb x nb or j x 1
+  KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, Tref, nb, p->gw, st));
+  if (kb > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      KF_TRY(gemv_t(n, kb, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, kb, p->gw, st));
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef, kb, X, ldb, nb, st));
+    }
+  }
+  const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
+  for (int j = 0; j < nb; ++j) {
+    double* xj = X + (int64_t)j * ldb;
+    if (j > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        KF_TRY(gemv_t(n, j, X, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, coef, j, p->gw, st));
+        KF_TRY(gemv_n_sub(n, j, X, ldb, coef, j, xj, ldb, 1, st));
+      }
+    }
+    KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, nrm2 + j, 1, p->gw, st));
+    KF_TRY(normalize_col(n, xj, nrm2 + j, Tref + (int64_t)j * nb + j, drop, p->flags + j, post + j, st));
+  }
+  if (done) KF_HIP(hipEventRecord(done, st));
+  std::vector<double> gram((size_t)nb * nb);
+  std::vector<int32_t> fl((size_t)nb);
+  KF_HIP(hipMemcpyAsync(gram.data(), Tref, sizeof(double) * nb * nb, hipMemcpyDeviceToHost, st));
+  KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+  KF_HIP(hipStreamSynchronize(st));
+  ref_out.assign((size_t)nb, 0.0);
+  for (int j = 0; j < nb; ++j) ref_out[(size_t)j] = std::sqrt(std::max(gram[(size_t)j * nb + j], 0.0));
+  int cnt = 0;
+  for (int j = 0; j < nb; ++j) {
+    if (!fl[(size_t)j]) continue;
+    if (j != cnt)
+      KF_HIP(hipMemcpyAsync(X + (int64_t)cnt * ldb, X + (int64_t)j * ldb, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                            st));
+    ++cnt;
+  }
+  *kept = cnt;
+  return KF_OK;
+}
+
+// New columns [c0, c0+nc) of the basis: add their rows/columns to
+// H = B^T S B and G = B^T M B.
+int rr_update(kf_problem* p, int c0, int nc) {
+  const int k = c0 + nc;
+  hipStream_t st = p->st;
+  const double* Q = p->B + (int64_t)c0 * p->ldb;
+  KF_TRY(spmv_cols(p->S, Q, p->ldb, p->W, p->n, nc, nullptr, st));
+  KF_TRY(gemv_t(p->n, k, p->B, p->ldb, p->W, nc, p->n, Q, nc, p->ldb, p->d_m, p->T, k, p->gw, st));
+  KF_TRY(rr_scatter(k, c0, nc, p->T, k, p->H, p->G, p->hcap, st));
+  return KF_OK;
+}
+
+struct CheckOut {
+  std::vector<double> ritz;       // all Ritz values
+  std::vector<double> acc_theta;  // accepted
+  std::vector<double> acc_res;
+  std::vector<int> acc_sel;       // index into the candidate list
+  std::vector<double> cand_theta;
+  std::vector<double> cand_res;
+  double orth = 0.0;
+};
+
+// Rayleigh-Ritz on the leading k columns; residuals for the Ritz values in
+// the interval; acceptance at tol.
+int rr_check(kf_problem* p, int k, double tol, CheckOut& out) {
+  hipStream_t st = p->st;
+  KF_TRY(eig_values(p->ew, k, p->H, p->hcap, st));
+  out.ritz.assign((size_t)k, 0.0);
+  KF_HIP(hipMemcpyAsync(out.ritz.data(), p->ew.theta, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
+  KF_HIP(hipMemcpyAsync(&out.orth, p->small + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+  KF_HIP(hipStreamSynchronize(st));
+  const double lo = p->omega_min, hi = p->omega_max;
+  std::vector<double> sel;
+  for (int i = 0; i < k; ++i) {
+    const double om = std::sqrt(std::max(out.ritz[(size_t)i], 0.0));
+    if (om >= lo && om <= hi) sel.push_back(out.ritz[(size_t)i]);
+  }
+  out.cand_theta = sel;
+  out.cand_res.assign(sel.size(), 0.0);
+  out.acc_theta.clear();
+  out.acc_res.clear();
+  out.acc_sel.clear();
+  const int nsel = (int)sel.size();
+  if (nsel == 0) return KF_OK;
+  // clusters of (nearly) equal Ritz values get mutually orthogonal vectors
+  const double tn = std::max(std::fabs(out.ritz.front()), std::fabs(out.ritz.back()));
+  std::vector<int32_t> cl{0};
+  for (int i = 1; i < nsel; ++i)
+    if (sel[(size_t)i] - sel[(size_t)i - 1] > 1e-9 * tn) cl.push_back(i);
+  const int ncl = (int)cl.size();
+  cl.push_back(nsel);
+  KF_TRY(eig_vectors(p->ew, k, sel.data(), cl.data(), ncl, nsel, st));
+  double* d_theta = p->small + 2048;
+  double* d_num = p->small + 2048 + 64;
+  double* d_den = p->small + 2048 + 128;
+  for (int c0 = 0; c0 < nsel; c0 += 64) {
+    const int nc = std::min(64, nsel - c0);
+    KF_TRY(gemm_nn(p->n, k, p->B, p->ldb, p->ew.Y + (int64_t)c0 * k, k, p->V, p->n, nc, st));
+    KF_TRY(spmv_cols(p->S, p->V, p->n, p->SV, p->n, nc, nullptr, st));
+    KF_HIP(hipMemcpyAsync(d_theta, sel.data() + c0, sizeof(double) * nc, hipMemcpyHostToDevice, st));
+    KF_TRY(residual_norms(p->n, p->SV, p->V, p->n, p->d_m, d_theta, nc, d_num, d_den, p->rw, st));
+    std::vector<double> num((size_t)nc), den((size_t)nc);
+    KF_HIP(hipMemcpyAsync(num.data(), d_num, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+    KF_HIP(hipMemcpyAsync(den.data(), d_den, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+    KF_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < nc; ++c) {
+      const double th = sel[(size_t)c0 + c];
+      double dn = std::sqrt(den[(size_t)c]);
+      if (!(dn > 0.0)) dn = std::max(std::fabs(th), 1e-300);
+      const double r = std::sqrt(std::max(num[(size_t)c], 0.0)) / dn;
+      out.cand_res[(size_t)c0 + c] = r;
+      if (r <= tol) {
+        out.acc_theta.push_back(th);
+        out.acc_res.push_back(r);
+        out.acc_sel.push_back(c0 + c);
+      }
+    }
+  }
+  return KF_OK;
+}
+
+void free_problem(kf_problem* p) {
+  if (!p) return;
+  free_sell(p->A);
+  free_sell(p->A64);
+  free_sell(p->S);
+  void* ptrs[] = {p->d_m, p->Y0, p->Y1, p->R, p->B, p->H, p->G, p->T, p->W, p->V, p->SV, p->small, p->flags};
+  for (void* q : ptrs) dfree(q);
+  if (p->gw.partial) (void)hipFree(p->gw.partial);
+  if (p->rw.partial) (void)hipFree(p->rw.partial);
+  free_eig(p->ew);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kf_default_options(kf_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = KF_FP64;
+  o->check_every = 1;
+  o->target = 0;
+  o->max_iters = 0;
+  o->drop_tol = 1e-10;
+  o->refine = 1;
+  o->want_vectors = 0;
+  o->index_bytes = 0;
+  o->xcd_remap = 1;
+  o->stream = nullptr;
+}
+
+const char* kf_last_error(void) { return g_err.c_str(); }
+
+int kf_time_step_rule(double lambda_est, double omega_min, double safety, double* tau, int32_t* L) {
+  if (!tau || !L) return fail(KF_EINVAL, "kf_time_step_rule: NULL output");
+  if (!(lambda_est > 0) || !std::isfinite(lambda_est)) return fail(KF_EINVAL, "kf_time_step_rule: lambda_est must be > 0");
+  if (!(omega_min > 0) || !std::isfinite(omega_min)) return fail(KF_EINVAL, "kf_time_step_rule: omega_min must be > 0");
+  if (!(safety > 0 && safety < 1)) return fail(KF_EINVAL, "kf_time_step_rule: safety must lie in (0, 1)");
+  const double t = safety * 2.0 / std::sqrt(lambda_est);
+  const double pi = 3.14159265358979323846;
+  const double Ld = std::ceil(2.0 * pi / (omega_min * t));
+  if (Ld > 1e9) return fail(KF_EINVAL, "kf_time_step_rule: step count overflows");
+  *tau = t;
+  *L = (int32_t)Ld;
+  return KF_OK;
+}
+
+int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double omega_max, double tau, int32_t L,
+              const kf_options* opt, kf_problem** out) {
+  if (!out) return fail(KF_EINVAL, "kf_create: NULL output handle");
+  *out = nullptr;
+  if (!(omega_min >= 0) || !(omega_max > omega_min) || !std::isfinite(omega_max))
+    return fail(KF_EINVAL, "kf_create: need 0 <= omega_min < omega_max (finite)");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(KF_EINVAL, "kf_create: tau must be positive and finite");
+  if (L < 1) return fail(KF_EINVAL, "kf_create: L must be >= 1");
+  kf_options o;
+  kf_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != KF_FP64 && o.precision != KF_MIXED) return fail(KF_EINVAL, "kf_create: unknown precision");
+  if (o.index_bytes != 0 && o.index_bytes != 2 && o.index_bytes != 4)
+    return fail(KF_EINVAL, "kf_create: index_bytes must be 0, 2 or 4");
+  if (o.check_every < 1) o.check_every = 1;
+  if (!(o.drop_tol > 0)) o.drop_tol = 1e-10;
+  HostCsr h;
+  KF_TRY(fetch_csr(S, m_diag, h));
+
+  kf_problem* p = new (std::nothrow) kf_problem();
+  if (!p) return fail(KF_ENOMEM, "kf_create: host allocation failed");
+  p->n = S->n;
+  p->nnz = S->nnz;
+  p->omega_min = omega_min;
+  p->omega_max = omega_max;
+  p->tau = tau;
+  p->L = L;
+  p->opt = o;
+  p->st = (hipStream_t)o.stream;
+  p->w = fourier_weights(omega_min, omega_max, tau, L);
+  int rc = KF_OK;
+  do {
+    DevCsr dc;
+    rc = upload_csr(h, p->n, p->nnz, p->st, dc);
+    if (rc) break;
+    rc = dalloc(&p->d_m, (size_t)p->n);
+    if (rc) break;
+    if (hipMemcpy(p->d_m, h.m.data(), sizeof(double) * p->n, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(KF_EHIP, "kf_create: copy of m_diag failed");
+      break;
+    }
+    std::vector<double> scale((size_t)p->n);
+    for (int32_t i = 0; i < p->n; ++i) scale[(size_t)i] = tau * tau / h.m[(size_t)i];
+    double* d_scale = nullptr;
+    rc = dalloc(&d_scale, (size_t)p->n);
+    if (rc) break;
+    if (hipMemcpy(d_scale, scale.data(), sizeof(double) * p->n, hipMemcpyHostToDevice) != hipSuccess) {
+      dfree(d_scale);
+      rc = fail(KF_EHIP, "kf_create: copy of the row scaling failed");
+      break;
+    }
+    const int vb = o.precision == KF_MIXED ? 4 : 8;
+    rc = build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, vb, o.index_bytes, p->st, p->A);
+    if (!rc && o.precision == KF_MIXED && o.refine)
+      rc = build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, 8, o.index_bytes, p->st, p->A64);
+    if (!rc) rc = build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, nullptr, 8, o.index_bytes, p->st, p->S);
+    dfree(d_scale);
+    if (rc) break;
+    for (hipEvent_t& e : p->ev)
+      if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
+    if (rc) break;
+  } while (false);
+  if (rc) {
+    free_problem(p);
+    return rc;
+  }
+  *out = p;
+  return KF_OK;
+}
+
+int kf_destroy(kf_problem* p) {
+  if (!p) return KF_OK;
+  (void)hipStreamSynchronize(p->st);
+  free_problem(p);
+  return KF_OK;
+}
+
+int kf_set_weights(kf_problem* p, const double* w, int32_t L) {
+  if (!p || !w) return fail(KF_EINVAL, "kf_set_weights: NULL argument");
+  if (L != p->L) return fail(KF_EINVAL, "kf_set_weights: expected exactly L coefficients");
+  for (int32_t l = 0; l < L; ++l)
+    if (!std::isfinite(w[l])) return fail(KF_EINVAL, "kf_set_weights: non-finite coefficient");
+  p->w.assign(w, w + L);
+  return KF_OK;
+}
+
+int kf_get_weights(const kf_problem* p, double* w_out) {
+  if (!p || !w_out) return fail(KF_EINVAL, "kf_get_weights: NULL argument");
+  std::memcpy(w_out, p->w.data(), sizeof(double) * p->w.size());
+  return KF_OK;
+}
+
+int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, double* beta_out) {
+  if (!p || (n > 0 && (!omega || !beta_out)) || n < 0) return fail(KF_EINVAL, "kf_filter_response: bad arguments");
+  // Lemma 2.3: beta~(omega) = sum_l w_l q_l(omega), q by the scalar recurrence
+  for (int32_t i = 0; i < n; ++i) {
+    const double f = 2.0 - p->tau * p->tau * omega[i] * omega[i];
+    double qm = 1.0, q = 1.0, s = 0.0;
+    for (size_t l = 0; l < p->w.size(); ++l) {
+      s += p->w[l] * q;
+      const double qn = f * q - qm;
+      qm = q;
+      q = qn;
+    }
+    beta_out[i] = s;
+  }
+  return KF_OK;
+}
+
+int kf_estimate_lambda_max(const kf_csr* S, const double* m_diag, int32_t iters, const double* x0, void* stream,
+                           double* out) {
+  if (!out || !x0) return fail(KF_EINVAL, "kf_estimate_lambda_max: NULL argument");
+  if (iters < 0) return fail(KF_EINVAL, "kf_estimate_lambda_max: iters must be >= 0");
+  HostCsr h;
+  KF_TRY(fetch_csr(S, m_diag, h));
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t n = S->n;
+  DevCsr dc;
+  KF_TRY(upload_csr(h, n, S->nnz, st, dc));
+  SellOp op;
+  double *dm = nullptr, *dminv = nullptr, *x = nullptr, *y = nullptr, *sc = nullptr;
+  GemvTWork gw;
+  int rc = KF_OK;
+  do {
+    rc = build_sell(n, S->nnz, dc.rowptr, dc.col, dc.val, nullptr, 8, 0, st, op);
+    if (rc) break;
+    if ((rc = dalloc(&dm, n)) || (rc = dalloc(&dminv, n)) || (rc = dalloc(&x, n)) || (rc = dalloc(&y, n)) ||
+        (rc = dalloc(&sc, 8)))
+      break;
+    std::vector<double> minv((size_t)n);
+    for (int32_t i = 0; i < n; ++i) minv[(size_t)i] = 1.0 / h.m[(size_t)i];
+    if (hipMemcpy(dm, h.m.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dminv, minv.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x, x0, sizeof(double) * n, S->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      rc = fail(KF_EHIP, "kf_estimate_lambda_max: copy failed");
+      break;
+    }
+    // x /= ||x||_M, then iters times x <- M^{-1} S x / ||.||_M
+    if ((rc = gemv_t(n, 1, x, n, nullptr, 0, 0, x, 1, n, dm, sc, 1, gw, st))) break;
+    if ((rc = normalize_col(n, x, sc, nullptr, 0.0, nullptr, nullptr, st))) break;
+    for (int32_t it = 0; it < iters && !rc; ++it) {
+      if ((rc = spmv_cols(op, x, n, y, n, 1, dminv, st))) break;
+      if ((rc = gemv_t(n, 1, y, n, nullptr, 0, 0, y, 1, n, dm, sc, 1, gw, st))) break;
+      if ((rc = normalize_col(n, y, sc, nullptr, 0.0, nullptr, nullptr, st))) break;
+      std::swap(x, y);
+    }
+    if (rc) break;
+    // Rayleigh quotient x^T S x / x^T M x
+    if ((rc = spmv_cols(op, x, n, y, n, 1, nullptr, st))) break;
+    if ((rc = gemv_t(n, 1, x, n, y, 1, n, x, 1, n, dm, sc, 1, gw, st))) break;
+    double hs[2] = {0, 0};
+    if (hipMemcpyAsync(hs, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(KF_EHIP, "kf_estimate_lambda_max: readback failed");
+      break;
+    }
+    if (!(hs[1] > 0) || !std::isfinite(hs[0])) {
+      rc = fail(KF_EINVAL, "kf_estimate_lambda_max: start vector vanished or diverged");
+      break;
+    }
+    *out = hs[0] / hs[1];
+  } while (false);
+  free_sell(op);
+  dfree(dm);
+  dfree(dminv);
+  dfree(x);
+  dfree(y);
+  dfree(sc);
+  if (gw.partial) (void)hipFree(gw.partial);
+  return rc;
+}
+
+int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b) {
+  if (!p || !x || !y) return fail(KF_EINVAL, "kf_apply_filter: NULL argument");
+  if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_apply_filter: b must lie in [1, 16]");
+  const int bk = pow2ceil(b);
+  KF_TRY(ensure_step_buffers(p, bk));
+  return run_filter(p, p->A, x, b, 1, b, bk, y, b, 1, b, p->w);
+}
+
+int kf_result_free(kf_result* r) {
+  if (!r) return KF_OK;
+  std::free(r->omega2);
+  std::free(r->omega);
+  std::free(r->residual);
+  std::free(r->vectors);
+  std::free(r->ritz);
+  std::free(r);
+  return KF_OK;
+}
+
+int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol, kf_result** out) {
+  const double t0 = now_s();
+  if (!p || !start || !out) return fail(KF_EINVAL, "kf_solve: NULL argument");
+  *out = nullptr;
+  if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_solve: b must lie in [1, 16]");
+  if (m_max < b) return fail(KF_EINVAL, "kf_solve: m_max must be >= b");
+  if (m_max > 2048) return fail(KF_EINVAL, "kf_solve: m_max must be <= 2048");
+  if (!(tol > 0)) return fail(KF_EINVAL, "kf_solve: tol must be positive");
+  for (int64_t i = 0; i < (int64_t)p->n * b; ++i)
+    if (!std::isfinite(start[i])) return fail(KF_EINVAL, "kf_solve: non-finite start block");
+  const int bk = pow2ceil(b);
+  hipStream_t st = p->st;
+  KF_TRY(ensure_step_buffers(p, bk));
+  KF_TRY(ensure_basis(p, m_max + bk));
+  KF_TRY(ensure_misc(p));
+  const int32_t n = p->n;
+  const int64_t ldb = p->ldb;
+
+  // start block: host row-major -> V (scratch) -> B[:, 0:b] column-major
+  KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyHostToDevice, st));
+  KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, ldb, st));
+  int kept = 0;
+  std::vector<double> ref;
+  double t_lf = 0, t_gs = 0, t_rr = 0;
+  hipEvent_t* ev = p->ev;
+  auto elapsed = [&](hipEvent_t a, hipEvent_t b2, double& acc) -> int {
+    float ms = 0.f;
+    KF_HIP(hipEventElapsedTime(&ms, a, b2));
+    acc += ms * 1e-3;
+    return KF_OK;
+  };
+  KF_HIP(hipEventRecord(ev[1], st));
+  KF_TRY(orth_block(p, 0, 0, b, &kept, ref, ev[2]));
+  KF_TRY(elapsed(ev[1], ev[2], t_gs));
+  if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
+  KF_HIP(hipEventRecord(ev[3], st));
+  KF_TRY(rr_update(p, 0, kept));
+  KF_HIP(hipEventRecord(ev[4], st));
+  bool rr_pending = true;  // ev[3] -> ev[4] not yet accumulated
+  int cur = kept, q0 = 0, qn = kept;
+  int iters = 0;
+  int64_t lf_steps = 0;
+  bool breakdown = false;
+  const int target = p->opt.target;
+  CheckOut chk;
+  int checked_at = -1;
+  double wsum = 0.0;
+  for (double v : p->w) wsum += std::fabs(v);
+  int status = KF_OK;
+  while (true) {
+    if (p->opt.max_iters > 0 && iters >= p->opt.max_iters) break;
+    if (cur >= m_max) break;
+    KF_HIP(hipEventRecord(ev[0], st));
+    KF_TRY(run_filter(p, p->A, p->B + (int64_t)q0 * ldb, 1, ldb, qn, bk, p->B + (int64_t)cur * ldb, 1, ldb, bk,
+                      p->w));
+    KF_HIP(hipEventRecord(ev[1], st));
+    ++iters;
+    lf_steps += (int64_t)qn * (p->L - 1);
+    KF_TRY(orth_block(p, cur, cur, bk, &kept, ref, ev[2]));  // synchronises the stream
+    if (rr_pending) {
+      KF_TRY(elapsed(ev[3], ev[4], t_rr));
+      rr_pending = false;
+    }
+    KF_TRY(elapsed(ev[0], ev[1], t_lf));
+    KF_TRY(elapsed(ev[1], ev[2], t_gs));
+    for (int j = 0; j < bk; ++j) {
+      // a stable step keeps |C x|_M <= sum|w_l| max|q_l| for |x|_M = 1
+      if (!std::isfinite(ref[(size_t)j]) || ref[(size_t)j] > 1e6 * std::max(wsum, 1e-300)) {
+        return fail(KF_EUNSTABLE, "kf_solve: time stepping diverged (tau too large for the spectrum?)");
+      }
+    }
+    kept = std::min(kept, m_max - cur);
+    if (kept == 0) {
+      breakdown = true;
+      break;
+    }
+    KF_HIP(hipEventRecord(ev[3], st));
+    KF_TRY(rr_update(p, cur, kept));
+    q0 = cur;
+    qn = kept;
+    cur += kept;
+    if (iters % p->opt.check_every == 0) {
+      KF_TRY(rr_check(p, cur, tol, chk));
+      checked_at = cur;
+    }
+    KF_HIP(hipEventRecord(ev[4], st));
+    rr_pending = true;
+    if (checked_at == cur && target > 0 && (int)chk.acc_theta.size() >= target) break;
+  }
+  if (checked_at != cur) {
+    if (!rr_pending) KF_HIP(hipEventRecord(ev[3], st));
+    KF_TRY(rr_check(p, cur, tol, chk));
+    KF_HIP(hipEventRecord(ev[4], st));
+    rr_pending = true;
+  }
+  KF_HIP(hipEventSynchronize(ev[4]));
+  if (rr_pending) KF_TRY(elapsed(ev[3], ev[4], t_rr));
+  p->basis_cols = cur;
+  if (breakdown)
+    status = KF_EBREAKDOWN;
+  else if (target > 0 && (int)chk.acc_theta.size() < target)
+    status = KF_ENOTCONV;
+
+  kf_result* r = (kf_result*)std::calloc(1, sizeof(kf_result));
+  if (!r) return fail(KF_ENOMEM, "kf_solve: result allocation");
+  const int na = (int)chk.acc_theta.size();
+  r->n = n;
+  r->n_pairs = na;
+  r->omega2 = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->omega = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->residual = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->n_ritz = (int)chk.ritz.size();
+  r->ritz = (double*)std::malloc(sizeof(double) * std::max(r->n_ritz, 1));
+  if (!r->omega2 || !r->omega || !r->residual || !r->ritz) {
+    kf_result_free(r);
+    return fail(KF_ENOMEM, "kf_solve: result allocation");
+  }
+  for (int i = 0; i < na; ++i) {
+    r->omega2[i] = chk.acc_theta[(size_t)i];
+    r->omega[i] = std::sqrt(std::max(chk.acc_theta[(size_t)i], 0.0));
+    r->residual[i] = chk.acc_res[(size_t)i];
+  }
+  std::memcpy(r->ritz, chk.ritz.data(), sizeof(double) * r->n_ritz);
+  if (p->opt.want_vectors && na > 0) {
+    r->vectors = (double*)std::malloc(sizeof(double) * (size_t)n * na);
+    if (!r->vectors) {
+      kf_result_free(r);
+      return fail(KF_ENOMEM, "kf_solve: vector allocation");
+    }
+    const int k = cur;
+    for (int a0 = 0; a0 < na; a0 += 64) {
+      const int nc = std::min(64, na - a0);
+      for (int c = 0; c < nc; ++c) {
+        const int s = chk.acc_sel[(size_t)a0 + c];
+        int rc = gemm_nn(n, k, p->B, ldb, p->ew.Y + (int64_t)s * k, k, p->V + (int64_t)c * n, n, 1, st);
+        if (rc) {
+          kf_result_free(r);
+          return rc;
+        }
+      }
+      if (hipMemcpyAsync(r->vectors + (size_t)a0 * n, p->V, sizeof(double) * n * nc, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        kf_result_free(r);
+        return fail(KF_EHIP, "kf_solve: vector readback failed");
+      }
+    }
+  }
+  r->krylov_steps = iters;
+  r->basis_size = cur;
+  r->breakdown = breakdown ? 1 : 0;
+  r->status = status;
+  r->leapfrog_vector_steps = lf_steps;
+  r->t_leapfrog = t_lf;
+  r->t_gs = t_gs;
+  r->t_rr = t_rr;
+  r->t_refine = 0.0;
+  r->orth_error = chk.orth;
+  KF_HIP(hipStreamSynchronize(st));
+  r->t_total = now_s() - t0;
+  *out = r;
+  return KF_OK;
+}
+
+int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols) {
+  if (!p || !out || !ncols || max_cols < 0) return fail(KF_EINVAL, "kf_copy_basis: bad arguments");
+  const int k = std::min(max_cols, (int32_t)p->basis_cols);
+  for (int c = 0; c < k; ++c)
+    KF_HIP(hipMemcpy(out + (size_t)c * p->n, p->B + (int64_t)c * p->ldb, sizeof(double) * p->n, hipMemcpyDeviceToHost));
+  *ncols = k;
+  return KF_OK;
+}
+
+}  // extern "C"

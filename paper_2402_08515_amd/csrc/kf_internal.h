@@ -1,0 +1,148 @@
+// Internal declarations shared by the host driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kf.h"
+
+namespace kf {
+
+// thread-local error text behind kf_last_error()
+void set_error(const std::string& msg);
+
+#define KF_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::kf::set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_)); \
+      return KF_EHIP;                                                                  \
+    }                                                                                  \
+  } while (0)
+
+#define KF_TRY(call)          \
+  do {                        \
+    int s_ = (call);          \
+    if (s_ != KF_OK) return s_; \
+  } while (0)
+
+constexpr int kSlice = 64;  // SELL slice height = wavefront width
+
+// Sliced-ELLPACK operator (slice height 64, one row per lane, entries of a
+// slice stored column by column so that lane l reads entry k of its row at
+// slice_ptr[s] + 64*k + l).  Column indices are either int32 absolute or
+// int16 offsets relative to the row.
+struct SellOp {
+  int32_t n = 0;
+  int32_t nslices = 0;
+  int64_t nstored = 0;
+  int idx_bytes = 4;
+  int val_bytes = 8;
+  int64_t* slice_ptr = nullptr;
+  void* val = nullptr;
+  void* idx = nullptr;
+  int32_t max_width = 0;
+};
+
+void free_sell(SellOp& op);
+
+// Build a SELL operator from a device CSR: values scaled per row by
+// row_scale[i] (device array, or nullptr for 1), stored as float64
+// (val_bytes 8) or float32 (val_bytes 4).  want_idx_bytes 0 chooses 2 when
+// every |col - row| < 32768.
+int build_sell(int32_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_col, const double* d_val,
+               const double* d_row_scale, int val_bytes, int want_idx_bytes, hipStream_t st, SellOp& out);
+
+// ---- fused leapfrog step ----------------------------------------------------
+enum StepMode { kMid = 0, kFirst = 1, kLast = 2, kFirstLast = 3 };
+
+// One step of eq. 2stepmethod fused with the rectangle-rule accumulation:
+//   nxt = 2 cur - prev - A cur   (prev ignored in kFirst: prev = cur)
+//   kFirst:  acc = w0*cur + w*nxt ;  otherwise acc += w*nxt
+//   kLast:   the accumulated value of columns j < bout goes to
+//            rout[i*rs + j*cs] (float64) and nxt is not stored;
+//            otherwise nxt -> out (may alias prev)
+// Blocks are n x b row-major in the stepping precision.
+int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
+                    double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int xcd_remap,
+                    hipStream_t st);
+
+// dst (n x b row-major, stepping precision) = src[i*rs + j*cs] for j < bsrc, 0 beyond.
+int launch_load_block(int val_bytes, int32_t n, int b, int bsrc, const double* src, int64_t rs, int64_t cs,
+                      void* dst, hipStream_t st);
+
+// rout[i*rs + j*cs] = w0 * src[i*srs + j*scs]   (L = 1: C = w0 I)
+int launch_scale_copy(int32_t n, int b, int bsrc, const double* src, int64_t srs, int64_t scs, double w0,
+                      double* rout, int64_t rs, int64_t cs, hipStream_t st);
+
+// ---- tall-skinny float64 kernels (column-major blocks) -----------------------
+// H[j + c*ldh] = sum_i Bk[i + j*ldb] * wc(i) * X_c[i],  j < k, c < n1 + n2,
+// X_c = X1[:, c] (c < n1, weight 1) or X2[:, c - n1] (weight m[i]).
+// Two passes (per-chunk partials, then a fixed-order sum): deterministic.
+struct GemvTWork {
+  double* partial = nullptr;
+  size_t cap = 0;  // doubles
+};
+int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, int n1, int64_t ldx1,
+           const double* X2, int n2, int64_t ldx2, const double* m, double* H, int64_t ldh, GemvTWork& wk,
+           hipStream_t st);
+
+// X[:, c] -= sum_j Bk[:, j] * H[j + c*ldh], c < nrhs
+int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
+               int64_t ldx, int nrhs, hipStream_t st);
+
+// Y[:, c] = S X[:, c] (c < ncols), optional row scaling Y[i,c] *= rscale[i]
+int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,
+              const double* rscale, hipStream_t st);
+
+// column j: x = x * scale where scale = 1/sqrt(nrm2) if sqrt(nrm2) > drop*ref
+// (ref = sqrt(ref2)), else 0; flags[j] = kept, out_norm[j] = sqrt(nrm2)
+int normalize_col(int32_t n, double* x, const double* nrm2, const double* ref2, double drop, int32_t* flag,
+                  double* out_norm, hipStream_t st);
+
+// V[:, c] = Bk * Y[:, c], c < nc  (Y is k x nc column-major, ldy)
+int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, int64_t ldy, double* V,
+            int64_t ldv, int nc, hipStream_t st);
+
+// per column c < nc: num[c] = ||SV_c - theta_c m.*V_c||^2, den[c] = ||SV_c||^2
+int residual_norms(int32_t n, const double* SV, const double* V, int64_t ld, const double* m,
+                   const double* theta, int nc, double* num, double* den, GemvTWork& wk, hipStream_t st);
+
+int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ldd, int nc, hipStream_t st);
+
+// H/G scatter: new columns [c0, c0+nc) from T (k x 2nc: first nc columns of
+// H, next nc of G) into the symmetric k x k matrices (ld ldh).
+int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, double* G, int64_t ldh,
+               hipStream_t st);
+
+// max |G - I| over the leading k x k block -> *out (device scalar)
+int orth_error(int k, const double* G, int64_t ldg, double* out, hipStream_t st);
+
+// ---- small dense symmetric eigensolver (projected pencil) ------------------
+struct EigWork {
+  double* A = nullptr;  // m x m
+  double* d = nullptr;
+  double* e = nullptr;
+  double* tau = nullptr;
+  double* theta = nullptr;
+  double* Z = nullptr;     // m x nsel (tridiagonal eigenvectors)
+  double* Y = nullptr;     // m x nsel (pencil eigenvectors)
+  double* scratch = nullptr;
+  double* sel = nullptr;   // selected eigenvalues
+  int32_t* cl = nullptr;   // cluster starts
+  size_t cap_m = 0, cap_sel = 0;
+};
+void free_eig(EigWork& w);
+int eig_reserve(EigWork& w, int m, int nsel);
+// Tridiagonalise the k x k symmetric matrix H (ld ldh) and compute all
+// eigenvalues ascending into w.theta.
+int eig_values(EigWork& w, int k, const double* H, int64_t ldh, hipStream_t st);
+// Eigenvectors for nsel selected eigenvalues (host array theta_sel, ascending,
+// with cluster ids) into w.Y (k x nsel column-major).
+int eig_vectors(EigWork& w, int k, const double* theta_sel, const int32_t* cluster_start, int nclusters,
+                int nsel, hipStream_t st);
+
+}  // namespace kf

@@ -1,0 +1,770 @@
+// Device kernels of the filtered time-domain Krylov eigensolver (gfx950).
+//
+// Hot path: k_leapfrog, one step of the explicit two-step scheme of Section
+// 2.3 (eq. 2stepmethod) fused with the rectangle-rule accumulation of eq.
+// disc_filtercoeff, over a sliced-ELLPACK copy of A = tau^2 M^{-1} S.  It is
+// bound by HBM bandwidth: per step it streams the matrix once (value + column
+// index per stored entry) and five vector streams (cur gather, prev, next,
+// accumulator read and write).  One wavefront owns a 64-row slice, one lane
+// one row, so every matrix load of a wavefront is a contiguous 64-entry run;
+// the matrix streams are loaded non-temporally to leave the caches to the
+// gathered vector.
+//
+// Around it: float64 tall-skinny kernels for M-inner Gram-Schmidt and the
+// projected pencil (Section 2.1 eq. projevp; Algorithm 2.5 orthogonalisation
+// loop), SpMV with S, and the residuals of Section 2.4 (eq. res).  All
+// reductions are two-pass with a fixed summation order (bitwise repeatable).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kf_internal.h"
+
+namespace kf {
+
+namespace {
+
+inline int ceil_div64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber
+// them so that each XCD receives one contiguous range of row slices and its
+// L2 keeps the neighbouring rows it gathers.
+__device__ __forceinline__ int xcd_map(int i, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = i & 7, t = i >> 3;
+  return (x < r) ? x * (q + 1) + t : r * (q + 1) + (x - r) * q + t;
+}
+
+template <typename T, int B>
+struct alignas((B * sizeof(T)) >= 16 ? 16 : (B * sizeof(T))) Row {
+  T v[B];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ---------------------------------------------------------------- SELL build
+__global__ __launch_bounds__(256) void k_sell_stats(int32_t n, int32_t nslices, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col, int32_t* __restrict__ width,
+                                                    int32_t* __restrict__ maxoff) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gid;
+  int len = 0, off = 0;
+  if (row < n) {
+    const int a = rowptr[row], b = rowptr[row + 1];
+    len = b - a;
+    for (int q = a; q < b; ++q) {
+      int d = col[q] - (int)row;
+      d = d < 0 ? -d : d;
+      off = d > off ? d : off;
+    }
+  }
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    len = max(len, __shfl_xor(len, s));
+    off = max(off, __shfl_xor(off, s));
+  }
+  const int64_t slice = gid >> 6;
+  if ((threadIdx.x & 63) == 0 && slice < nslices) {
+    width[slice] = len;
+    maxoff[slice] = off;
+  }
+}
+
+template <typename VT, typename IT>
+__global__ __launch_bounds__(256) void k_sell_fill(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                   const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, const double* __restrict__ rscale,
+                                                   VT* __restrict__ oval, IT* __restrict__ oidx) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slice = gid >> 6;
+  const int lane = (int)(gid & 63);
+  if (slice >= nslices) return;
+  const int64_t row = gid;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  int a = 0, len = 0;
+  double sc = 1.0;
+  if (row < n) {
+    a = rowptr[row];
+    len = rowptr[row + 1] - a;
+    if (rscale) sc = rscale[row];
+  }
+  for (int q = 0; q < width; ++q) {
+    const int64_t pos = base + (int64_t)q * 64 + lane;
+    if (q < len) {
+      oval[pos] = (VT)(sc * val[a + q]);
+      const int c = col[a + q];
+      oidx[pos] = relative ? (IT)(c - (int)row) : (IT)c;
+    } else {
+      // padding: zero value, index of the row itself (a valid gather)
+      oval[pos] = (VT)0;
+      oidx[pos] = relative ? (IT)0 : (IT)(row < n ? row : 0);
+    }
+  }
+}
+
+// ------------------------------------------------------------ fused leapfrog
+template <typename T, typename IT, int B, int MODE>
+__global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                  const T* __restrict__ val, const IT* __restrict__ idx,
+                                                  const T* __restrict__ cur, const T* prev, T* out,
+                                                  T* __restrict__ acc, double* __restrict__ rout, int64_t rs,
+                                                  int64_t cs, int bout, T w0, T w, int remap) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int slice = wg * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int row = slice * 64 + lane;
+  if (row >= n) return;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  const T* __restrict__ vp = val + base + lane;
+  const IT* __restrict__ ip = idx + base + lane;
+  T sum[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) sum[j] = (T)0;
+#pragma unroll 4
+  for (int q = 0; q < width; ++q) {
+    const T a = __builtin_nontemporal_load(vp + (int64_t)q * 64);
+    const IT ci = __builtin_nontemporal_load(ip + (int64_t)q * 64);
+    const int c = relative ? row + (int)ci : (int)ci;
+    const Row<T, B> x = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) sum[j] = fma(a, x.v[j], sum[j]);
+  }
+  const Row<T, B> yc = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)row * B);
+  Row<T, B> yp;
+  if (MODE & kFirst) {
+    yp = yc;
+  } else {
+    yp = *reinterpret_cast<const Row<T, B>*>(prev + (int64_t)row * B);
+  }
+  Row<T, B> nx;
+#pragma unroll
+  for (int j = 0; j < B; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
+  if (!(MODE & kLast)) *reinterpret_cast<Row<T, B>*>(out + (int64_t)row * B) = nx;
+  Row<T, B> r;
+  if (MODE & kFirst) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
+  } else {
+    r = *reinterpret_cast<const Row<T, B>*>(acc + (int64_t)row * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
+  }
+  if (MODE & kLast) {
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (j < bout) rout[(int64_t)row * rs + (int64_t)j * cs] = (double)r.v[j];
+  } else {
+    *reinterpret_cast<Row<T, B>*>(acc + (int64_t)row * B) = r;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_load_block(int32_t n, int b, int bsrc, const double* __restrict__ src,
+                                                    int64_t rs, int64_t cs, T* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < b; ++j) dst[i * b + j] = j < bsrc ? (T)src[i * rs + (int64_t)j * cs] : (T)0;
+}
+
+__global__ __launch_bounds__(256) void k_scale_copy(int32_t n, int b, int bsrc, const double* __restrict__ src,
+                                                    int64_t srs, int64_t scs, double w0, double* __restrict__ dst,
+                                                    int64_t rs, int64_t cs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < b; ++j) dst[i * rs + (int64_t)j * cs] = j < bsrc ? w0 * src[i * srs + (int64_t)j * scs] : 0.0;
+}
+
+// ------------------------------------------------------- tall-skinny float64
+// Stage 1 of H = Bk^T diag(w) X: one workgroup per (row chunk, group of 64
+// basis columns); the weighted X chunk sits in LDS, each wavefront reduces
+// whole basis columns against it.
+template <int NR>
+__global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                const double* __restrict__ X1, int n1, int64_t ldx1,
+                                                const double* __restrict__ X2, int n2, int64_t ldx2,
+                                                const double* __restrict__ m, double* __restrict__ partial, int CH) {
+  extern __shared__ double xs[];
+  const int nrhs = n1 + n2;
+  const int chunk = blockIdx.x;
+  const int64_t r0 = (int64_t)chunk * CH;
+  const int rows = (int)std::min<int64_t>(CH, (int64_t)n - r0);
+  for (int t = threadIdx.x; t < CH * nrhs; t += blockDim.x) {
+    const int c = t / CH, r = t - c * CH;
+    double v = 0.0;
+    if (r < rows) {
+      const int64_t i = r0 + r;
+      v = c < n1 ? X1[i + (int64_t)c * ldx1] : X2[i + (int64_t)(c - n1) * ldx2] * m[i];
+    }
+    xs[t] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j0 = blockIdx.y * 64;
+  for (int jj = wave; jj < 64; jj += 4) {
+    const int j = j0 + jj;
+    if (j >= k) break;
+    const double* __restrict__ bcol = Bk + (int64_t)j * ldb + r0;
+    double s[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) s[c] = 0.0;
+    for (int r = lane; r < rows; r += 64) {
+      const double bv = bcol[r];
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nrhs) s[c] = fma(bv, xs[c * CH + r], s[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+      if (c < nrhs) s[c] = wave_sum(s[c]);
+    if (lane == 0) {
+      double* p = partial + ((int64_t)chunk * k + j) * nrhs;
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nrhs) p[c] = s[c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
+                                                        const double* __restrict__ partial, double* __restrict__ H,
+                                                        int64_t ldh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * nrhs) return;
+  const int j = t / nrhs, c = t - j * nrhs;
+  double s = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) s += partial[(int64_t)ch * k * nrhs + t];
+  H[j + (int64_t)c * ldh] = s;
+}
+
+// X[:, c] (-)= Bk * H[:, c]   (SUB: subtract from X; else V = Bk H)
+template <int NR, bool SUB>
+__global__ __launch_bounds__(256) void k_gemv_n(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                const double* __restrict__ H, int64_t ldh, double* X, int64_t ldx,
+                                                int nrhs) {
+  constexpr int JT = 128;
+  __shared__ double hs[JT * NR];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c0 = blockIdx.y * NR;
+  const int nc = std::min(NR, nrhs - c0);
+  double acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+  for (int j0 = 0; j0 < k; j0 += JT) {
+    const int jt = std::min(JT, k - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < jt * NR; t += blockDim.x) {
+      const int j = t / NR, c = t - j * NR;
+      hs[t] = c < nc ? H[(j0 + j) + (int64_t)(c0 + c) * ldh] : 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+      const double* __restrict__ bp = Bk + i + (int64_t)j0 * ldb;
+      for (int j = 0; j < jt; ++j) {
+        const double bv = bp[(int64_t)j * ldb];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = fma(bv, hs[j * NR + c], acc[c]);
+      }
+    }
+  }
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      if (c < nc) {
+        double* xp = X + i + (int64_t)(c0 + c) * ldx;
+        if (SUB)
+          *xp -= acc[c];
+        else
+          *xp = acc[c];
+      }
+    }
+  }
+}
+
+template <typename IT, int NC>
+__global__ __launch_bounds__(256) void k_spmv_cols(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                   const double* __restrict__ val, const IT* __restrict__ idx,
+                                                   const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                                   int64_t ldy, int ncols, const double* __restrict__ rscale) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int row = slice * 64 + lane;
+  if (row >= n) return;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int q = 0; q < width; ++q) {
+    const double a = val[base + (int64_t)q * 64 + lane];
+    const IT ci = idx[base + (int64_t)q * 64 + lane];
+    const int64_t col = relative ? row + (int)ci : (int)ci;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) acc[c] = fma(a, X[col + (int64_t)c * ldx], acc[c]);
+  }
+  const double sc = rscale ? rscale[row] : 1.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c < ncols) Y[row + (int64_t)c * ldy] = acc[c] * sc;
+}
+
+__global__ __launch_bounds__(256) void k_normalize_col(int32_t n, double* __restrict__ x,
+                                                       const double* __restrict__ nrm2,
+                                                       const double* __restrict__ ref2, double drop,
+                                                       int32_t* __restrict__ flag, double* __restrict__ out_norm) {
+  const double nr = sqrt(fmax(*nrm2, 0.0));
+  const double rf = ref2 ? sqrt(fmax(*ref2, 0.0)) : 0.0;
+  const bool keep = isfinite(nr) && nr > 0.0 && nr > drop * rf;
+  const double sc = keep ? 1.0 / nr : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = keep ? x[i] * sc : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (flag) *flag = keep ? 1 : 0;
+    if (out_norm) *out_norm = nr;
+  }
+}
+
+// partial[(chunk*nc + c)*2 + {0,1}] = sums over the chunk of
+// (SV - theta m V)^2 and SV^2 for column c
+__global__ __launch_bounds__(256) void k_resid_partial(int32_t n, const double* __restrict__ SV,
+                                                       const double* __restrict__ V, int64_t ld,
+                                                       const double* __restrict__ m,
+                                                       const double* __restrict__ theta, int nc, int CH,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[2][4];
+  const int chunk = blockIdx.x, c = blockIdx.y;
+  const int64_t r0 = (int64_t)chunk * CH;
+  const int64_t r1 = std::min<int64_t>(r0 + CH, n);
+  const double th = theta[c];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const double sv = SV[i + (int64_t)c * ld];
+    const double t = sv - th * m[i] * V[i + (int64_t)c * ld];
+    a = fma(t, t, a);
+    b = fma(sv, sv, b);
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[((int64_t)chunk * nc + c) * 2 + 0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    partial[((int64_t)chunk * nc + c) * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_resid_reduce(int nchunks, int nc, const double* __restrict__ partial,
+                                                      double* __restrict__ num, double* __restrict__ den) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    a += partial[((int64_t)ch * nc + c) * 2 + 0];
+    b += partial[((int64_t)ch * nc + c) * 2 + 1];
+  }
+  num[c] = a;
+  den[c] = b;
+}
+
+__global__ __launch_bounds__(256) void k_copy_cols(int32_t n, const double* __restrict__ src, int64_t lds,
+                                                   double* __restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) dst[i + (int64_t)c * ldd] = src[i + (int64_t)c * lds];
+}
+
+__global__ __launch_bounds__(256) void k_rr_scatter(int k, int c0, int nc, const double* __restrict__ T,
+                                                    int64_t ldt, double* __restrict__ H, double* __restrict__ G,
+                                                    int64_t ldh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * nc) return;
+  const int c = t / k, j = t - c * k;
+  const int col = c0 + c;
+  double h, g;
+  if (j < c0) {
+    h = T[j + (int64_t)c * ldt];
+    g = T[j + (int64_t)(nc + c) * ldt];
+  } else {
+    const int cj = j - c0;  // j is itself a new column
+    h = 0.5 * (T[j + (int64_t)c * ldt] + T[col + (int64_t)cj * ldt]);
+    g = 0.5 * (T[j + (int64_t)(nc + c) * ldt] + T[col + (int64_t)(nc + cj) * ldt]);
+  }
+  H[j + (int64_t)col * ldh] = h;
+  H[col + (int64_t)j * ldh] = h;
+  G[j + (int64_t)col * ldh] = g;
+  G[col + (int64_t)j * ldh] = g;
+}
+
+__global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __restrict__ G, int64_t ldg,
+                                                     double* __restrict__ out) {
+  __shared__ double red[16];
+  double mx = 0.0;
+  const int64_t tot = (int64_t)k * k;
+  for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int64_t c = t / k, j = t - c * k;
+    const double v = fabs(G[j + c * ldg] - (j == c ? 1.0 : 0.0));
+    mx = v > mx ? v : mx;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    *out = r;
+  }
+}
+
+// ---- host-side dispatch helpers
+template <typename T, typename IT, int B>
+int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+  const int grid = ceil_div64(A.nslices, 4);
+  const T* v = static_cast<const T*>(A.val);
+  const IT* ix = static_cast<const IT*>(A.idx);
+  const T* c = static_cast<const T*>(cur);
+  const T* p = static_cast<const T*>(prev);
+  T* o = static_cast<T*>(out);
+  T* a = static_cast<T*>(acc);
+  switch (mode) {
+    case kMid:
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
+                         v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      break;
+    case kFirst:
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      break;
+    case kLast:
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
+                         v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      break;
+    default:
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      break;
+  }
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+template <typename T, typename IT>
+int launch_lf_t(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
+                double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+  switch (b) {
+    case 1: return launch_lf_b<T, IT, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    case 2: return launch_lf_b<T, IT, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    case 4: return launch_lf_b<T, IT, 4>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    case 8: return launch_lf_b<T, IT, 8>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    case 16: return launch_lf_b<T, IT, 16>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    default: set_error("leapfrog: block width must be 1, 2, 4, 8 or 16"); return KF_EINVAL;
+  }
+}
+
+}  // namespace
+
+void free_sell(SellOp& op) {
+  if (op.slice_ptr) (void)hipFree(op.slice_ptr);
+  if (op.val) (void)hipFree(op.val);
+  if (op.idx) (void)hipFree(op.idx);
+  op = SellOp();
+}
+
+int build_sell(int32_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_col, const double* d_val,
+               const double* d_row_scale, int val_bytes, int want_idx_bytes, hipStream_t st, SellOp& out) {
+  free_sell(out);
+  if (n <= 0) {
+    set_error("build_sell: empty matrix");
+    return KF_EINVAL;
+  }
+  const int32_t ns = ceil_div64(n, kSlice);
+  int32_t* d_stats = nullptr;
+  KF_HIP(hipMalloc(&d_stats, sizeof(int32_t) * 2 * (size_t)ns));
+  const int grid = ceil_div64((int64_t)ns * kSlice, 256);
+  hipLaunchKernelGGL(k_sell_stats, dim3(grid), dim3(256), 0, st, n, ns, d_rowptr, d_col, d_stats, d_stats + ns);
+  std::vector<int32_t> h(2 * (size_t)ns);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_stats, sizeof(int32_t) * 2 * ns, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_stats);
+  if (e != hipSuccess) {
+    set_error(std::string("build_sell: ") + hipGetErrorString(e));
+    return KF_EHIP;
+  }
+  std::vector<int64_t> ptr((size_t)ns + 1);
+  ptr[0] = 0;
+  int32_t maxw = 0, maxoff = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    ptr[s + 1] = ptr[s] + (int64_t)h[s] * kSlice;
+    maxw = std::max(maxw, h[s]);
+    maxoff = std::max(maxoff, h[ns + s]);
+  }
+  int ib = want_idx_bytes;
+  if (ib == 0) ib = maxoff < 32768 ? 2 : 4;
+  if (ib == 2 && maxoff >= 32768) {
+    set_error("build_sell: 16-bit relative column offsets requested but |col-row| reaches " +
+              std::to_string(maxoff));
+    return KF_EINVAL;
+  }
+  if (ib != 2 && ib != 4) {
+    set_error("build_sell: index width must be 0, 2 or 4");
+    return KF_EINVAL;
+  }
+  if (val_bytes != 4 && val_bytes != 8) {
+    set_error("build_sell: value width must be 4 or 8");
+    return KF_EINVAL;
+  }
+  const int64_t tot = std::max<int64_t>(ptr[ns], kSlice);
+  out.n = n;
+  out.nslices = ns;
+  out.nstored = ptr[ns];
+  out.idx_bytes = ib;
+  out.val_bytes = val_bytes;
+  out.max_width = maxw;
+  if (hipMalloc(&out.slice_ptr, sizeof(int64_t) * (ns + 1)) != hipSuccess ||
+      hipMalloc(&out.val, (size_t)tot * val_bytes) != hipSuccess ||
+      hipMalloc(&out.idx, (size_t)tot * ib) != hipSuccess) {
+    free_sell(out);
+    set_error("build_sell: device allocation failed");
+    return KF_ENOMEM;
+  }
+  KF_HIP(hipMemcpyAsync(out.slice_ptr, ptr.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+  if (val_bytes == 8 && ib == 2)
+    hipLaunchKernelGGL((k_sell_fill<double, int16_t>), dim3(grid), dim3(256), 0, st, n, ns, out.slice_ptr, d_rowptr,
+                       d_col, d_val, d_row_scale, (double*)out.val, (int16_t*)out.idx);
+  else if (val_bytes == 8)
+    hipLaunchKernelGGL((k_sell_fill<double, int32_t>), dim3(grid), dim3(256), 0, st, n, ns, out.slice_ptr, d_rowptr,
+                       d_col, d_val, d_row_scale, (double*)out.val, (int32_t*)out.idx);
+  else if (ib == 2)
+    hipLaunchKernelGGL((k_sell_fill<float, int16_t>), dim3(grid), dim3(256), 0, st, n, ns, out.slice_ptr, d_rowptr,
+                       d_col, d_val, d_row_scale, (float*)out.val, (int16_t*)out.idx);
+  else
+    hipLaunchKernelGGL((k_sell_fill<float, int32_t>), dim3(grid), dim3(256), 0, st, n, ns, out.slice_ptr, d_rowptr,
+                       d_col, d_val, d_row_scale, (float*)out.val, (int32_t*)out.idx);
+  KF_HIP(hipGetLastError());
+  KF_HIP(hipStreamSynchronize(st));
+  (void)nnz;
+  return KF_OK;
+}
+
+int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
+                    double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int xcd_remap,
+                    hipStream_t st) {
+  if (A.val_bytes == 8) {
+    if (A.idx_bytes == 2)
+      return launch_lf_t<double, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+    return launch_lf_t<double, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+  }
+  if (A.idx_bytes == 2)
+    return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+  return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+}
+
+int launch_load_block(int val_bytes, int32_t n, int b, int bsrc, const double* src, int64_t rs, int64_t cs,
+                      void* dst, hipStream_t st) {
+  const int grid = ceil_div64(n, 256);
+  if (val_bytes == 8)
+    hipLaunchKernelGGL(k_load_block<double>, dim3(grid), dim3(256), 0, st, n, b, bsrc, src, rs, cs, (double*)dst);
+  else
+    hipLaunchKernelGGL(k_load_block<float>, dim3(grid), dim3(256), 0, st, n, b, bsrc, src, rs, cs, (float*)dst);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int launch_scale_copy(int32_t n, int b, int bsrc, const double* src, int64_t srs, int64_t scs, double w0,
+                      double* rout, int64_t rs, int64_t cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, b, bsrc, src, srs, scs, w0, rout,
+                     rs, cs);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, int n1, int64_t ldx1,
+           const double* X2, int n2, int64_t ldx2, const double* m, double* H, int64_t ldh, GemvTWork& wk,
+           hipStream_t st) {
+  const int nrhs = n1 + n2;
+  if (k <= 0 || nrhs <= 0) return KF_OK;
+  if (nrhs > 32) {
+    set_error("gemv_t: at most 32 right-hand sides");
+    return KF_EINVAL;
+  }
+  if (n2 > 0 && m == nullptr) {
+    set_error("gemv_t: weighted columns need the mass vector");
+    return KF_EINVAL;
+  }
+  const int CH = nrhs <= 8 ? 1024 : (nrhs <= 16 ? 512 : 256);
+  const int nchunks = ceil_div64(n, CH);
+  const size_t need = (size_t)nchunks * k * nrhs;
+  if (wk.cap < need) {
+    if (wk.partial) (void)hipFree(wk.partial);
+    wk.partial = nullptr;
+    wk.cap = 0;
+    const size_t cap = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&wk.partial, cap * sizeof(double)) != hipSuccess) {
+      set_error("gemv_t: cannot allocate the partial-sum buffer");
+      return KF_ENOMEM;
+    }
+    wk.cap = cap;
+  }
+  const dim3 grid(nchunks, ceil_div64(k, 64));
+  const size_t lds = sizeof(double) * CH * nrhs;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_gemv_t<1>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 2)
+    hipLaunchKernelGGL(k_gemv_t<2>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL(k_gemv_t<4>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL(k_gemv_t<8>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 16)
+    hipLaunchKernelGGL(k_gemv_t<16>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else
+    hipLaunchKernelGGL(k_gemv_t<32>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 256)), dim3(256), 0, st, nchunks, k, nrhs,
+                     wk.partial, H, ldh);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
+               int64_t ldx, int nrhs, hipStream_t st) {
+  if (k <= 0 || nrhs <= 0) return KF_OK;
+  const int NR = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8);
+  const dim3 grid(ceil_div64(n, 256), ceil_div64(nrhs, NR));
+  if (NR == 1)
+    hipLaunchKernelGGL((k_gemv_n<1, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+  else if (NR == 4)
+    hipLaunchKernelGGL((k_gemv_n<4, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+  else
+    hipLaunchKernelGGL((k_gemv_n<8, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, int64_t ldy, double* V, int64_t ldv,
+            int nc, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
+  hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols, const double* rscale,
+              hipStream_t st) {
+  if (S.val_bytes != 8) {
+    set_error("spmv_cols: needs the float64 operator");
+    return KF_EINVAL;
+  }
+  const int grid = ceil_div64(S.nslices, 4);
+  for (int c0 = 0; c0 < ncols; c0 += 16) {
+    const int nc = std::min(16, ncols - c0);
+    const double* x = X + (int64_t)c0 * ldx;
+    double* y = Y + (int64_t)c0 * ldy;
+    if (S.idx_bytes == 2) {
+      if (nc == 1)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 1>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 4)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+    } else {
+      if (nc == 1)
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 1>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 4)
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+    }
+    KF_HIP(hipGetLastError());
+  }
+  return KF_OK;
+}
+
+int normalize_col(int32_t n, double* x, const double* nrm2, const double* ref2, double drop, int32_t* flag,
+                  double* out_norm, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize_col, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, x, nrm2, ref2, drop, flag,
+                     out_norm);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int residual_norms(int32_t n, const double* SV, const double* V, int64_t ld, const double* m, const double* theta,
+                   int nc, double* num, double* den, GemvTWork& wk, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  const int CH = 8192;
+  const int nchunks = ceil_div64(n, CH);
+  const size_t need = (size_t)nchunks * nc * 2;
+  if (wk.cap < need) {
+    if (wk.partial) (void)hipFree(wk.partial);
+    wk.partial = nullptr;
+    wk.cap = 0;
+    if (hipMalloc(&wk.partial, need * sizeof(double)) != hipSuccess) {
+      set_error("residual_norms: allocation failed");
+      return KF_ENOMEM;
+    }
+    wk.cap = need;
+  }
+  hipLaunchKernelGGL(k_resid_partial, dim3(nchunks, nc), dim3(256), 0, st, n, SV, V, ld, m, theta, nc, CH,
+                     wk.partial);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_resid_reduce, dim3(ceil_div64(nc, 256)), dim3(256), 0, st, nchunks, nc, wk.partial, num, den);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ldd, int nc, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div64(n, 256), nc), dim3(256), 0, st, n, src, lds, dst, ldd);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, double* G, int64_t ldh,
+               hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  hipLaunchKernelGGL(k_rr_scatter, dim3(ceil_div64((int64_t)k * nc, 256)), dim3(256), 0, st, k, c0, nc, T, ldt, H, G,
+                     ldh);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int orth_error(int k, const double* G, int64_t ldg, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_orth_error, dim3(1), dim3(1024), 0, st, k, G, ldg, out);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+}  // namespace kf

@@ -1,0 +1,295 @@
+"""ctypes binding of libkf.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts NumPy /
+SciPy / torch objects to the plain pointers and sizes of ``include/kf.h`` and
+back.  torch is imported first so that the process has one HIP runtime (the
+one torch loaded) and so that device blocks can be handed over as torch
+tensors on the current stream.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+import torch  # noqa: F401  (load torch's HIP runtime before libkf.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkf.so")
+
+KF_OK, KF_EINVAL, KF_ENOMEM, KF_EHIP, KF_EUNSTABLE, KF_EBREAKDOWN, KF_ENOTCONV = range(7)
+KF_FP64, KF_MIXED = 0, 1
+_PREC = {"fp64": KF_FP64, "mixed": KF_MIXED}
+
+
+class KfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[kf status {code}] {msg}")
+        self.code = code
+
+
+class CsrT(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("nnz", C.c_int64),
+        ("rowptr", C.c_void_p),
+        ("col", C.c_void_p),
+        ("val", C.c_void_p),
+        ("on_device", C.c_int32),
+    ]
+
+
+class OptionsT(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32),
+        ("check_every", C.c_int32),
+        ("target", C.c_int32),
+        ("max_iters", C.c_int32),
+        ("drop_tol", C.c_double),
+        ("refine", C.c_int32),
+        ("want_vectors", C.c_int32),
+        ("index_bytes", C.c_int32),
+        ("xcd_remap", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class ResultT(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("n_pairs", C.c_int32),
+        ("omega2", C.POINTER(C.c_double)),
+        ("omega", C.POINTER(C.c_double)),
+        ("residual", C.POINTER(C.c_double)),
+        ("vectors", C.POINTER(C.c_double)),
+        ("n_ritz", C.c_int32),
+        ("ritz", C.POINTER(C.c_double)),
+        ("krylov_steps", C.c_int32),
+        ("basis_size", C.c_int32),
+        ("breakdown", C.c_int32),
+        ("status", C.c_int32),
+        ("leapfrog_vector_steps", C.c_int64),
+        ("t_total", C.c_double),
+        ("t_leapfrog", C.c_double),
+        ("t_gs", C.c_double),
+        ("t_rr", C.c_double),
+        ("t_refine", C.c_double),
+        ("orth_error", C.c_double),
+    ]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "kf_default_options": (None, [C.POINTER(OptionsT)]),
+    "kf_last_error": (C.c_char_p, []),
+    "kf_create": (
+        C.c_int,
+        [C.POINTER(CsrT), C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(OptionsT),
+         C.POINTER(C.c_void_p)],
+    ),
+    "kf_destroy": (C.c_int, [C.c_void_p]),
+    "kf_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "kf_get_weights": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kf_estimate_lambda_max": (
+        C.c_int, [C.POINTER(CsrT), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+    ),
+    "kf_time_step_rule": (C.c_int, [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "kf_filter_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "kf_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
+    "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
+    "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+}
+
+
+def lib():
+    """Load libkf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().kf_last_error().decode()
+
+
+def _check(code: int):
+    if code not in (KF_OK,):
+        raise KfError(code, last_error())
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _host_csr(S):
+    import scipy.sparse as sp
+
+    S = sp.csr_matrix(S)
+    rowptr = np.ascontiguousarray(S.indptr, dtype=np.int32)
+    col = np.ascontiguousarray(S.indices, dtype=np.int32)
+    val = np.ascontiguousarray(S.data, dtype=np.float64)
+    keep = (rowptr, col, val)
+    c = CsrT(S.shape[0], int(S.nnz), _ptr(rowptr), _ptr(col), _ptr(val), 0)
+    return c, keep
+
+
+def _stream_handle() -> int:
+    # the legacy default stream (0) when torch sees no device: validation
+    # errors are raised before any device call
+    if not torch.cuda.is_available():
+        return 0
+    return torch.cuda.current_stream().cuda_stream
+
+
+def time_step_rule(lambda_est: float, omega_min: float, safety: float = 0.9):
+    tau = C.c_double()
+    L = C.c_int32()
+    _check(lib().kf_time_step_rule(lambda_est, omega_min, safety, C.byref(tau), C.byref(L)))
+    return tau.value, L.value
+
+
+def estimate_lambda_max(S, m, iters: int, x0) -> float:
+    c, keep = _host_csr(S)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    out = C.c_double()
+    _check(lib().kf_estimate_lambda_max(C.byref(c), _ptr(m), iters, _ptr(x0), _stream_handle(), C.byref(out)))
+    return out.value
+
+
+@dataclass
+class SolveResult:
+    omega2: np.ndarray
+    omega: np.ndarray
+    residual: np.ndarray
+    vectors: np.ndarray | None
+    ritz: np.ndarray
+    krylov_steps: int
+    basis_size: int
+    breakdown: bool
+    status: int
+    leapfrog_vector_steps: int
+    t_total: float
+    t_leapfrog: float
+    t_gs: float
+    t_rr: float
+    t_refine: float
+    orth_error: float
+
+
+class Problem:
+    """Handle of ``kf_create``: pencil, interval, tau, L and options."""
+
+    def __init__(self, S, m, omega_min: float, omega_max: float, tau: float, L: int, precision: str = "fp64",
+                 check_every: int = 1, target: int = 0, max_iters: int = 0, drop_tol: float = 1e-10,
+                 refine: bool = True, want_vectors: bool = False, index_bytes: int = 0, xcd_remap: bool = True):
+        L_ = lib()
+        self._h = C.c_void_p()
+        opt = OptionsT()
+        L_.kf_default_options(C.byref(opt))
+        opt.precision = _PREC[precision]
+        opt.check_every = check_every
+        opt.target = target
+        opt.max_iters = max_iters
+        opt.drop_tol = drop_tol
+        opt.refine = int(refine)
+        opt.want_vectors = int(want_vectors)
+        opt.index_bytes = index_bytes
+        opt.xcd_remap = int(xcd_remap)
+        opt.stream = _stream_handle()
+        c, keep = _host_csr(S)
+        m = np.ascontiguousarray(m, dtype=np.float64)
+        _check(L_.kf_create(C.byref(c), _ptr(m), omega_min, omega_max, tau, L, C.byref(opt), C.byref(self._h)))
+        self.n = S.shape[0]
+        self.L = L
+        self.tau = tau
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kf_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self) -> np.ndarray:
+        w = np.empty(self.L)
+        _check(lib().kf_get_weights(self._h, _ptr(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(lib().kf_set_weights(self._h, _ptr(w), int(w.size)))
+
+    def filter_response(self, omega) -> np.ndarray:
+        om = np.ascontiguousarray(np.atleast_1d(omega), dtype=np.float64)
+        out = np.empty_like(om)
+        _check(lib().kf_filter_response(self._h, _ptr(om), int(om.size), _ptr(out)))
+        return out
+
+    def apply_filter(self, x: torch.Tensor) -> torch.Tensor:
+        """y = C x for a device block x (n x b float64, contiguous)."""
+        if x.dim() == 1:
+            x = x[:, None]
+        if x.device.type != "cuda" or x.dtype != torch.float64 or not x.is_contiguous() or x.shape[0] != self.n:
+            raise ValueError("x must be a contiguous float64 CUDA tensor with n rows")
+        y = torch.empty_like(x)
+        _check(lib().kf_apply_filter(self._h, x.data_ptr(), y.data_ptr(), int(x.shape[1])))
+        return y
+
+    def solve(self, start, m_max: int, tol: float) -> SolveResult:
+        V0 = np.ascontiguousarray(start, dtype=np.float64)
+        if V0.ndim == 1:
+            V0 = V0[:, None]
+        res = C.POINTER(ResultT)()
+        _check(lib().kf_solve(self._h, _ptr(V0), int(V0.shape[1]), int(m_max), float(tol), C.byref(res)))
+        try:
+            r = res.contents
+            na = r.n_pairs
+            vec = None
+            if r.vectors:
+                vec = np.ctypeslib.as_array(r.vectors, shape=(na, self.n)).T.copy()
+            out = SolveResult(
+                omega2=np.ctypeslib.as_array(r.omega2, shape=(na,)).copy() if na else np.zeros(0),
+                omega=np.ctypeslib.as_array(r.omega, shape=(na,)).copy() if na else np.zeros(0),
+                residual=np.ctypeslib.as_array(r.residual, shape=(na,)).copy() if na else np.zeros(0),
+                vectors=vec,
+                ritz=np.ctypeslib.as_array(r.ritz, shape=(r.n_ritz,)).copy() if r.n_ritz else np.zeros(0),
+                krylov_steps=r.krylov_steps,
+                basis_size=r.basis_size,
+                breakdown=bool(r.breakdown),
+                status=r.status,
+                leapfrog_vector_steps=r.leapfrog_vector_steps,
+                t_total=r.t_total,
+                t_leapfrog=r.t_leapfrog,
+                t_gs=r.t_gs,
+                t_rr=r.t_rr,
+                t_refine=r.t_refine,
+                orth_error=r.orth_error,
+            )
+        finally:
+            lib().kf_result_free(res)
+        return out
+
+    def basis(self, max_cols: int) -> np.ndarray:
+        out = np.empty((max_cols, self.n))
+        nc = C.c_int32()
+        _check(lib().kf_copy_basis(self._h, _ptr(out), int(max_cols), C.byref(nc)))
+        return out[: nc.value].T.copy()

@@ -1,0 +1,94 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/kf.h declares, and rejects invalid input before touching a device."""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from synth.grids import grid_problem
+
+
+def _kf():
+    from paper_2402_08515_amd import kf
+
+    return kf
+
+
+def _declared(repo_root):
+    txt = open(os.path.join(repo_root, "include", "kf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kf_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol(repo_root):
+    kf = _kf()
+    names = _declared(repo_root)
+    assert len(names) >= 13
+    lib = kf.lib()
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    out = subprocess.run(["nm", "-D", "--defined-only", kf.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (kf_[a-z_]+)", out))
+    assert set(names) <= exported
+
+
+def test_time_step_rule_matches_oracle():
+    kf = _kf()
+    for lam, om in [(32028.459056753818, 10.0), (1.1e5, 30.0), (4.0, 0.5)]:
+        assert kf.time_step_rule(lam, om) == pytest.approx(oracle.time_step_rule(lam, om))
+    with pytest.raises(kf.KfError):
+        kf.time_step_rule(-1.0, 10.0)
+    with pytest.raises(kf.KfError):
+        kf.time_step_rule(1.0, 0.0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    S, m, h = grid_problem(2, 8)
+    return S, m
+
+
+def _expect_einval(fn):
+    kf = _kf()
+    with pytest.raises(kf.KfError) as ei:
+        fn()
+    assert ei.value.code == kf.KF_EINVAL
+    return str(ei.value)
+
+
+def test_create_rejects_bad_pencils(small):
+    kf = _kf()
+    S, m = small
+    assert "m_diag" in _expect_einval(lambda: kf.Problem(S, -m, 1.0, 2.0, 0.01, 10))
+    m2 = m.copy()
+    m2[3] = np.inf
+    _expect_einval(lambda: kf.Problem(S, m2, 1.0, 2.0, 0.01, 10))
+    S2 = S.copy()
+    S2.indices[3], S2.indices[4] = S2.indices[4], S2.indices[3]
+    assert "increasing" in _expect_einval(lambda: kf.Problem(S2, m, 1.0, 2.0, 0.01, 10))
+    S3 = S.copy()
+    S3.data[5] = np.nan
+    assert "non-finite" in _expect_einval(lambda: kf.Problem(S3, m, 1.0, 2.0, 0.01, 10))
+    S4 = S.copy()
+    S4.indices[0] = S.shape[0]
+    assert "range" in _expect_einval(lambda: kf.Problem(S4, m, 1.0, 2.0, 0.01, 10))
+
+
+def test_create_rejects_bad_parameters(small):
+    kf = _kf()
+    S, m = small
+    _expect_einval(lambda: kf.Problem(S, m, 2.0, 1.0, 0.01, 10))
+    _expect_einval(lambda: kf.Problem(S, m, -1.0, 1.0, 0.01, 10))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.0, 10))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, float("nan"), 10))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 0))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, index_bytes=3))
+
+
+def test_last_error_is_a_string():
+    kf = _kf()
+    assert isinstance(kf.last_error(), str)
