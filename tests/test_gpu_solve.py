@@ -1,0 +1,151 @@
+"""GPU parity of the whole eigensolver (Algorithm 2.5 + eq. projevp + eq. res)
+against the CPU oracle and the closed-form spectrum.
+
+Bars (Section 2.4 acceptance at residual tol; eigenvalues compared in
+ascending order as omega^2):
+* float64 mode: relative eigenvalue difference <= 1e-10 against the oracle run
+  on the same inputs, and against the closed form;
+* the accepted sets must coincide (same count), residuals <= tol on both.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import distinct_target, grid_spectrum, power_start, start_block, workload
+from synth.grids import grid_problem, jittered_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _kf():
+    from paper_2402_08515_amd import kf
+
+    return kf
+
+
+def _params(S, m, omin, omax, seed):
+    lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], seed), 30)
+    tau, L = oracle.time_step_rule(lam, omin)
+    return tau, L, oracle.discrete_weights(omin, omax, tau, L)
+
+
+@pytest.fixture(scope="module")
+def grid2d():
+    P = workload("grid2d_64")
+    tau, L, w = _params(P.S, P.m, P.omega_min, P.omega_max, P.seed)
+    V0 = start_block(P.n, 1, P.seed)
+    ref = oracle.krylov_solve(P.S, P.m, tau, w, V0, P.omega_min, P.omega_max, tol=1e-9, m_max=40, keep_basis=True)
+    return P, tau, L, w, V0, ref
+
+
+def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d):
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    print("case grid2d_64 fp64 solve", flush=True)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    got = prob.solve(V0, m_max=40, tol=1e-9)
+    tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
+    assert got.basis_size == 40 and got.krylov_steps == 39
+    assert got.omega2.size == ref.omega2.size == tgt
+    assert np.max(np.abs(got.omega2 - ref.omega2) / ref.omega2) <= 1e-10
+    assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
+    assert got.residual.max() <= 1e-9
+    # unconverged Ritz values after many iterations follow rounding noise in
+    # the late basis vectors and are not compared (only accepted pairs are)
+    assert got.orth_error < 1e-12
+    assert got.leapfrog_vector_steps == 39 * (L - 1)
+
+
+def test_grid2d_basis_matches_oracle(grid2d):
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    got = prob.solve(V0, m_max=12, tol=1e-9)
+    Bg = prob.basis(12)
+    Bo = ref.basis[:, :12]
+    # columns agree up to rounding growth of the Krylov recursion
+    err = np.abs(Bg - Bo).max(axis=0) / np.abs(Bo).max(axis=0)
+    assert err[:6].max() <= 1e-9, err
+    G = Bg.T @ (P.m[:, None] * Bg)
+    assert np.abs(G - np.eye(12)).max() < 1e-12
+    # while the bases agree, every Ritz value of the projected pencil agrees
+    th = oracle.rayleigh_ritz(P.S, P.m, Bo, 0.0, 1e9)[0]
+    np.testing.assert_allclose(got.ritz, th, rtol=1e-9)
+
+
+def test_target_stops_early_and_vectors_are_eigenvectors(grid2d):
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, target=11, want_vectors=True)
+    got = prob.solve(V0, m_max=40, tol=1e-9)
+    assert got.omega2.size == 11 and got.status == 0 and got.basis_size <= 40
+    V = got.vectors
+    R = P.S @ V - (P.m[:, None] * V) * got.omega2[None, :]
+    res = np.linalg.norm(R, axis=0) / np.linalg.norm(P.S @ V, axis=0)
+    assert res.max() <= 1e-9 and got.residual.max() <= 1e-9
+    assert np.abs(V.T @ (P.m[:, None] * V) - np.eye(11)).max() < 1e-8
+
+
+@pytest.mark.parametrize("b", [2, 3])
+def test_block_start_recovers_multiplicities(b):
+    kf = _kf()
+    S, m, h = grid_problem(2, 24)
+    lam = grid_spectrum(2, 24)
+    tau, L = oracle.time_step_rule(lam.max(), 15.0)
+    w = oracle.discrete_weights(15.0, 24.0, tau, L)
+    tgt, vals, mult = distinct_target(lam, 15.0, 24.0, b)
+    V0 = start_block(S.shape[0], b, 9)
+    ref = oracle.krylov_solve(S, m, tau, w, V0, 15.0, 24.0, tol=1e-9, m_max=160, target=tgt)
+    prob = kf.Problem(S, m, 15.0, 24.0, tau, L, target=tgt)
+    got = prob.solve(V0, m_max=160, tol=1e-9)
+    expect = np.repeat(vals, np.minimum(mult, b))
+    assert got.omega2.size == tgt == ref.omega2.size
+    np.testing.assert_allclose(got.omega2, expect, rtol=1e-10)
+    np.testing.assert_allclose(got.omega2, ref.omega2, rtol=1e-10)
+
+
+def test_unstructured_neumann_matches_oracle():
+    kf = _kf()
+    S, m = jittered_problem(2, 14, 0.2, seed=11)
+    tau, L, w = _params(S, m, 8.0, 14.0, 1)
+    V0 = start_block(S.shape[0], 1, 4)
+    ref = oracle.krylov_solve(S, m, tau, w, V0, 8.0, 14.0, tol=1e-9, m_max=120)
+    got = kf.Problem(S, m, 8.0, 14.0, tau, L).solve(V0, m_max=120, tol=1e-9)
+    assert got.omega2.size == ref.omega2.size > 0
+    np.testing.assert_allclose(got.omega2, ref.omega2, rtol=1e-10)
+
+
+def test_breakdown_on_exact_eigenvector():
+    kf = _kf()
+    n = 20
+    S, m, h = grid_problem(2, n)
+    x = np.arange(1, n) * h
+    v = np.outer(np.sin(2 * np.pi * x), np.sin(3 * np.pi * x)).ravel()
+    tau, L = oracle.time_step_rule(grid_spectrum(2, n).max(), 5.0)
+    got = kf.Problem(S, m, 5.0, 15.0, tau, L).solve(v[:, None], m_max=10, tol=1e-9)
+    mu = 4 * n * n * np.sin(np.arange(1, n) * np.pi / (2 * n)) ** 2
+    assert got.breakdown and got.basis_size == 1 and got.krylov_steps == 1
+    assert got.omega2.size == 1 and got.omega2[0] == pytest.approx(mu[1] + mu[2], rel=1e-12)
+
+
+def test_unstable_time_step_is_reported():
+    kf = _kf()
+    S, m, h = grid_problem(2, 16)
+    lam = grid_spectrum(2, 16).max()
+    tau = 2.6 / math.sqrt(lam)  # violates tau < 2/omega_max
+    prob = kf.Problem(S, m, 5.0, 10.0, tau, 60)
+    with pytest.raises(kf.KfError) as ei:
+        prob.solve(start_block(S.shape[0], 1, 0), m_max=10, tol=1e-9)
+    assert ei.value.code == kf.KF_EUNSTABLE
+
+
+def test_repeat_runs_are_bitwise_identical(grid2d):
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    a = prob.solve(V0, m_max=30, tol=1e-9)
+    b = prob.solve(V0, m_max=30, tol=1e-9)
+    assert np.array_equal(a.ritz, b.ritz) and np.array_equal(a.omega2, b.omega2)
