@@ -91,7 +91,8 @@ def main():
     ap.add_argument("--workload", default="grid3d_96")
     ap.add_argument("--m-max", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--check-growth", type=float, default=0.15)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -115,7 +116,7 @@ def main():
     tau, L = kf.time_step_rule(lam, P.omega_min)
     print(f"[bench] lambda_est={lam:.6g} tau={tau:.6g} L={L}", file=sys.stderr, flush=True)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
-                      check_every=args.check_every)
+                      check_every=args.check_every, check_growth=args.check_growth)
     V0 = start_block(P.n, P.block, P.seed)
 
     results = []

@@ -75,6 +75,15 @@ typedef struct kf_options {
   int32_t precision;     /* kf_precision */
   int32_t check_every;   /* Rayleigh-Ritz every this many Krylov iterations
                             (>= 1); the final state is always checked */
+  double check_growth;   /* additionally wait until the basis has grown by
+                            this fraction since the last check (0: no wait);
+                            checks cost O(k^3) in the basis size k */
+  int32_t full_reorth;   /* 1: classical Gram-Schmidt twice against the whole
+                            basis; 0: twice against the last two blocks (C is
+                            M-self-adjoint, so the filtered block is
+                            orthogonal to the older ones in exact arithmetic)
+                            then once against the whole basis, a second time
+                            only when that pass removed over half the norm */
   int32_t target;        /* stop once this many pairs are accepted (0: never) */
   int32_t max_iters;     /* cap on filter applications (0: none) */
   double drop_tol;       /* a new column whose M-norm after orthogonalisation
@@ -115,9 +124,11 @@ typedef struct kf_result {
                              residuals */
   double t_refine;        /* seconds in the mixed-mode refinement */
   double orth_error;      /* max |B^T M B - I| over the columns checked */
+  int32_t full_passes;    /* Gram-Schmidt passes over the whole basis */
 } kf_result;
 
-/* Fill *opt with defaults: KF_FP64, check_every 1, no target, no cap,
+/* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
+ * orthogonalisation (full_reorth 0), no target, no cap,
  * drop_tol 1e-10, refine 1, no vectors, automatic index width, XCD remap on,
  * default stream. */
 void kf_default_options(kf_options* opt);

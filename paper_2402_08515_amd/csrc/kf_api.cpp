@@ -58,7 +58,7 @@ struct kf_problem {
   double* H = nullptr;
   double* G = nullptr;
   int hcap = 0;
-  double* T = nullptr;  // (bcap x 32) coefficients
+  double* T = nullptr;  // (bcap x 64) coefficients
   double* W = nullptr;  // n x 16 scratch (S Q)
   double* V = nullptr;  // n x 64 Ritz vectors
   double* SV = nullptr; // n x 64
@@ -250,7 +250,7 @@ int ensure_basis(kf_problem* p, int cols) {
   KF_TRY(dalloc(&p->B, (size_t)p->ldb * cols));
   KF_TRY(dalloc(&p->H, (size_t)cols * cols));
   KF_TRY(dalloc(&p->G, (size_t)cols * cols));
-  KF_TRY(dalloc(&p->T, (size_t)cols * 32));
+  KF_TRY(dalloc(&p->T, (size_t)cols * 64));
   p->bcap = cols;
   p->hcap = cols;
   return KF_OK;
@@ -271,8 +271,20 @@ int ensure_misc(kf_problem* p) {
 // columns that lose more than drop_tol of their M-norm, compact the kept
 // columns to [c0, c0+kept).  ref_out receives the pre-orthogonalisation
 // M-norms.  Synchronises the stream.
+// pn > 0: the projected-pencil columns of basis columns [kb - pn, kb) are
+// still pending; they are computed in the same pass over B as the first
+// Gram-Schmidt coefficients (one pass fewer per Krylov iteration).
+//
+// loc0 >= 0 selects the three-term form: C is M-self-adjoint (Lemma 2.3,
+// C = beta~(M^{-1}S)), so the filtered block is M-orthogonal, in exact
+// arithmetic, to every basis block except the last two, [loc0, kb).  The
+// block is first orthogonalised (twice) against that window only, then once
+// against the whole basis; a second full pass runs only when the full pass
+// removed more than half of the M-norm of a column (the test of Daniel,
+// Gragg, Kaufman and Stewart).  loc0 < 0 runs classical Gram-Schmidt twice
+// against the whole basis.
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
-               hipEvent_t done = nullptr) {
+               hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr) {
   hipStream_t st = p->st;
   const int32_t n = p->n;
   const int64_t ldb = p->ldb;
@@ -282,11 +294,52 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   double* nrm2 = p->small + 512;     // nb squared norms
   double* coef = p->T;               // kb x nb or j x 1
   KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, Tref, nb, p->gw, st));
-  if (kb > 0) {
-    for (int pass = 0; pass < 2; ++pass) {
+  // pass over the whole basis; the first one also forms the pending
+  // projected-pencil columns [B^T S Q | B^T M Q] with Q = B[:, kb-pn:kb]
+  // adjacent to the block
+  auto full_pass = [&](bool with_pending) -> int {
+    if (with_pending && pn > 0) {
+      const int p0 = kb - pn;
+      const double* Q = p->B + (int64_t)p0 * ldb;
+      KF_TRY(spmv_cols(p->S, Q, ldb, p->W, n, pn, nullptr, st));
+      KF_TRY(gemv_t(n, kb, p->B, ldb, p->W, pn, n, Q, pn + nb, ldb, p->d_m, coef, kb, p->gw, st));
+      KF_TRY(rr_scatter(kb, p0, pn, coef, kb, p->H, p->G, p->hcap, st));
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef + (int64_t)2 * pn * kb, kb, X, ldb, nb, st));
+    } else {
       KF_TRY(gemv_t(n, kb, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, kb, p->gw, st));
       KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef, kb, X, ldb, nb, st));
     }
+    if (full_passes) ++*full_passes;
+    return KF_OK;
+  };
+  if (kb > 0 && loc0 < 0) {
+    KF_TRY(full_pass(true));
+    KF_TRY(full_pass(false));
+  } else if (kb > 0) {
+    const int lw = kb - loc0;
+    const double* Bl = p->B + (int64_t)loc0 * ldb;
+    for (int pass = 0; pass < 2; ++pass) {
+      KF_TRY(gemv_t(n, lw, Bl, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, lw, p->gw, st));
+      KF_TRY(gemv_n_sub(n, lw, Bl, ldb, coef, lw, X, ldb, nb, st));
+    }
+    double* g1 = p->small + 768;       // column M-norms^2 before the full pass
+    double* g2 = p->small + 768 + 16;  // and after it
+    for (int j = 0; j < nb; ++j) {
+      double* xj = X + (int64_t)j * ldb;
+      KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, g1 + j, 1, p->gw, st));
+    }
+    KF_TRY(full_pass(true));
+    for (int j = 0; j < nb; ++j) {
+      double* xj = X + (int64_t)j * ldb;
+      KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, g2 + j, 1, p->gw, st));
+    }
+    double hg[32];
+    KF_HIP(hipMemcpyAsync(hg, g1, sizeof(double) * 32, hipMemcpyDeviceToHost, st));
+    KF_HIP(hipStreamSynchronize(st));
+    bool again = false;
+    for (int j = 0; j < nb; ++j)
+      if (hg[16 + j] < 0.25 * hg[j]) again = true;  // norm fell below half
+    if (again) KF_TRY(full_pass(false));
   }
   const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
   for (int j = 0; j < nb; ++j) {
@@ -426,6 +479,8 @@ void kf_default_options(kf_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = KF_FP64;
   o->check_every = 1;
+  o->check_growth = 0.0;
+  o->full_reorth = 0;
   o->target = 0;
   o->max_iters = 0;
   o->drop_tol = 1e-10;
@@ -467,6 +522,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.index_bytes != 0 && o.index_bytes != 2 && o.index_bytes != 4)
     return fail(KF_EINVAL, "kf_create: index_bytes must be 0, 2 or 4");
   if (o.check_every < 1) o.check_every = 1;
+  if (!(o.check_growth >= 0.0) || !std::isfinite(o.check_growth)) o.check_growth = 0.0;
   if (!(o.drop_tol > 0)) o.drop_tol = 1e-10;
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
@@ -679,20 +735,31 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   KF_TRY(orth_block(p, 0, 0, b, &kept, ref, ev[2]));
   KF_TRY(elapsed(ev[1], ev[2], t_gs));
   if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
-  KF_HIP(hipEventRecord(ev[3], st));
-  KF_TRY(rr_update(p, 0, kept));
-  KF_HIP(hipEventRecord(ev[4], st));
-  bool rr_pending = true;  // ev[3] -> ev[4] not yet accumulated
   int cur = kept, q0 = 0, qn = kept;
+  int prev0 = 0;       // first column of the block before the last one
+  int full_passes = 0;
+  int pending = kept;  // basis columns whose projected-pencil columns are not yet formed
+  bool rr_pending = false;  // ev[3] -> ev[4] not yet accumulated
   int iters = 0;
   int64_t lf_steps = 0;
   bool breakdown = false;
   const int target = p->opt.target;
   CheckOut chk;
   int checked_at = -1;
+  int next_check = 0;
   double wsum = 0.0;
   for (double v : p->w) wsum += std::fabs(v);
   int status = KF_OK;
+  auto check_now = [&]() -> int {
+    if (!rr_pending) KF_HIP(hipEventRecord(ev[3], st));
+    if (pending > 0) KF_TRY(rr_update(p, cur - pending, pending));
+    pending = 0;
+    KF_TRY(rr_check(p, cur, tol, chk));
+    KF_HIP(hipEventRecord(ev[4], st));
+    rr_pending = true;
+    checked_at = cur;
+    return KF_OK;
+  };
   while (true) {
     if (p->opt.max_iters > 0 && iters >= p->opt.max_iters) break;
     if (cur >= m_max) break;
@@ -702,7 +769,9 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
     KF_HIP(hipEventRecord(ev[1], st));
     ++iters;
     lf_steps += (int64_t)qn * (p->L - 1);
-    KF_TRY(orth_block(p, cur, cur, bk, &kept, ref, ev[2]));  // synchronises the stream
+    KF_TRY(orth_block(p, cur, cur, bk, &kept, ref, ev[2], pending, p->opt.full_reorth ? -1 : prev0,
+                      &full_passes));  // synchronises the stream
+    pending = 0;
     if (rr_pending) {
       KF_TRY(elapsed(ev[3], ev[4], t_rr));
       rr_pending = false;
@@ -720,25 +789,18 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
       breakdown = true;
       break;
     }
-    KF_HIP(hipEventRecord(ev[3], st));
-    KF_TRY(rr_update(p, cur, kept));
+    prev0 = q0;
     q0 = cur;
     qn = kept;
     cur += kept;
-    if (iters % p->opt.check_every == 0) {
-      KF_TRY(rr_check(p, cur, tol, chk));
-      checked_at = cur;
+    pending = kept;
+    if (iters % p->opt.check_every == 0 && cur >= next_check) {
+      KF_TRY(check_now());
+      next_check = (int)std::ceil(cur * (1.0 + p->opt.check_growth));
+      if (target > 0 && (int)chk.acc_theta.size() >= target) break;
     }
-    KF_HIP(hipEventRecord(ev[4], st));
-    rr_pending = true;
-    if (checked_at == cur && target > 0 && (int)chk.acc_theta.size() >= target) break;
   }
-  if (checked_at != cur) {
-    if (!rr_pending) KF_HIP(hipEventRecord(ev[3], st));
-    KF_TRY(rr_check(p, cur, tol, chk));
-    KF_HIP(hipEventRecord(ev[4], st));
-    rr_pending = true;
-  }
+  if (checked_at != cur) KF_TRY(check_now());
   KF_HIP(hipEventSynchronize(ev[4]));
   if (rr_pending) KF_TRY(elapsed(ev[3], ev[4], t_rr));
   p->basis_cols = cur;
@@ -802,6 +864,7 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   r->t_rr = t_rr;
   r->t_refine = 0.0;
   r->orth_error = chk.orth;
+  r->full_passes = full_passes;
   KF_HIP(hipStreamSynchronize(st));
   r->t_total = now_s() - t0;
   *out = r;

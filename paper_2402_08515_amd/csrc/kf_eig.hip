@@ -55,23 +55,42 @@ __global__ __launch_bounds__(256) void k_copy_square(int k, const double* __rest
   A[t] = H[i + j * ldh];
 }
 
+// Householder reduction to tridiagonal form, one workgroup, full symmetric
+// storage in global memory (L2 resident), one row per thread.  Step k uses
+// the reflector v_k (v_k[k+1] = 1) with scalar tau_k and w_k = p - (tau/2)(p.v)v,
+// p = tau A22 v.  The rank-2 update of step k and the product p of step k+1
+// share one pass over the trailing matrix: column k+1 is updated first, v_{k+1}
+// is formed from it, then every remaining entry is updated and immediately
+// multiplied into p_{k+1}.  Reflector k is stored below the subdiagonal of
+// column k.
 __global__ __launch_bounds__(1024) void k_tridiag(int m, double* __restrict__ A, double* __restrict__ d,
                                                   double* __restrict__ e, double* __restrict__ tau) {
   extern __shared__ double sh[];
-  double* v = sh;
-  double* w = sh + m;
-  double* red = sh + 2 * m;
+  double* vb[2] = {sh, sh + m};
+  double* wb[2] = {sh + 2 * m, sh + 3 * m};
+  double* red = sh + 4 * m;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = 0; k + 2 < m; ++k) {
-    const int n2 = m - k - 1;
-    const double* col = A + (int64_t)k * m + k + 1;
-    double s = 0.0;
-    for (int i = 1 + tid; i < n2; i += nt) {
-      const double xi = col[i];
-      s = fma(xi, xi, s);
+  if (m == 1) {
+    if (tid == 0) d[0] = A[0];
+    return;
+  }
+  if (m == 2) {
+    if (tid == 0) {
+      d[0] = A[0];
+      d[1] = A[3];
+      e[0] = A[1];
+      tau[0] = 0.0;
     }
+    return;
+  }
+  // reflector from column k (entries k+1..m-1) into v (absolute indexing);
+  // returns tau (0 when the column is already reduced) and sets e[k]
+  auto make_reflector = [&](int k, double* v) -> double {
+    const double* col = A + (int64_t)k * m;
+    double s = 0.0;
+    for (int i = k + 2 + tid; i < m; i += nt) s = fma(col[i], col[i], s);
     s = block_sum(s, red);
-    const double alpha = col[0];
+    const double alpha = col[k + 1];
     double beta = alpha, tk = 0.0, v0 = 1.0;
     if (s > 0.0) {
       const double mu = sqrt(alpha * alpha + s);
@@ -79,161 +98,272 @@ __global__ __launch_bounds__(1024) void k_tridiag(int m, double* __restrict__ A,
       v0 = alpha - beta;
       tk = (beta - alpha) / beta;
     }
-    for (int i = tid; i < n2; i += nt) v[i] = (i == 0) ? 1.0 : (tk == 0.0 ? 0.0 : col[i] / v0);
-    __syncthreads();
+    for (int i = tid; i < m; i += nt) v[i] = (i <= k) ? 0.0 : (i == k + 1 ? 1.0 : (tk == 0.0 ? 0.0 : col[i] / v0));
     if (tid == 0) {
       e[k] = beta;
       tau[k] = tk;
-      d[k] = A[k + (int64_t)k * m];
     }
-    for (int i = 1 + tid; i < n2; i += nt) A[(int64_t)k * m + k + 1 + i] = v[i];
-    if (tk == 0.0) continue;  // uniform: tk comes from a block-wide sum
-    // p = tk * A22 v
-    const double* a22 = A + (int64_t)(k + 1) * m + (k + 1);
-    for (int i = tid; i < n2; i += nt) {
+    __syncthreads();
+    return tk;
+  };
+  // w = p - (tau/2)(p.v) v with p already in w (scaled by tau)
+  auto finish_w = [&](int k, double tk, double* v, double* w) {
+    double pv = 0.0;
+    for (int i = k + 1 + tid; i < m; i += nt) pv = fma(w[i], v[i], pv);
+    pv = block_sum(pv, red);
+    const double K = 0.5 * tk * pv;
+    for (int i = tid; i < m; i += nt) w[i] = (i <= k) ? 0.0 : w[i] - K * v[i];
+    __syncthreads();
+  };
+
+  // step 0: reflector and the plain product p = tau A22 v
+  if (tid == 0) d[0] = A[0];
+  double tk = make_reflector(0, vb[0]);
+  {
+    double* v = vb[0];
+    double* w = wb[0];
+    for (int i = 1 + tid; i < m; i += nt) {
       double acc = 0.0;
-      const double* ai = a22 + i;
-      for (int j = 0; j < n2; ++j) acc = fma(ai[(int64_t)j * m], v[j], acc);
+#pragma unroll 8
+      for (int j = 1; j < m; ++j) acc = fma(A[i + (int64_t)j * m], v[j], acc);
       w[i] = tk * acc;
     }
     __syncthreads();
-    double pv = 0.0;
-    for (int i = tid; i < n2; i += nt) pv = fma(w[i], v[i], pv);
-    pv = block_sum(pv, red);
-    const double K = 0.5 * tk * pv;
-    for (int i = tid; i < n2; i += nt) w[i] -= K * v[i];
-    __syncthreads();
-    double* b22 = A + (int64_t)(k + 1) * m + (k + 1);
-    const int64_t tot = (int64_t)n2 * n2;
-    for (int64_t t = tid; t < tot; t += nt) {
-      const int j = (int)(t / n2), i = (int)(t - (int64_t)j * n2);
-      b22[i + (int64_t)j * m] -= v[i] * w[j] + w[i] * v[j];
-    }
-    __syncthreads();
+    finish_w(0, tk, v, w);
   }
-  if (tid == 0) {
-    if (m >= 2) {
-      d[m - 2] = A[(m - 2) + (int64_t)(m - 2) * m];
-      e[m - 2] = A[(m - 1) + (int64_t)(m - 2) * m];
-      tau[m - 2] = 0.0;
+  int cur = 0;
+  for (int k = 0; k + 2 < m; ++k) {
+    double* v = vb[cur];
+    double* w = wb[cur];
+    // store reflector k below the subdiagonal of column k
+    for (int i = k + 2 + tid; i < m; i += nt) A[i + (int64_t)k * m] = v[i];
+    // rank-2 update of column k+1 (rows k+1..m-1)
+    const int c = k + 1;
+    for (int i = c + tid; i < m; i += nt) A[i + (int64_t)c * m] -= v[i] * w[c] + w[i] * v[c];
+    __syncthreads();
+    if (tid == 0) d[c] = A[c + (int64_t)c * m];
+    if (c + 2 > m - 1) {
+      // last 2 x 2 block: update the remaining entry and finish
+      if (tid == 0) {
+        const int j = c + 1;
+        const double a = A[j + (int64_t)j * m] - 2.0 * v[j] * w[j];
+        A[j + (int64_t)j * m] = a;
+        d[j] = a;
+        e[c] = A[j + (int64_t)c * m];
+        tau[c] = 0.0;
+      }
+      break;
     }
-    d[m - 1] = A[(m - 1) + (int64_t)(m - 1) * m];
+    double* vn = vb[cur ^ 1];
+    double* wn = wb[cur ^ 1];
+    const double tn = make_reflector(c, vn);
+    // fused pass: update rows/cols >= c+1 with step k, accumulate p_{k+1}
+    for (int i = c + 1 + tid; i < m; i += nt) {
+      const double vi = v[i], wi = w[i];
+      double acc = 0.0;
+      double* __restrict__ ai = A + i;
+      int j = c + 1;
+      // eight independent loads in flight before the dependent updates
+      for (; j + 8 <= m; j += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = ai[(int64_t)(j + u) * m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = a[u] - vi * w[j + u] - wi * v[j + u];
+          ai[(int64_t)(j + u) * m] = a[u];
+          acc = fma(a[u], vn[j + u], acc);
+        }
+      }
+      for (; j < m; ++j) {
+        const double a = ai[(int64_t)j * m] - vi * w[j] - wi * v[j];
+        ai[(int64_t)j * m] = a;
+        acc = fma(a, vn[j], acc);
+      }
+      wn[i] = tn * acc;
+    }
+    __syncthreads();
+    finish_w(c, tn, vn, wn);
+    cur ^= 1;
   }
 }
 
-__device__ int sturm_count(int m, const double* __restrict__ d, const double* __restrict__ e, double x,
+__device__ int sturm_count(int m, const double* __restrict__ d, const double* __restrict__ e2, double x,
                            double pivmin) {
   int c = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++c;
   for (int j = 1; j < m; ++j) {
-    q = (d[j] - x) - e[j - 1] * e[j - 1] / q;
+    q = (d[j] - x) - e2[j - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++c;
   }
   return c;
 }
 
-__global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict__ d, const double* __restrict__ e,
-                                                double* __restrict__ theta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+__global__ __launch_bounds__(256) void k_tri_prep(int m, const double* __restrict__ d, const double* __restrict__ e,
+                                                  double* __restrict__ e2, double* __restrict__ bounds) {
+  // e2 = e^2; bounds = {gershgorin lo, hi, pivmin}
+  __shared__ double red[3][4];
   double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
-  for (int j = 0; j < m; ++j) {
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
     const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < m - 1 ? fabs(e[j]) : 0.0);
     lo = fmin(lo, d[j] - r);
     hi = fmax(hi, d[j] + r);
-    if (j < m - 1) emax2 = fmax(emax2, e[j] * e[j]);
+    if (j < m - 1) {
+      e2[j] = e[j] * e[j];
+      emax2 = fmax(emax2, e2[j]);
+    }
   }
-  const double pivmin = DBL_MIN * fmax(1.0, emax2);
-  const double tn = fmax(fabs(lo), fabs(hi));
-  lo -= 2.0 * DBL_EPSILON * tn + pivmin;
-  hi += 2.0 * DBL_EPSILON * tn + pivmin;
-  for (int it = 0; it < 256; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (!(mid > lo && mid < hi)) break;
-    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    if (sturm_count(m, d, e, mid, pivmin) > i)
-      hi = mid;
-    else
-      lo = mid;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    emax2 = fmax(emax2, __shfl_xor(emax2, off));
   }
-  theta[i] = 0.5 * (lo + hi);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = lo;
+    red[1][threadIdx.x >> 6] = hi;
+    red[2][threadIdx.x >> 6] = emax2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = fmin(red[0][0], red[0][w]);
+      red[0][0] = lo;
+      hi = fmax(red[1][0], red[1][w]);
+      red[1][0] = hi;
+      emax2 = fmax(red[2][0], red[2][w]);
+      red[2][0] = emax2;
+    }
+    lo = red[0][0];
+    hi = red[1][0];
+    const double pivmin = DBL_MIN * fmax(1.0, red[2][0]);
+    const double tn = fmax(fabs(lo), fabs(hi));
+    bounds[0] = lo - 2.0 * DBL_EPSILON * tn - pivmin;
+    bounds[1] = hi + 2.0 * DBL_EPSILON * tn + pivmin;
+    bounds[2] = pivmin;
+  }
 }
 
-// Inverse iteration, one lane per cluster of selected eigenvalues.
+// Eigenvalue i by 65-section: the 64 lanes of a wavefront evaluate Sturm
+// counts at 64 interior points of the bracket, which shrinks 65-fold per
+// round until it is a few ulps wide.
+__global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict__ d, const double* __restrict__ e2,
+                                                const double* __restrict__ bounds, double* __restrict__ theta) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  double lo = bounds[0], hi = bounds[1];
+  const double pivmin = bounds[2];
+  for (int it = 0; it < 64; ++it) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    const double h = (hi - lo) / 65.0;
+    const double x = lo + (lane + 1) * h;
+    const bool above = sturm_count(m, d, e2, x, pivmin) > i;
+    const unsigned long long mask = __ballot(above);
+    double nlo, nhi;
+    if (mask == 0ull) {
+      nlo = __shfl(x, 63);
+      nhi = hi;
+    } else {
+      const int f = __ffsll((long long)mask) - 1;
+      nhi = __shfl(x, f);
+      nlo = f > 0 ? __shfl(x, f - 1) : lo;
+    }
+    if (!(nhi - nlo < hi - lo)) break;  // no progress: bracket is at rounding level
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) theta[i] = 0.5 * (lo + hi);
+}
+
+// Inverse iteration, one lane per cluster of selected eigenvalues; the
+// recurrences carry their running values in registers so that only
+// independent loads and stores touch memory.
 __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ d, const double* __restrict__ e,
-                                              int ncl, const int32_t* __restrict__ cstart,
-                                              const double* __restrict__ sel, double* __restrict__ Z,
-                                              double* __restrict__ scratch) {
+                                              const double* __restrict__ bounds, int ncl,
+                                              const int32_t* __restrict__ cstart, const double* __restrict__ sel,
+                                              double* __restrict__ Z, double* __restrict__ scratch) {
   const int cl = blockIdx.x * blockDim.x + threadIdx.x;
   if (cl >= ncl) return;
-  double tn = 0.0;
-  for (int j = 0; j < m; ++j)
-    tn = fmax(tn, fabs(d[j]) + (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < m - 1 ? fabs(e[j]) : 0.0));
+  const double tn = fmax(fabs(bounds[0]), fabs(bounds[1]));
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
   double prev_lam = -INFINITY;
   for (int s = cstart[cl]; s < cstart[cl + 1]; ++s) {
     double lam = sel[s];
     if (s > cstart[cl] && lam - prev_lam < 10.0 * tiny) lam = prev_lam + 10.0 * tiny;
     prev_lam = lam;
-    double* u0 = scratch + (int64_t)s * 5 * m;
-    double* u1 = u0 + m;
-    double* u2 = u1 + m;
-    double* lm = u2 + m;
-    double* pv = lm + m;  // 1.0 where rows i, i+1 were swapped
-    double* z = Z + (int64_t)s * m;
-    // LU of T - lam I with partial pivoting
-    u0[0] = d[0] - lam;
-    u1[0] = m > 1 ? e[0] : 0.0;
+    double* __restrict__ rinv = scratch + (int64_t)s * 5 * m;
+    double* __restrict__ u1 = rinv + m;
+    double* __restrict__ u2 = u1 + m;
+    double* __restrict__ lm = u2 + m;
+    double* __restrict__ pv = lm + m;
+    double* __restrict__ z = Z + (int64_t)s * m;
+    // LU of T - lam I with partial pivoting; row i is (a, b, c) at columns
+    // (i, i+1, i+2) while it is being eliminated
+    double a = d[0] - lam;
+    double b = m > 1 ? e[0] : 0.0;
     for (int i = 0; i + 1 < m; ++i) {
       const double bi = e[i];
       const double ai1 = d[i + 1] - lam;
       const double ci1 = (i + 2 < m) ? e[i + 1] : 0.0;
-      if (fabs(u0[i]) >= fabs(bi)) {
-        const double l = (u0[i] != 0.0) ? bi / u0[i] : 0.0;
+      double na, nb;
+      if (fabs(a) >= fabs(bi)) {
+        const double l = (a != 0.0) ? bi / a : 0.0;
         pv[i] = 0.0;
         lm[i] = l;
         u2[i] = 0.0;
-        u0[i + 1] = ai1 - l * u1[i];
-        u1[i + 1] = ci1;
+        u1[i] = b;
+        if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+        rinv[i] = 1.0 / a;
+        na = ai1 - l * b;
+        nb = ci1;
       } else {
-        const double l = u0[i] / bi;
-        const double t = u1[i];
+        const double l = a / bi;
         pv[i] = 1.0;
         lm[i] = l;
-        u0[i] = bi;
         u1[i] = ai1;
         u2[i] = ci1;
-        u0[i + 1] = t - l * ai1;
-        u1[i + 1] = -l * ci1;
+        rinv[i] = 1.0 / bi;
+        na = b - l * ai1;
+        nb = -l * ci1;
       }
+      a = na;
+      b = nb;
     }
+    if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+    rinv[m - 1] = 1.0 / a;
+    u1[m - 1] = 0.0;
     u2[m - 1] = 0.0;
-    for (int i = 0; i < m; ++i)
-      if (fabs(u0[i]) < tiny) u0[i] = u0[i] < 0.0 ? -tiny : tiny;
-    // start vector: fixed, generic (no structure that could hide a component)
+    if (m >= 2) u2[m - 2] = 0.0;
     for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * (s - cstart[cl]) + 0.1);
     for (int it = 0; it < 3; ++it) {
+      // forward: row swaps and elimination, running value in a register
+      double y = z[0];
       for (int i = 0; i + 1 < m; ++i) {
+        double nx = z[i + 1];
         if (pv[i] != 0.0) {
-          const double t = z[i];
-          z[i] = z[i + 1];
-          z[i + 1] = t;
+          const double t = y;
+          y = nx;
+          nx = t;
         }
-        z[i + 1] -= lm[i] * z[i];
+        z[i] = y;
+        y = nx - lm[i] * y;
       }
-      z[m - 1] = z[m - 1] / u0[m - 1];
-      if (m >= 2) z[m - 2] = (z[m - 2] - u1[m - 2] * z[m - 1]) / u0[m - 2];
-      for (int i = m - 3; i >= 0; --i) z[i] = (z[i] - u1[i] * z[i + 1] - u2[i] * z[i + 2]) / u0[i];
-      // keep clear of overflow before re-orthogonalising
-      double mx = 0.0;
-      for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(z[i]));
-      if (mx > 0.0) {
-        const double r = 1.0 / mx;
-        for (int i = 0; i < m; ++i) z[i] *= r;
+      z[m - 1] = y;
+      // backward substitution with U (diagonal inverse, two superdiagonals)
+      double x1 = 0.0, x2 = 0.0, mx = 0.0;
+      for (int i = m - 1; i >= 0; --i) {
+        const double x = (z[i] - u1[i] * x1 - u2[i] * x2) * rinv[i];
+        z[i] = x;
+        mx = fmax(mx, fabs(x));
+        x2 = x1;
+        x1 = x;
       }
+      const double r = mx > 0.0 ? 1.0 / mx : 0.0;
+      for (int i = 0; i < m; ++i) z[i] *= r;
       for (int q = cstart[cl]; q < s; ++q) {
         const double* zq = Z + (int64_t)q * m;
         double dot = 0.0;
@@ -242,9 +372,8 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
       }
       double nrm = 0.0;
       for (int i = 0; i < m; ++i) nrm = fma(z[i], z[i], nrm);
-      nrm = sqrt(nrm);
-      const double r = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = 0; i < m; ++i) z[i] *= r;
+      const double rn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = 0; i < m; ++i) z[i] *= rn;
     }
   }
 }
@@ -290,7 +419,7 @@ __global__ __launch_bounds__(256) void k_backtransform(int m, const double* __re
 }  // namespace
 
 void free_eig(EigWork& w) {
-  double* ptrs[] = {w.A, w.d, w.e, w.tau, w.theta, w.Z, w.Y, w.scratch, w.sel};
+  double* ptrs[] = {w.A, w.d, w.e, w.e2, w.bounds, w.tau, w.theta, w.Z, w.Y, w.scratch, w.sel};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.cl) (void)hipFree(w.cl);
@@ -299,14 +428,15 @@ void free_eig(EigWork& w) {
 
 int eig_reserve(EigWork& w, int m, int nsel) {
   if ((size_t)m > w.cap_m) {
-    double** ps[] = {&w.A, &w.d, &w.e, &w.tau, &w.theta};
+    double** ps[] = {&w.A, &w.d, &w.e, &w.e2, &w.bounds, &w.tau, &w.theta};
     for (double** p : ps) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
     }
     const size_t mm = (size_t)m;
     if (hipMalloc(&w.A, sizeof(double) * mm * mm) != hipSuccess || hipMalloc(&w.d, sizeof(double) * mm) != hipSuccess ||
-        hipMalloc(&w.e, sizeof(double) * mm) != hipSuccess || hipMalloc(&w.tau, sizeof(double) * mm) != hipSuccess ||
+        hipMalloc(&w.e, sizeof(double) * mm) != hipSuccess || hipMalloc(&w.e2, sizeof(double) * mm) != hipSuccess ||
+        hipMalloc(&w.bounds, sizeof(double) * 4) != hipSuccess || hipMalloc(&w.tau, sizeof(double) * mm) != hipSuccess ||
         hipMalloc(&w.theta, sizeof(double) * mm) != hipSuccess) {
       set_error("eig_reserve: allocation failed");
       return KF_ENOMEM;
@@ -345,10 +475,12 @@ int eig_values(EigWork& w, int k, const double* H, int64_t ldh, hipStream_t st) 
   KF_TRY(eig_reserve(w, k, 1));
   hipLaunchKernelGGL(k_copy_square, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, st, k, H, ldh, w.A);
   KF_HIP(hipGetLastError());
-  const size_t lds = sizeof(double) * (2 * (size_t)k + 32);
+  const size_t lds = sizeof(double) * (4 * (size_t)k + 32);
   hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lds, st, k, w.A, w.d, w.e, w.tau);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_bisect, dim3(cdiv(k, 256)), dim3(256), 0, st, k, w.d, w.e, w.theta);
+  hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(256), 0, st, k, w.d, w.e, w.e2, w.bounds);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bisect, dim3(cdiv(k, 4)), dim3(256), 0, st, k, w.d, w.e2, w.bounds, w.theta);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
@@ -359,8 +491,8 @@ int eig_vectors(EigWork& w, int k, const double* theta_sel, const int32_t* clust
   KF_TRY(eig_reserve(w, k, nsel));
   KF_HIP(hipMemcpyAsync(w.sel, theta_sel, sizeof(double) * nsel, hipMemcpyHostToDevice, st));
   KF_HIP(hipMemcpyAsync(w.cl, cluster_start, sizeof(int32_t) * (nclusters + 1), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_invit, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, nclusters, w.cl, w.sel, w.Z,
-                     w.scratch);
+  hipLaunchKernelGGL(k_invit, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters, w.cl,
+                     w.sel, w.Z, w.scratch);
   KF_HIP(hipGetLastError());
   const int grid = cdiv(nsel, 4);
   const int mt = cdiv(k, 64);

@@ -126,6 +126,8 @@ struct EigWork {
   double* A = nullptr;  // m x m
   double* d = nullptr;
   double* e = nullptr;
+  double* e2 = nullptr;      // squared off-diagonal
+  double* bounds = nullptr;  // Gershgorin bracket and pivot floor
   double* tau = nullptr;
   double* theta = nullptr;
   double* Z = nullptr;     // m x nsel (tridiagonal eigenvectors)

@@ -229,23 +229,32 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
     for (int c = 0; c < NR; ++c)
       if (c < nrhs) s[c] = wave_sum(s[c]);
     if (lane == 0) {
-      double* p = partial + ((int64_t)chunk * k + j) * nrhs;
+      // layout [output (j, c)][chunk]: the second pass reads each output's
+      // partials contiguously
+      const int nchunks = gridDim.x;
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        if (c < nrhs) p[c] = s[c];
+        if (c < nrhs) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = s[c];
     }
   }
 }
 
+// Second pass: one wavefront per output, lanes stride over the chunks in a
+// fixed order, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
                                                         const double* __restrict__ partial, double* __restrict__ H,
                                                         int64_t ldh) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= k * nrhs) return;
-  const int j = t / nrhs, c = t - j * nrhs;
+  const double* p = partial + (int64_t)t * nchunks;
   double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) s += partial[(int64_t)ch * k * nrhs + t];
-  H[j + (int64_t)c * ldh] = s;
+  for (int ch = lane; ch < nchunks; ch += 64) s += p[ch];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int j = t / nrhs, c = t - j * nrhs;
+    H[j + (int64_t)c * ldh] = s;
+  }
 }
 
 // X[:, c] (-)= Bk * H[:, c]   (SUB: subtract from X; else V = Bk H)
@@ -603,15 +612,15 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
            hipStream_t st) {
   const int nrhs = n1 + n2;
   if (k <= 0 || nrhs <= 0) return KF_OK;
-  if (nrhs > 32) {
-    set_error("gemv_t: at most 32 right-hand sides");
+  if (nrhs > 64) {
+    set_error("gemv_t: at most 64 right-hand sides");
     return KF_EINVAL;
   }
   if (n2 > 0 && m == nullptr) {
     set_error("gemv_t: weighted columns need the mass vector");
     return KF_EINVAL;
   }
-  const int CH = nrhs <= 8 ? 1024 : (nrhs <= 16 ? 512 : 256);
+  const int CH = nrhs <= 8 ? 1024 : (nrhs <= 16 ? 512 : (nrhs <= 32 ? 256 : 128));
   const int nchunks = ceil_div64(n, CH);
   const size_t need = (size_t)nchunks * k * nrhs;
   if (wk.cap < need) {
@@ -642,11 +651,14 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   else if (nrhs <= 16)
     hipLaunchKernelGGL(k_gemv_t<16>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
-  else
+  else if (nrhs <= 32)
     hipLaunchKernelGGL(k_gemv_t<32>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
+  else
+    hipLaunchKernelGGL(k_gemv_t<64>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 256)), dim3(256), 0, st, nchunks, k, nrhs,
+  hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
                      wk.partial, H, ldh);
   KF_HIP(hipGetLastError());
   return KF_OK;
@@ -670,8 +682,13 @@ int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H,
 int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, int64_t ldy, double* V, int64_t ldv,
             int nc, hipStream_t st) {
   if (nc <= 0) return KF_OK;
-  const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
-  hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+  if (nc <= 8) {
+    const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
+    hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+  } else {
+    const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 32));
+    hipLaunchKernelGGL((k_gemv_n<32, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+  }
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

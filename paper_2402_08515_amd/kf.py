@@ -46,6 +46,8 @@ class OptionsT(C.Structure):
     _fields_ = [
         ("precision", C.c_int32),
         ("check_every", C.c_int32),
+        ("check_growth", C.c_double),
+        ("full_reorth", C.c_int32),
         ("target", C.c_int32),
         ("max_iters", C.c_int32),
         ("drop_tol", C.c_double),
@@ -78,6 +80,7 @@ class ResultT(C.Structure):
         ("t_rr", C.c_double),
         ("t_refine", C.c_double),
         ("orth_error", C.c_double),
+        ("full_passes", C.c_int32),
     ]
 
 
@@ -188,13 +191,14 @@ class SolveResult:
     t_rr: float
     t_refine: float
     orth_error: float
+    full_passes: int
 
 
 class Problem:
     """Handle of ``kf_create``: pencil, interval, tau, L and options."""
 
     def __init__(self, S, m, omega_min: float, omega_max: float, tau: float, L: int, precision: str = "fp64",
-                 check_every: int = 1, target: int = 0, max_iters: int = 0, drop_tol: float = 1e-10,
+                 check_every: int = 1, check_growth: float = 0.0, full_reorth: bool = False, target: int = 0, max_iters: int = 0, drop_tol: float = 1e-10,
                  refine: bool = True, want_vectors: bool = False, index_bytes: int = 0, xcd_remap: bool = True):
         L_ = lib()
         self._h = C.c_void_p()
@@ -202,6 +206,8 @@ class Problem:
         L_.kf_default_options(C.byref(opt))
         opt.precision = _PREC[precision]
         opt.check_every = check_every
+        opt.check_growth = check_growth
+        opt.full_reorth = int(full_reorth)
         opt.target = target
         opt.max_iters = max_iters
         opt.drop_tol = drop_tol
@@ -283,6 +289,7 @@ class Problem:
                 t_rr=r.t_rr,
                 t_refine=r.t_refine,
                 orth_error=r.orth_error,
+                full_passes=r.full_passes,
             )
         finally:
             lib().kf_result_free(res)

@@ -41,11 +41,12 @@ def grid2d():
     return P, tau, L, w, V0, ref
 
 
-def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d):
+@pytest.mark.parametrize("full_reorth", [False, True])
+def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth):
     kf = _kf()
     P, tau, L, w, V0, ref = grid2d
-    print("case grid2d_64 fp64 solve", flush=True)
-    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    print(f"case grid2d_64 fp64 solve full_reorth={full_reorth}", flush=True)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, full_reorth=full_reorth)
     got = prob.solve(V0, m_max=40, tol=1e-9)
     tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
     assert got.basis_size == 40 and got.krylov_steps == 39
@@ -149,3 +150,44 @@ def test_repeat_runs_are_bitwise_identical(grid2d):
     a = prob.solve(V0, m_max=30, tol=1e-9)
     b = prob.solve(V0, m_max=30, tol=1e-9)
     assert np.array_equal(a.ritz, b.ritz) and np.array_equal(a.omega2, b.omega2)
+
+
+@pytest.fixture(scope="module")
+def grid3d():
+    import synth
+
+    P = workload("grid3d_96")
+    kf = _kf()
+    lam = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
+    tau, L = kf.time_step_rule(lam, P.omega_min)
+    tgt, vals, mult = distinct_target(grid_spectrum(3, 96), P.omega_min, P.omega_max, 1)
+    return P, tau, L, tgt, vals
+
+
+def test_grid3d_filter_full_size_matches_oracle(grid3d):
+    """The fused kernel at the benchmark's size and launch configuration."""
+    import torch
+
+    kf = _kf()
+    P, tau, L, tgt, vals = grid3d
+    print(f"case grid3d_96 apply_filter n={P.n} L={L}", flush=True)
+    V0 = start_block(P.n, 1, P.seed)
+    ref = oracle.apply_filter(P.S, P.m, tau, oracle.discrete_weights(P.omega_min, P.omega_max, tau, L), V0)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    y = prob.apply_filter(torch.from_numpy(V0).cuda()).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
+    """All 110 distinct eigenvalues in [30, 40] at the benchmark's settings;
+    the oracle's own run at this size takes minutes, so the closed form of
+    the pencil is the reference (eigenvalue error ~ residual^2)."""
+    kf = _kf()
+    P, tau, L, tgt, vals = grid3d
+    print(f"case grid3d_96 solve target={tgt}", flush=True)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, target=tgt, check_every=4, check_growth=0.15)
+    got = prob.solve(start_block(P.n, 1, P.seed), m_max=1024, tol=1e-6)
+    assert got.omega2.size == tgt == 110
+    assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
+    assert got.residual.max() <= 1e-6
+    assert got.orth_error < 1e-10
