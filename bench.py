@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--check-growth", type=float, default=0.15)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-traffic", action="store_true",
+                    help="for hardware-counter runs: a few filter applications and a plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not part of it",
@@ -118,6 +120,19 @@ def main():
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
                       check_every=args.check_every, check_growth=args.check_growth)
     V0 = start_block(P.n, P.block, P.seed)
+
+    if args.probe_traffic:
+        # counter calibration: one device-to-device copy of exactly 1 GiB read
+        # + 1 GiB written, then 3 filter applications (3*(L-1) fused steps)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        b = torch.empty_like(a)
+        b.copy_(a)
+        x = torch.from_numpy(V0).cuda()
+        for _ in range(3):
+            prob.apply_filter(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "copy_bytes": a.numel() * 8, "workload": P.name, "L": L}))
+        return
 
     results = []
     for i in range(args.warmup):

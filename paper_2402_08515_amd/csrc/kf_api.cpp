@@ -31,6 +31,15 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 using namespace kf;
 
+// time-stepping buffers (n x cap blocks)
+struct StepBufs {
+  void* Y0 = nullptr;
+  void* Y1 = nullptr;
+  void* R = nullptr;
+  int cap = 0;  // block width held
+  int vb = 0;   // value bytes
+};
+
 struct kf_problem {
   int32_t n = 0;
   int64_t nnz = 0;
@@ -45,12 +54,17 @@ struct kf_problem {
   SellOp A64;             // float64 copy for the mixed-mode refinement
   SellOp S;               // S in float64 (projection, residuals)
 
-  // time-stepping buffers (n x bk in the stepping precision)
-  void* Y0 = nullptr;
-  void* Y1 = nullptr;
-  void* R = nullptr;
-  int ycap = 0;       // block width the buffers hold
-  int yvb = 0;        // value bytes of the buffers
+  // time-stepping buffers (n x bk): stepping precision, and float64 for the
+  // mixed-mode refinement
+  StepBufs sb;    // stepping precision
+  StepBufs sb64;  // float64 (mixed-mode refinement)
+  // refinement blocks (n x rcap, leading dimension ldb)
+  double* Vx = nullptr;
+  double* Yy = nullptr;
+  double* Ysel = nullptr;  // gathered small vectors (k x rcap)
+  double* Gm = nullptr;    // rcap x rcap
+  int rcap = 0;
+  int rkcap = 0;
   // Krylov basis and projected pencil
   double* B = nullptr;
   int64_t ldb = 0;
@@ -199,39 +213,45 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
-int ensure_step_buffers(kf_problem* p, int bk) {
-  const int vb = p->A.val_bytes;
-  if (p->ycap >= bk && p->yvb == vb) return KF_OK;
-  dfree(p->Y0);
-  dfree(p->Y1);
-  dfree(p->R);
-  p->Y0 = p->Y1 = p->R = nullptr;
-  p->ycap = 0;
+int ensure_step_buffers(kf_problem* p, StepBufs& sb, int bk, int vb) {
+  if (sb.cap >= bk && sb.vb == vb) return KF_OK;
+  dfree(sb.Y0);
+  dfree(sb.Y1);
+  dfree(sb.R);
+  sb = StepBufs();
   const size_t bytes = (size_t)p->n * bk * vb;
-  if (hipMalloc(&p->Y0, bytes) != hipSuccess || hipMalloc(&p->Y1, bytes) != hipSuccess ||
-      hipMalloc(&p->R, bytes) != hipSuccess)
+  if (hipMalloc(&sb.Y0, bytes) != hipSuccess || hipMalloc(&sb.Y1, bytes) != hipSuccess ||
+      hipMalloc(&sb.R, bytes) != hipSuccess)
     return fail(KF_ENOMEM, "kf: time-stepping buffers");
-  p->ycap = bk;
-  p->yvb = vb;
+  sb.cap = bk;
+  sb.vb = vb;
   return KF_OK;
+}
+
+void free_step_buffers(StepBufs& sb) {
+  dfree(sb.Y0);
+  dfree(sb.Y1);
+  dfree(sb.R);
+  sb = StepBufs();
 }
 
 // C applied to bsrc columns of src (strides srs between rows, scs between
 // columns; float64) with kernel block width bk; the first bout columns of the
 // result go to dst (strides drs, dcs).  Asynchronous.
-int run_filter(kf_problem* p, const SellOp& A, const double* src, int64_t srs, int64_t scs, int bsrc, int bk,
-               double* dst, int64_t drs, int64_t dcs, int bout, const std::vector<double>& w) {
+int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, int64_t srs, int64_t scs, int bsrc,
+               int bk, double* dst, int64_t drs, int64_t dcs, int bout, const std::vector<double>& w) {
   const int L = (int)w.size();
   hipStream_t st = p->st;
   if (L == 1) return launch_scale_copy(p->n, bout, std::min(bsrc, bout), src, srs, scs, w[0], dst, drs, dcs, st);
-  KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, p->Y1, st));
-  void* Y[2] = {p->Y0, p->Y1};
+  KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
+  KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, sb.Y1, st));
+  void* Y[2] = {sb.Y0, sb.Y1};
   for (int l = 1; l < L; ++l) {
     int mode = (l == 1) ? kFirst : kMid;
     if (l == L - 1) mode |= kLast;
     void* cur = Y[l & 1];
     void* nxt = Y[(l + 1) & 1];
-    KF_TRY(launch_leapfrog(A, bk, mode, cur, nxt, nxt, p->R, dst, drs, dcs, bout, w[0], w[(size_t)l],
+    KF_TRY(launch_leapfrog(A, bk, mode, cur, nxt, nxt, sb.R, dst, drs, dcs, bout, w[0], w[(size_t)l],
                            p->opt.xcd_remap, st));
   }
   return KF_OK;
@@ -390,49 +410,47 @@ struct CheckOut {
   std::vector<double> acc_theta;  // accepted
   std::vector<double> acc_res;
   std::vector<int> acc_sel;       // index into the candidate list
-  std::vector<double> cand_theta;
+  std::vector<double> cand_theta; // candidates (interval widened by the margin)
   std::vector<double> cand_res;
+  std::vector<double> vectors;    // n x accepted (host), when requested
   double orth = 0.0;
 };
 
-// Rayleigh-Ritz on the leading k columns; residuals for the Ritz values in
-// the interval; acceptance at tol.
-int rr_check(kf_problem* p, int k, double tol, CheckOut& out) {
+// Ritz vectors V = Bk Ysel (chunks of 64), residuals ||S v - theta M v|| /
+// ||S v|| and acceptance (theta inside the interval and residual <= tol).
+// ew.Y holds the k x nsel eigenvectors for sel.
+int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const std::vector<double>& sel_in, double tol,
+                   bool want_vectors, CheckOut& out, bool rayleigh = false) {
+  std::vector<double> sel = sel_in;
   hipStream_t st = p->st;
-  KF_TRY(eig_values(p->ew, k, p->H, p->hcap, st));
-  out.ritz.assign((size_t)k, 0.0);
-  KF_HIP(hipMemcpyAsync(out.ritz.data(), p->ew.theta, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-  KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
-  KF_HIP(hipMemcpyAsync(&out.orth, p->small + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
-  KF_HIP(hipStreamSynchronize(st));
-  const double lo = p->omega_min, hi = p->omega_max;
-  std::vector<double> sel;
-  for (int i = 0; i < k; ++i) {
-    const double om = std::sqrt(std::max(out.ritz[(size_t)i], 0.0));
-    if (om >= lo && om <= hi) sel.push_back(out.ritz[(size_t)i]);
-  }
+  const int nsel = (int)sel.size();
   out.cand_theta = sel;
   out.cand_res.assign(sel.size(), 0.0);
   out.acc_theta.clear();
   out.acc_res.clear();
   out.acc_sel.clear();
-  const int nsel = (int)sel.size();
-  if (nsel == 0) return KF_OK;
-  // clusters of (nearly) equal Ritz values get mutually orthogonal vectors
-  const double tn = std::max(std::fabs(out.ritz.front()), std::fabs(out.ritz.back()));
-  std::vector<int32_t> cl{0};
-  for (int i = 1; i < nsel; ++i)
-    if (sel[(size_t)i] - sel[(size_t)i - 1] > 1e-9 * tn) cl.push_back(i);
-  const int ncl = (int)cl.size();
-  cl.push_back(nsel);
-  KF_TRY(eig_vectors(p->ew, k, sel.data(), cl.data(), ncl, nsel, st));
+  out.vectors.clear();
+  const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
   double* d_theta = p->small + 2048;
   double* d_num = p->small + 2048 + 64;
   double* d_den = p->small + 2048 + 128;
   for (int c0 = 0; c0 < nsel; c0 += 64) {
     const int nc = std::min(64, nsel - c0);
-    KF_TRY(gemm_nn(p->n, k, p->B, p->ldb, p->ew.Y + (int64_t)c0 * k, k, p->V, p->n, nc, st));
+    KF_TRY(gemm_nn(p->n, k, Bk, ldb, p->ew.Y + (int64_t)c0 * k, k, p->V, p->n, nc, st));
     KF_TRY(spmv_cols(p->S, p->V, p->n, p->SV, p->n, nc, nullptr, st));
+    if (rayleigh) {
+      // theta <- v^T S v / v^T M v for each Ritz vector
+      double* q = p->small + 2048 + 192;  // 2 x 64
+      for (int c = 0; c < nc; ++c)
+        KF_TRY(gemv_t(p->n, 1, p->V + (int64_t)c * p->n, p->n, p->SV + (int64_t)c * p->n, 1, p->n,
+                      p->V + (int64_t)c * p->n, 1, p->n, p->d_m, q + 2 * c, 1, p->gw, st));
+      std::vector<double> hq((size_t)2 * nc);
+      KF_HIP(hipMemcpyAsync(hq.data(), q, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, st));
+      KF_HIP(hipStreamSynchronize(st));
+      for (int c = 0; c < nc; ++c)
+        if (hq[(size_t)2 * c + 1] > 0.0) sel[(size_t)c0 + c] = hq[(size_t)2 * c] / hq[(size_t)2 * c + 1];
+      out.cand_theta = sel;
+    }
     KF_HIP(hipMemcpyAsync(d_theta, sel.data() + c0, sizeof(double) * nc, hipMemcpyHostToDevice, st));
     KF_TRY(residual_norms(p->n, p->SV, p->V, p->n, p->d_m, d_theta, nc, d_num, d_den, p->rw, st));
     std::vector<double> num((size_t)nc), den((size_t)nc);
@@ -445,14 +463,197 @@ int rr_check(kf_problem* p, int k, double tol, CheckOut& out) {
       if (!(dn > 0.0)) dn = std::max(std::fabs(th), 1e-300);
       const double r = std::sqrt(std::max(num[(size_t)c], 0.0)) / dn;
       out.cand_res[(size_t)c0 + c] = r;
-      if (r <= tol) {
+      const double om = std::sqrt(std::max(th, 0.0));
+      const bool inside = th >= lo2 && th <= hi2 && om >= p->omega_min && om <= p->omega_max;
+      if (inside && r <= tol) {
         out.acc_theta.push_back(th);
         out.acc_res.push_back(r);
         out.acc_sel.push_back(c0 + c);
+        if (want_vectors) {
+          const size_t off = out.vectors.size();
+          out.vectors.resize(off + (size_t)p->n);
+          KF_HIP(hipMemcpyAsync(out.vectors.data() + off, p->V + (int64_t)c * p->n, sizeof(double) * p->n,
+                                hipMemcpyDeviceToHost, st));
+        }
       }
     }
+    if (want_vectors) KF_HIP(hipStreamSynchronize(st));
   }
   return KF_OK;
+}
+
+// eigenvalues of the k x k symmetric matrix Hm (ld ldh) into out (host), and
+// eigenvectors for those selected by keep() into ew.Y; returns the selection
+template <class Keep>
+int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector<double>& theta, Keep keep,
+                std::vector<double>& sel) {
+  hipStream_t st = p->st;
+  KF_TRY(eig_values(p->ew, k, Hm, ldh, st));
+  theta.assign((size_t)k, 0.0);
+  KF_HIP(hipMemcpyAsync(theta.data(), p->ew.theta, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  KF_HIP(hipStreamSynchronize(st));
+  sel.clear();
+  for (int i = 0; i < k; ++i)
+    if (keep(theta[(size_t)i])) sel.push_back(theta[(size_t)i]);
+  const int nsel = (int)sel.size();
+  if (nsel == 0) return KF_OK;
+  // clusters of (nearly) equal values get mutually orthogonal vectors
+  const double tn = std::max(std::fabs(theta.front()), std::fabs(theta.back()));
+  std::vector<int32_t> cl{0};
+  for (int i = 1; i < nsel; ++i)
+    if (sel[(size_t)i] - sel[(size_t)i - 1] > 1e-9 * tn) cl.push_back(i);
+  const int ncl = (int)cl.size();
+  cl.push_back(nsel);
+  return eig_vectors(p->ew, k, sel.data(), cl.data(), ncl, nsel, st);
+}
+
+// Rayleigh-Ritz on the leading k basis columns.  Residuals are formed for the
+// Ritz values with omega in the interval widened by `margin` on both sides;
+// acceptance needs omega inside the interval and residual <= tol.
+int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, bool want_vectors) {
+  hipStream_t st = p->st;
+  KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
+  KF_HIP(hipMemcpyAsync(&out.orth, p->small + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+  const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+  std::vector<double> sel;
+  KF_TRY(small_eigen(
+      p, k, p->H, p->hcap, out.ritz,
+      [&](double th) {
+        const double om = std::sqrt(std::max(th, 0.0));
+        return om >= lo && om <= hi;
+      },
+      sel));
+  return ritz_residuals(p, p->B, p->ldb, k, sel, tol, want_vectors, out);
+}
+
+// Mixed-precision refinement.  The near-interval Ritz vectors X of the
+// float32 Krylov space (residual <= 0.1, omega within the interval widened by
+// the margin) get one float64 application of the filter, Y = C X, which
+// damps the high-frequency round-off of the float32 steps; the pencil is
+// projected onto span(Y) in float64.  span(Y) is M-orthonormalised through the
+// eigen-decomposition of G = Y^T M Y (twice; directions with eigenvalue below
+// 1e-12 of the largest are dropped), and each Ritz value is replaced by the
+// Rayleigh quotient of its Ritz vector before the residual is taken.
+// Limitation: float32 round-off also seeds the copies of a multiple
+// eigenvalue that a block of b start vectors cannot see in exact arithmetic
+// (multiplicity > b); those half-converged copies contaminate the pairs near
+// them, so such spectra need b >= the multiplicity in this mode.
+int eig_orthonormalise(kf_problem* p, double* Z, int nz, double* out, int* r_out) {
+  // out = Z * U diag(g)^{-1/2} over the kept eigenpairs (g, U) of Z^T M Z
+  hipStream_t st = p->st;
+  const int n = p->n;
+  const int64_t ld = p->ldb;
+  for (int c0 = 0; c0 < nz; c0 += 32) {
+    const int nb = std::min(32, nz - c0);
+    KF_TRY(gemv_t(n, nz, Z, ld, nullptr, 0, 0, Z + (int64_t)c0 * ld, nb, ld, p->d_m, p->Gm + (int64_t)c0 * nz, nz,
+                  p->gw, st));
+  }
+  KF_TRY(symmetrize(nz, p->Gm, nz, st));
+  std::vector<double> g, gsel;
+  KF_TRY(small_eigen(p, nz, p->Gm, nz, g, [](double) { return true; }, gsel));
+  const double gmax = g.empty() ? 0.0 : g.back();
+  std::vector<int> keep;
+  for (int i = 0; i < nz; ++i)
+    if (g[(size_t)i] > 1e-12 * gmax) keep.push_back(i);
+  const int r = (int)keep.size();
+  *r_out = r;
+  if (r == 0) return KF_OK;
+  std::vector<double> U((size_t)nz * nz), Th((size_t)nz * r);
+  KF_HIP(hipMemcpyAsync(U.data(), p->ew.Y, sizeof(double) * nz * nz, hipMemcpyDeviceToHost, st));
+  KF_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < r; ++j) {
+    const double sc = 1.0 / std::sqrt(g[(size_t)keep[(size_t)j]]);
+    for (int i = 0; i < nz; ++i) Th[(size_t)j * nz + i] = U[(size_t)keep[(size_t)j] * nz + i] * sc;
+  }
+  KF_HIP(hipMemcpyAsync(p->Ysel, Th.data(), sizeof(double) * nz * r, hipMemcpyHostToDevice, st));
+  KF_TRY(gemm_nn(n, nz, Z, ld, p->Ysel, nz, out, ld, r, st));
+  KF_HIP(hipStreamSynchronize(st));
+  return KF_OK;
+}
+
+int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out) {
+  hipStream_t st = p->st;
+  const int n = p->n;
+  const int64_t ld = p->ldb;
+  std::vector<int> pick;
+  for (size_t s = 0; s < in.cand_res.size(); ++s)
+    if (in.cand_res[s] <= 0.1) pick.push_back((int)s);
+  const int nc = (int)pick.size();
+  out = in;
+  if (nc == 0 || !p->A64.val) return KF_OK;
+  if (nc > 2048) return fail(KF_EINVAL, "kf_solve: refinement block larger than 2048 columns");
+  if (nc > p->rcap || k > p->rkcap) {
+    dfree(p->Vx);
+    dfree(p->Yy);
+    dfree(p->Ysel);
+    dfree(p->Gm);
+    p->Vx = p->Yy = p->Ysel = p->Gm = nullptr;
+    p->rcap = p->rkcap = 0;
+    const int cap = std::max(nc, 64);
+    const int kc = std::max(k, cap);
+    KF_TRY(dalloc(&p->Vx, (size_t)ld * cap));
+    KF_TRY(dalloc(&p->Yy, (size_t)ld * cap));
+    KF_TRY(dalloc(&p->Ysel, (size_t)kc * cap));
+    KF_TRY(dalloc(&p->Gm, (size_t)cap * cap));
+    p->rcap = cap;
+    p->rkcap = kc;
+  }
+  // X = B * (selected eigenvectors of the last check), into Vx
+  for (int i = 0; i < nc; ++i)
+    KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)i * k, p->ew.Y + (int64_t)pick[(size_t)i] * k, sizeof(double) * k,
+                          hipMemcpyDeviceToDevice, st));
+  KF_TRY(gemm_nn(n, k, p->B, p->ldb, p->Ysel, k, p->Vx, ld, nc, st));
+  // Yy = C X in float64
+  for (int c0 = 0; c0 < nc; c0 += 16) {
+    const int nb = std::min(16, nc - c0);
+    KF_TRY(run_filter(p, p->A64, p->sb64, p->Vx + (int64_t)c0 * ld, 1, ld, nb, pow2ceil(nb), p->Yy + (int64_t)c0 * ld,
+                      1, ld, nb, p->w));
+  }
+  int r = 0, r2 = 0;
+  KF_TRY(eig_orthonormalise(p, p->Yy, nc, p->Vx, &r));
+  if (r == 0) return KF_OK;
+  KF_TRY(eig_orthonormalise(p, p->Vx, r, p->Yy, &r2));
+  if (r2 == 0) return KF_OK;
+  // projected pencil Z^T S Z with Z = Yy[:, :r2]; S Z into Vx
+  for (int c0 = 0; c0 < r2; c0 += 16) {
+    const int nb = std::min(16, r2 - c0);
+    KF_TRY(spmv_cols(p->S, p->Yy + (int64_t)c0 * ld, ld, p->Vx + (int64_t)c0 * ld, ld, nb, nullptr, st));
+  }
+  for (int c0 = 0; c0 < r2; c0 += 32) {
+    const int nb = std::min(32, r2 - c0);
+    KF_TRY(gemv_t(n, r2, p->Yy, ld, p->Vx + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr,
+                  p->Gm + (int64_t)c0 * r2, r2, p->gw, st));
+  }
+  KF_TRY(symmetrize(r2, p->Gm, r2, st));
+  const double margin = 0.05 * (p->omega_max - p->omega_min);
+  const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+  std::vector<double> th, sel;
+  KF_TRY(small_eigen(
+      p, r2, p->Gm, r2, th,
+      [&](double t) {
+        const double om = std::sqrt(std::max(t, 0.0));
+        return om >= lo && om <= hi;
+      },
+      sel));
+  KF_TRY(ritz_residuals(p, p->Yy, ld, r2, sel, tol, want_vectors, out, true));
+  out.ritz = in.ritz;
+  out.orth = in.orth;
+  return KF_OK;
+}
+
+// Pairs that count towards the target: accepted values within 1e-8
+// (relative) of each other form one eigenvalue, which counts at most b times
+// (a block of b start vectors sees at most b directions of an eigenspace).
+int distinct_count(const std::vector<double>& acc, int b) {
+  int cnt = 0;
+  size_t i = 0;
+  while (i < acc.size()) {
+    size_t j = i + 1;
+    while (j < acc.size() && acc[j] - acc[j - 1] <= 1e-8 * std::fabs(acc[j])) ++j;
+    cnt += (int)std::min<size_t>(j - i, (size_t)b);
+    i = j;
+  }
+  return cnt;
 }
 
 void free_problem(kf_problem* p) {
@@ -460,8 +661,10 @@ void free_problem(kf_problem* p) {
   free_sell(p->A);
   free_sell(p->A64);
   free_sell(p->S);
-  void* ptrs[] = {p->d_m, p->Y0, p->Y1, p->R, p->B, p->H, p->G, p->T, p->W, p->V, p->SV, p->small, p->flags};
+  void* ptrs[] = {p->d_m, p->B, p->H, p->G, p->T, p->W, p->V, p->SV, p->small, p->flags, p->Vx, p->Yy, p->Ysel, p->Gm};
   for (void* q : ptrs) dfree(q);
+  free_step_buffers(p->sb);
+  free_step_buffers(p->sb64);
   if (p->gw.partial) (void)hipFree(p->gw.partial);
   if (p->rw.partial) (void)hipFree(p->rw.partial);
   free_eig(p->ew);
@@ -685,8 +888,7 @@ int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b) {
   if (!p || !x || !y) return fail(KF_EINVAL, "kf_apply_filter: NULL argument");
   if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_apply_filter: b must lie in [1, 16]");
   const int bk = pow2ceil(b);
-  KF_TRY(ensure_step_buffers(p, bk));
-  return run_filter(p, p->A, x, b, 1, b, bk, y, b, 1, b, p->w);
+  return run_filter(p, p->A, p->sb, x, b, 1, b, bk, y, b, 1, b, p->w);
 }
 
 int kf_result_free(kf_result* r) {
@@ -712,7 +914,6 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
     if (!std::isfinite(start[i])) return fail(KF_EINVAL, "kf_solve: non-finite start block");
   const int bk = pow2ceil(b);
   hipStream_t st = p->st;
-  KF_TRY(ensure_step_buffers(p, bk));
   KF_TRY(ensure_basis(p, m_max + bk));
   KF_TRY(ensure_misc(p));
   const int32_t n = p->n;
@@ -735,6 +936,15 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   KF_TRY(orth_block(p, 0, 0, b, &kept, ref, ev[2]));
   KF_TRY(elapsed(ev[1], ev[2], t_gs));
   if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
+  // Mixed precision: float32 time stepping leaves a residual floor of about
+  // eps32 * lambda_max / omega^2 (lambda_max <= 4/tau^2 by the CFL bound); the
+  // Krylov loop accepts at ten times that floor and the float64 refinement
+  // takes the pairs to tol.  Candidates are taken from the interval widened
+  // by 5% of its width.
+  const bool refine = p->opt.precision == KF_MIXED && p->opt.refine && p->A64.val;
+  const double floor32 = 5.96e-8 * 4.0 / (p->tau * p->tau) / std::max(p->omega_min * p->omega_min, 1e-300);
+  const double tol_loop = refine ? std::max(tol, std::min(1e-3, 10.0 * floor32)) : tol;
+  const double margin = refine ? 0.05 * (p->omega_max - p->omega_min) : 0.0;
   int cur = kept, q0 = 0, qn = kept;
   int prev0 = 0;       // first column of the block before the last one
   int full_passes = 0;
@@ -754,7 +964,7 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
     if (!rr_pending) KF_HIP(hipEventRecord(ev[3], st));
     if (pending > 0) KF_TRY(rr_update(p, cur - pending, pending));
     pending = 0;
-    KF_TRY(rr_check(p, cur, tol, chk));
+    KF_TRY(rr_check(p, cur, tol_loop, chk, margin, false));
     KF_HIP(hipEventRecord(ev[4], st));
     rr_pending = true;
     checked_at = cur;
@@ -764,8 +974,8 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
     if (p->opt.max_iters > 0 && iters >= p->opt.max_iters) break;
     if (cur >= m_max) break;
     KF_HIP(hipEventRecord(ev[0], st));
-    KF_TRY(run_filter(p, p->A, p->B + (int64_t)q0 * ldb, 1, ldb, qn, bk, p->B + (int64_t)cur * ldb, 1, ldb, bk,
-                      p->w));
+    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)q0 * ldb, 1, ldb, qn, bk, p->B + (int64_t)cur * ldb, 1, ldb,
+                      bk, p->w));
     KF_HIP(hipEventRecord(ev[1], st));
     ++iters;
     lf_steps += (int64_t)qn * (p->L - 1);
@@ -797,62 +1007,58 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
     if (iters % p->opt.check_every == 0 && cur >= next_check) {
       KF_TRY(check_now());
       next_check = (int)std::ceil(cur * (1.0 + p->opt.check_growth));
-      if (target > 0 && (int)chk.acc_theta.size() >= target) break;
+      if (target > 0 && distinct_count(chk.acc_theta, b) >= target) break;
     }
   }
   if (checked_at != cur) KF_TRY(check_now());
   KF_HIP(hipEventSynchronize(ev[4]));
   if (rr_pending) KF_TRY(elapsed(ev[3], ev[4], t_rr));
   p->basis_cols = cur;
+  double t_ref = 0.0;
+  CheckOut fin;
+  if (refine) {
+    KF_HIP(hipEventRecord(ev[3], st));
+    KF_TRY(refine_mixed(p, cur, tol, chk, p->opt.want_vectors != 0, fin));
+    KF_HIP(hipEventRecord(ev[4], st));
+    KF_HIP(hipEventSynchronize(ev[4]));
+    KF_TRY(elapsed(ev[3], ev[4], t_ref));
+  } else if (p->opt.want_vectors) {
+    KF_TRY(rr_check(p, cur, tol, fin, margin, true));
+  } else {
+    fin = chk;
+  }
   if (breakdown)
     status = KF_EBREAKDOWN;
-  else if (target > 0 && (int)chk.acc_theta.size() < target)
+  else if (target > 0 && distinct_count(fin.acc_theta, b) < target)
     status = KF_ENOTCONV;
 
   kf_result* r = (kf_result*)std::calloc(1, sizeof(kf_result));
   if (!r) return fail(KF_ENOMEM, "kf_solve: result allocation");
-  const int na = (int)chk.acc_theta.size();
+  const int na = (int)fin.acc_theta.size();
   r->n = n;
   r->n_pairs = na;
   r->omega2 = (double*)std::malloc(sizeof(double) * std::max(na, 1));
   r->omega = (double*)std::malloc(sizeof(double) * std::max(na, 1));
   r->residual = (double*)std::malloc(sizeof(double) * std::max(na, 1));
-  r->n_ritz = (int)chk.ritz.size();
+  r->n_ritz = (int)fin.ritz.size();
   r->ritz = (double*)std::malloc(sizeof(double) * std::max(r->n_ritz, 1));
   if (!r->omega2 || !r->omega || !r->residual || !r->ritz) {
     kf_result_free(r);
     return fail(KF_ENOMEM, "kf_solve: result allocation");
   }
   for (int i = 0; i < na; ++i) {
-    r->omega2[i] = chk.acc_theta[(size_t)i];
-    r->omega[i] = std::sqrt(std::max(chk.acc_theta[(size_t)i], 0.0));
-    r->residual[i] = chk.acc_res[(size_t)i];
+    r->omega2[i] = fin.acc_theta[(size_t)i];
+    r->omega[i] = std::sqrt(std::max(fin.acc_theta[(size_t)i], 0.0));
+    r->residual[i] = fin.acc_res[(size_t)i];
   }
-  std::memcpy(r->ritz, chk.ritz.data(), sizeof(double) * r->n_ritz);
+  std::memcpy(r->ritz, fin.ritz.data(), sizeof(double) * r->n_ritz);
   if (p->opt.want_vectors && na > 0) {
     r->vectors = (double*)std::malloc(sizeof(double) * (size_t)n * na);
     if (!r->vectors) {
       kf_result_free(r);
       return fail(KF_ENOMEM, "kf_solve: vector allocation");
     }
-    const int k = cur;
-    for (int a0 = 0; a0 < na; a0 += 64) {
-      const int nc = std::min(64, na - a0);
-      for (int c = 0; c < nc; ++c) {
-        const int s = chk.acc_sel[(size_t)a0 + c];
-        int rc = gemm_nn(n, k, p->B, ldb, p->ew.Y + (int64_t)s * k, k, p->V + (int64_t)c * n, n, 1, st);
-        if (rc) {
-          kf_result_free(r);
-          return rc;
-        }
-      }
-      if (hipMemcpyAsync(r->vectors + (size_t)a0 * n, p->V, sizeof(double) * n * nc, hipMemcpyDeviceToHost, st) !=
-              hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
-        kf_result_free(r);
-        return fail(KF_EHIP, "kf_solve: vector readback failed");
-      }
-    }
+    std::memcpy(r->vectors, fin.vectors.data(), sizeof(double) * (size_t)n * na);
   }
   r->krylov_steps = iters;
   r->basis_size = cur;
@@ -862,7 +1068,7 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   r->t_leapfrog = t_lf;
   r->t_gs = t_gs;
   r->t_rr = t_rr;
-  r->t_refine = 0.0;
+  r->t_refine = t_ref;
   r->orth_error = chk.orth;
   r->full_passes = full_passes;
   KF_HIP(hipStreamSynchronize(st));

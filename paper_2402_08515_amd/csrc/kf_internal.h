@@ -118,6 +118,9 @@ int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ld
 int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, double* G, int64_t ldh,
                hipStream_t st);
 
+// A = (A + A^T)/2 for the leading k x k block
+int symmetrize(int k, double* A, int64_t lda, hipStream_t st);
+
 // max |G - I| over the leading k x k block -> *out (device scalar)
 int orth_error(int k, const double* G, int64_t ldg, double* out, hipStream_t st);
 

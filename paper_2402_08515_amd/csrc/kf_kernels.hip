@@ -422,6 +422,16 @@ __global__ __launch_bounds__(256) void k_rr_scatter(int k, int c0, int nc, const
   G[col + (int64_t)j * ldh] = g;
 }
 
+__global__ __launch_bounds__(256) void k_symmetrize(int k, double* __restrict__ A, int64_t lda) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  const int64_t j = t / k, i = t - j * k;
+  if (i <= j) return;
+  const double v = 0.5 * (A[i + j * lda] + A[j + i * lda]);
+  A[i + j * lda] = v;
+  A[j + i * lda] = v;
+}
+
 __global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __restrict__ G, int64_t ldg,
                                                      double* __restrict__ out) {
   __shared__ double red[16];
@@ -774,6 +784,13 @@ int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, d
   if (nc <= 0) return KF_OK;
   hipLaunchKernelGGL(k_rr_scatter, dim3(ceil_div64((int64_t)k * nc, 256)), dim3(256), 0, st, k, c0, nc, T, ldt, H, G,
                      ldh);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int symmetrize(int k, double* A, int64_t lda, hipStream_t st) {
+  if (k <= 1) return KF_OK;
+  hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div64((int64_t)k * k, 256)), dim3(256), 0, st, k, A, lda);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
