@@ -194,6 +194,42 @@ int kf_result_free(kf_result* r);
  * receives the number copied. */
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols);
 
+/* ---- batches of independent problems (one batched time-stepping launch) ----
+ * Every member is a full problem (kf_create semantics); the time loops of all
+ * members advance together: one filter application of the whole batch is a
+ * captured graph of max(L)-1 fused-step launches over the stacked
+ * (block-diagonal) operator, replayed once per Krylov iteration.
+ * Orthogonalisation and Rayleigh-Ritz run per member. */
+typedef struct kf_problem_desc {
+  kf_csr S;
+  const double* m_diag;  /* host (or device, with S.on_device) */
+  double omega_min, omega_max, tau;
+  int32_t L;
+  int32_t target;        /* per-member stop count (0: run to m_max) */
+} kf_problem_desc;
+
+typedef struct kf_batch kf_batch; /* opaque */
+
+/* Create a batch of P (1..256) members from descs[P]; opt applies to every
+ * member (its stream and target are ignored: the batch owns one stream).
+ * *out is released with kf_destroy_batch. */
+int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* opt, kf_batch** out);
+
+/* Release a batch (NULL accepted). */
+int kf_destroy_batch(kf_batch* bt);
+
+/* y_p = C_p x_p for every member p in one batched application: x[p], y[p]
+ * are DEVICE pointers to n_p x b COLUMN-major float64 blocks (leading
+ * dimension n_p), 1 <= b <= 16.  Synchronous. */
+int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y, int32_t b);
+
+/* Solve every member from its host start block starts[p] (n_p x b
+ * row-major); results[P] receives one library-owned result per member
+ * (release each with kf_result_free).  t_leapfrog of every result is the time
+ * of the batched time stepping of the whole batch.  Synchronous. */
+int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t m_max, double tol,
+                   kf_result** results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,6 +85,24 @@ struct kf_problem {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
+struct kf_batch {
+  int P = 0;
+  std::vector<kf_problem*> probs;
+  hipStream_t st = nullptr;
+  SellOp A;                  // stacked block-diagonal operator, stepping precision
+  int32_t* d_sp = nullptr;   // slice -> problem
+  BatchTables h_tb{};
+  BatchTables* d_tb = nullptr;
+  void* wtab = nullptr;      // P x lmax weights, stepping precision
+  int lmax = 1;
+  int64_t rows = 0;
+  StepBufs sb;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_bk = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
 namespace {
 
 constexpr int kSmall = 4096;
@@ -902,136 +920,172 @@ int kf_result_free(kf_result* r) {
   return KF_OK;
 }
 
-int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol, kf_result** out) {
-  const double t0 = now_s();
-  if (!p || !start || !out) return fail(KF_EINVAL, "kf_solve: NULL argument");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// State of one eigensolve between filter applications (Algorithm 2.5's Krylov
+// loop unrolled into begin / after-filter / finish so that a batch driver can
+// interleave many problems around one batched time-stepping launch).
+struct SolveState {
+  int b = 1, bk = 1, m_max = 0;
+  double tol = 0, tol_loop = 0, margin = 0;
+  bool refine = false;
+  int cur = 0, q0 = 0, qn = 0, prev0 = 0, pending = 0;
+  int iters = 0, full_passes = 0, checked_at = -1, next_check = 0, target = 0;
+  int64_t lf_steps = 0;
+  bool breakdown = false, done = false, rr_pending = false, timed_filter = false;
+  double wsum = 0, t0 = 0, t_lf = 0, t_gs = 0, t_rr = 0, t_ref = 0;
+  CheckOut chk;
+  std::vector<double> ref;
+};
+
+int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
+  float ms = 0.f;
+  KF_HIP(hipEventElapsedTime(&ms, a, b));
+  acc += ms * 1e-3;
+  return KF_OK;
+}
+
+int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol, SolveState& s) {
+  s = SolveState();
+  s.t0 = now_s();
+  if (!p || !start) return fail(KF_EINVAL, "kf_solve: NULL argument");
   if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_solve: b must lie in [1, 16]");
   if (m_max < b) return fail(KF_EINVAL, "kf_solve: m_max must be >= b");
   if (m_max > 2048) return fail(KF_EINVAL, "kf_solve: m_max must be <= 2048");
   if (!(tol > 0)) return fail(KF_EINVAL, "kf_solve: tol must be positive");
   for (int64_t i = 0; i < (int64_t)p->n * b; ++i)
     if (!std::isfinite(start[i])) return fail(KF_EINVAL, "kf_solve: non-finite start block");
-  const int bk = pow2ceil(b);
+  s.b = b;
+  s.bk = pow2ceil(b);
+  s.m_max = m_max;
+  s.tol = tol;
   hipStream_t st = p->st;
-  KF_TRY(ensure_basis(p, m_max + bk));
+  KF_TRY(ensure_basis(p, m_max + s.bk));
   KF_TRY(ensure_misc(p));
   const int32_t n = p->n;
-  const int64_t ldb = p->ldb;
-
   // start block: host row-major -> V (scratch) -> B[:, 0:b] column-major
   KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyHostToDevice, st));
-  KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, ldb, st));
+  KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, p->ldb, st));
   int kept = 0;
-  std::vector<double> ref;
-  double t_lf = 0, t_gs = 0, t_rr = 0;
-  hipEvent_t* ev = p->ev;
-  auto elapsed = [&](hipEvent_t a, hipEvent_t b2, double& acc) -> int {
-    float ms = 0.f;
-    KF_HIP(hipEventElapsedTime(&ms, a, b2));
-    acc += ms * 1e-3;
-    return KF_OK;
-  };
-  KF_HIP(hipEventRecord(ev[1], st));
-  KF_TRY(orth_block(p, 0, 0, b, &kept, ref, ev[2]));
-  KF_TRY(elapsed(ev[1], ev[2], t_gs));
+  KF_HIP(hipEventRecord(p->ev[1], st));
+  KF_TRY(orth_block(p, 0, 0, b, &kept, s.ref, p->ev[2]));
+  KF_TRY(elapsed_acc(p->ev[1], p->ev[2], s.t_gs));
   if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
   // Mixed precision: float32 time stepping leaves a residual floor of about
   // eps32 * lambda_max / omega^2 (lambda_max <= 4/tau^2 by the CFL bound); the
   // Krylov loop accepts at ten times that floor and the float64 refinement
   // takes the pairs to tol.  Candidates are taken from the interval widened
   // by 5% of its width.
-  const bool refine = p->opt.precision == KF_MIXED && p->opt.refine && p->A64.val;
+  s.refine = p->opt.precision == KF_MIXED && p->opt.refine && p->A64.val;
   const double floor32 = 5.96e-8 * 4.0 / (p->tau * p->tau) / std::max(p->omega_min * p->omega_min, 1e-300);
-  const double tol_loop = refine ? std::max(tol, std::min(1e-3, 10.0 * floor32)) : tol;
-  const double margin = refine ? 0.05 * (p->omega_max - p->omega_min) : 0.0;
-  int cur = kept, q0 = 0, qn = kept;
-  int prev0 = 0;       // first column of the block before the last one
-  int full_passes = 0;
-  int pending = kept;  // basis columns whose projected-pencil columns are not yet formed
-  bool rr_pending = false;  // ev[3] -> ev[4] not yet accumulated
-  int iters = 0;
-  int64_t lf_steps = 0;
-  bool breakdown = false;
-  const int target = p->opt.target;
-  CheckOut chk;
-  int checked_at = -1;
-  int next_check = 0;
-  double wsum = 0.0;
-  for (double v : p->w) wsum += std::fabs(v);
-  int status = KF_OK;
-  auto check_now = [&]() -> int {
-    if (!rr_pending) KF_HIP(hipEventRecord(ev[3], st));
-    if (pending > 0) KF_TRY(rr_update(p, cur - pending, pending));
-    pending = 0;
-    KF_TRY(rr_check(p, cur, tol_loop, chk, margin, false));
-    KF_HIP(hipEventRecord(ev[4], st));
-    rr_pending = true;
-    checked_at = cur;
-    return KF_OK;
-  };
-  while (true) {
-    if (p->opt.max_iters > 0 && iters >= p->opt.max_iters) break;
-    if (cur >= m_max) break;
-    KF_HIP(hipEventRecord(ev[0], st));
-    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)q0 * ldb, 1, ldb, qn, bk, p->B + (int64_t)cur * ldb, 1, ldb,
-                      bk, p->w));
-    KF_HIP(hipEventRecord(ev[1], st));
-    ++iters;
-    lf_steps += (int64_t)qn * (p->L - 1);
-    KF_TRY(orth_block(p, cur, cur, bk, &kept, ref, ev[2], pending, p->opt.full_reorth ? -1 : prev0,
-                      &full_passes));  // synchronises the stream
-    pending = 0;
-    if (rr_pending) {
-      KF_TRY(elapsed(ev[3], ev[4], t_rr));
-      rr_pending = false;
-    }
-    KF_TRY(elapsed(ev[0], ev[1], t_lf));
-    KF_TRY(elapsed(ev[1], ev[2], t_gs));
-    for (int j = 0; j < bk; ++j) {
-      // a stable step keeps |C x|_M <= sum|w_l| max|q_l| for |x|_M = 1
-      if (!std::isfinite(ref[(size_t)j]) || ref[(size_t)j] > 1e6 * std::max(wsum, 1e-300)) {
-        return fail(KF_EUNSTABLE, "kf_solve: time stepping diverged (tau too large for the spectrum?)");
-      }
-    }
-    kept = std::min(kept, m_max - cur);
-    if (kept == 0) {
-      breakdown = true;
-      break;
-    }
-    prev0 = q0;
-    q0 = cur;
-    qn = kept;
-    cur += kept;
-    pending = kept;
-    if (iters % p->opt.check_every == 0 && cur >= next_check) {
-      KF_TRY(check_now());
-      next_check = (int)std::ceil(cur * (1.0 + p->opt.check_growth));
-      if (target > 0 && distinct_count(chk.acc_theta, b) >= target) break;
-    }
+  s.tol_loop = s.refine ? std::max(tol, std::min(1e-3, 10.0 * floor32)) : tol;
+  s.margin = s.refine ? 0.05 * (p->omega_max - p->omega_min) : 0.0;
+  s.cur = kept;
+  s.q0 = 0;
+  s.qn = kept;
+  s.prev0 = 0;
+  s.pending = kept;
+  s.target = p->opt.target;
+  for (double v : p->w) s.wsum += std::fabs(v);
+  return KF_OK;
+}
+
+bool solve_wants_filter(const kf_problem* p, const SolveState& s) {
+  if (s.done) return false;
+  if (p->opt.max_iters > 0 && s.iters >= p->opt.max_iters) return false;
+  return s.cur < s.m_max;
+}
+
+int solve_check_now(kf_problem* p, SolveState& s) {
+  hipStream_t st = p->st;
+  if (!s.rr_pending) KF_HIP(hipEventRecord(p->ev[3], st));
+  if (s.pending > 0) KF_TRY(rr_update(p, s.cur - s.pending, s.pending));
+  s.pending = 0;
+  KF_TRY(rr_check(p, s.cur, s.tol_loop, s.chk, s.margin, false));
+  KF_HIP(hipEventRecord(p->ev[4], st));
+  s.rr_pending = true;
+  s.checked_at = s.cur;
+  return KF_OK;
+}
+
+// The filtered block C Q (Q = B[:, q0:q0+qn]) is in B[:, cur:cur+bk).
+int solve_after_filter(kf_problem* p, SolveState& s) {
+  hipStream_t st = p->st;
+  ++s.iters;
+  s.lf_steps += (int64_t)s.qn * (p->L - 1);
+  int kept = 0;
+  KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], s.pending, p->opt.full_reorth ? -1 : s.prev0,
+                    &s.full_passes));  // synchronises the stream
+  s.pending = 0;
+  if (s.rr_pending) {
+    KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
+    s.rr_pending = false;
   }
-  if (checked_at != cur) KF_TRY(check_now());
-  KF_HIP(hipEventSynchronize(ev[4]));
-  if (rr_pending) KF_TRY(elapsed(ev[3], ev[4], t_rr));
-  p->basis_cols = cur;
-  double t_ref = 0.0;
+  if (s.timed_filter) {
+    KF_TRY(elapsed_acc(p->ev[0], p->ev[1], s.t_lf));
+    KF_TRY(elapsed_acc(p->ev[1], p->ev[2], s.t_gs));
+  }
+  for (int j = 0; j < s.bk; ++j) {
+    // a stable step keeps |C x|_M <= sum|w_l| max|q_l| for |x|_M = 1
+    if (!std::isfinite(s.ref[(size_t)j]) || s.ref[(size_t)j] > 1e6 * std::max(s.wsum, 1e-300))
+      return fail(KF_EUNSTABLE, "kf_solve: time stepping diverged (tau too large for the spectrum?)");
+  }
+  kept = std::min(kept, s.m_max - s.cur);
+  if (kept == 0) {
+    s.breakdown = true;
+    s.done = true;
+    return KF_OK;
+  }
+  s.prev0 = s.q0;
+  s.q0 = s.cur;
+  s.qn = kept;
+  s.cur += kept;
+  s.pending = kept;
+  if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
+    KF_TRY(solve_check_now(p, s));
+    s.next_check = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));
+    if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) s.done = true;
+  }
+  (void)st;
+  return KF_OK;
+}
+
+int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
+  hipStream_t st = p->st;
+  const int32_t n = p->n;
+  const int b = s.b;
+  CheckOut& chk = s.chk;
+  if (s.checked_at != s.cur) KF_TRY(solve_check_now(p, s));
+  KF_HIP(hipEventSynchronize(p->ev[4]));
+  if (s.rr_pending) KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
+  s.rr_pending = false;
+  p->basis_cols = s.cur;
   CheckOut fin;
-  if (refine) {
-    KF_HIP(hipEventRecord(ev[3], st));
-    KF_TRY(refine_mixed(p, cur, tol, chk, p->opt.want_vectors != 0, fin));
-    KF_HIP(hipEventRecord(ev[4], st));
-    KF_HIP(hipEventSynchronize(ev[4]));
-    KF_TRY(elapsed(ev[3], ev[4], t_ref));
+  if (s.refine) {
+    KF_HIP(hipEventRecord(p->ev[3], st));
+    KF_TRY(refine_mixed(p, s.cur, s.tol, chk, p->opt.want_vectors != 0, fin));
+    KF_HIP(hipEventRecord(p->ev[4], st));
+    KF_HIP(hipEventSynchronize(p->ev[4]));
+    KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_ref));
   } else if (p->opt.want_vectors) {
-    KF_TRY(rr_check(p, cur, tol, fin, margin, true));
+    KF_TRY(rr_check(p, s.cur, s.tol, fin, s.margin, true));
   } else {
     fin = chk;
   }
-  if (breakdown)
+  const int target = s.target;
+  int status = KF_OK;
+  if (s.breakdown)
     status = KF_EBREAKDOWN;
   else if (target > 0 && distinct_count(fin.acc_theta, b) < target)
     status = KF_ENOTCONV;
-
+  const int iters = s.iters;
+  const int cur = s.cur;
+  const bool breakdown = s.breakdown;
+  const int64_t lf_steps = s.lf_steps;
+  const double t_lf = s.t_lf, t_gs = s.t_gs, t_rr = s.t_rr, t_ref = s.t_ref, t0 = s.t0;
+  const int full_passes = s.full_passes;
   kf_result* r = (kf_result*)std::calloc(1, sizeof(kf_result));
   if (!r) return fail(KF_ENOMEM, "kf_solve: result allocation");
   const int na = (int)fin.acc_theta.size();
@@ -1077,12 +1131,291 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   return KF_OK;
 }
 
+
+}  // namespace
+
+extern "C" {
+
+int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol, kf_result** out) {
+  if (!out) return fail(KF_EINVAL, "kf_solve: NULL argument");
+  *out = nullptr;
+  if (!p) return fail(KF_EINVAL, "kf_solve: NULL argument");
+  SolveState s;
+  KF_TRY(solve_begin(p, start, b, m_max, tol, s));
+  s.timed_filter = true;
+  const int64_t ldb = p->ldb;
+  while (solve_wants_filter(p, s)) {
+    KF_HIP(hipEventRecord(p->ev[0], p->st));
+    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.q0 * ldb, 1, ldb, s.qn, s.bk, p->B + (int64_t)s.cur * ldb, 1,
+                      ldb, s.bk, p->w));
+    KF_HIP(hipEventRecord(p->ev[1], p->st));
+    KF_TRY(solve_after_filter(p, s));
+  }
+  return solve_finish(p, s, out);
+}
+
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols) {
   if (!p || !out || !ncols || max_cols < 0) return fail(KF_EINVAL, "kf_copy_basis: bad arguments");
   const int k = std::min(max_cols, (int32_t)p->basis_cols);
   for (int c = 0; c < k; ++c)
     KF_HIP(hipMemcpy(out + (size_t)c * p->n, p->B + (int64_t)c * p->ldb, sizeof(double) * p->n, hipMemcpyDeviceToHost));
   *ncols = k;
+  return KF_OK;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+void free_batch(kf_batch* bt) {
+  if (!bt) return;
+  if (bt->st) (void)hipStreamSynchronize(bt->st);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  for (kf_problem* p : bt->probs) kf_destroy(p);
+  free_sell(bt->A);
+  dfree(bt->d_sp);
+  dfree(bt->d_tb);
+  dfree(bt->wtab);
+  free_step_buffers(bt->sb);
+  for (hipEvent_t e : bt->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (bt->st) (void)hipStreamDestroy(bt->st);
+  delete bt;
+}
+
+// Record the batched filter application (load + lmax-1 fused steps) for block
+// width bk once; replays read the per-problem tables from device memory.
+int ensure_batch_graph(kf_batch* bt, int bk) {
+  if (bt->exec && bt->graph_bk == bk) return KF_OK;
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->exec = nullptr;
+  bt->graph = nullptr;
+  // stacked time-stepping buffers (rows x bk)
+  if (bt->sb.cap < bk || bt->sb.vb != bt->A.val_bytes) {
+    free_step_buffers(bt->sb);
+    const size_t bytes = (size_t)bt->rows * bk * bt->A.val_bytes;
+    if (hipMalloc(&bt->sb.Y0, bytes) != hipSuccess || hipMalloc(&bt->sb.Y1, bytes) != hipSuccess ||
+        hipMalloc(&bt->sb.R, bytes) != hipSuccess)
+      return fail(KF_ENOMEM, "kf_batch: time-stepping buffers");
+    bt->sb.cap = bk;
+    bt->sb.vb = bt->A.val_bytes;
+  }
+  hipStream_t st = bt->st;
+  KF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = launch_load_batch(bt->A.val_bytes, bt->rows, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, bt->sb.Y1, st);
+  void* Y[2] = {bt->sb.Y0, bt->sb.Y1};
+  for (int l = 1; l < bt->lmax && rc == KF_OK; ++l)
+    rc = launch_leapfrog_batch(bt->A, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, l, Y[l & 1], Y[(l + 1) & 1],
+                               Y[(l + 1) & 1], bt->sb.R, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc != KF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(KF_EHIP, std::string("kf_batch: graph capture failed: ") + hipGetErrorString(e));
+  bt->graph = g;
+  KF_HIP(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+  bt->graph_bk = bk;
+  return KF_OK;
+}
+
+int run_batch_filter(kf_batch* bt, int bk) {
+  KF_TRY(ensure_batch_graph(bt, bk));
+  KF_HIP(hipMemcpyAsync(bt->d_tb, &bt->h_tb, sizeof(BatchTables), hipMemcpyHostToDevice, bt->st));
+  KF_HIP(hipGraphLaunch(bt->exec, bt->st));
+  return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* opt, kf_batch** out) {
+  if (!out) return fail(KF_EINVAL, "kf_create_batch: NULL output");
+  *out = nullptr;
+  if (P < 1 || P > kMaxBatch || !descs)
+    return fail(KF_EINVAL, "kf_create_batch: need 1 <= P <= " + std::to_string(kMaxBatch) + " descriptors");
+  kf_options o;
+  kf_default_options(&o);
+  if (opt) o = *opt;
+  kf_batch* bt = new (std::nothrow) kf_batch();
+  if (!bt) return fail(KF_ENOMEM, "kf_create_batch: host allocation");
+  bt->P = P;
+  int rc = KF_OK;
+  do {
+    if (hipStreamCreate(&bt->st) != hipSuccess) {
+      rc = fail(KF_EHIP, "kf_create_batch: stream creation failed");
+      break;
+    }
+    o.stream = bt->st;
+    // stacked operator: problem p occupies rows [row0_p, row0_p + n_p), padded to 64
+    std::vector<int32_t> rowptr{0}, col;
+    std::vector<double> val;
+    std::vector<int32_t> sp;
+    int64_t row0 = 0;
+    for (int32_t q = 0; q < P && rc == KF_OK; ++q) {
+      const kf_problem_desc& d = descs[q];
+      kf_options oq = o;
+      oq.target = d.target;
+      kf_problem* pq = nullptr;
+      rc = kf_create(&d.S, d.m_diag, d.omega_min, d.omega_max, d.tau, d.L, &oq, &pq);
+      if (rc) {
+        set_error("kf_create_batch: problem " + std::to_string(q) + ": " + kf_last_error());
+        break;
+      }
+      bt->probs.push_back(pq);
+      HostCsr h;
+      rc = fetch_csr(&d.S, d.m_diag, h);
+      if (rc) break;
+      const int32_t n = d.S.n;
+      const int64_t padded = ((int64_t)n + 63) / 64 * 64;
+      if (row0 + padded > INT32_MAX / 2) {
+        rc = fail(KF_EINVAL, "kf_create_batch: stacked problems exceed 2^30 rows");
+        break;
+      }
+      for (int32_t i = 0; i < n; ++i) {
+        const double sc = d.tau * d.tau / h.m[(size_t)i];
+        for (int32_t k = h.rowptr[(size_t)i]; k < h.rowptr[(size_t)i + 1]; ++k) {
+          col.push_back((int32_t)(row0 + h.col[(size_t)k]));
+          val.push_back(sc * h.val[(size_t)k]);
+        }
+        rowptr.push_back((int32_t)col.size());
+      }
+      for (int64_t i = n; i < padded; ++i) rowptr.push_back((int32_t)col.size());
+      for (int64_t s = 0; s < padded / 64; ++s) sp.push_back(q);
+      bt->h_tb.row0[q] = row0;
+      bt->h_tb.n[q] = n;
+      bt->h_tb.L[q] = d.L;
+      bt->lmax = std::max(bt->lmax, (int)d.L);
+      row0 += padded;
+    }
+    if (rc) break;
+    bt->rows = row0;
+    HostCsr hs;
+    hs.rowptr = std::move(rowptr);
+    hs.col = std::move(col);
+    hs.val = std::move(val);
+    DevCsr dc;
+    rc = upload_csr(hs, (int32_t)bt->rows, (int64_t)hs.col.size(), bt->st, dc);
+    if (rc) break;
+    const int vb = o.precision == KF_MIXED ? 4 : 8;
+    rc = build_sell((int32_t)bt->rows, (int64_t)hs.col.size(), dc.rowptr, dc.col, dc.val, nullptr, vb, o.index_bytes,
+                    bt->st, bt->A);
+    if (rc) break;
+    if ((rc = dalloc(&bt->d_sp, sp.size()))) break;
+    if ((rc = dalloc(&bt->d_tb, 1))) break;
+    std::vector<double> w64((size_t)P * bt->lmax, 0.0);
+    for (int32_t q = 0; q < P; ++q)
+      for (size_t l = 0; l < bt->probs[(size_t)q]->w.size(); ++l) w64[(size_t)q * bt->lmax + l] = bt->probs[(size_t)q]->w[l];
+    if (hipMalloc(&bt->wtab, w64.size() * vb) != hipSuccess) {
+      rc = fail(KF_ENOMEM, "kf_create_batch: weight table");
+      break;
+    }
+    if (vb == 8) {
+      if (hipMemcpy(bt->wtab, w64.data(), w64.size() * 8, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
+    } else {
+      std::vector<float> w32(w64.begin(), w64.end());
+      if (hipMemcpy(bt->wtab, w32.data(), w32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
+    }
+    if (rc == KF_OK && hipMemcpy(bt->d_sp, sp.data(), sizeof(int32_t) * sp.size(), hipMemcpyHostToDevice) != hipSuccess)
+      rc = KF_EHIP;
+    if (rc) {
+      set_error("kf_create_batch: table upload failed");
+      break;
+    }
+    for (hipEvent_t& e : bt->ev)
+      if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create_batch: event creation failed");
+  } while (false);
+  if (rc) {
+    free_batch(bt);
+    return rc;
+  }
+  *out = bt;
+  return KF_OK;
+}
+
+int kf_destroy_batch(kf_batch* bt) {
+  free_batch(bt);
+  return KF_OK;
+}
+
+int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y, int32_t b) {
+  if (!bt || !x || !y) return fail(KF_EINVAL, "kf_batch_apply_filter: NULL argument");
+  if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_batch_apply_filter: b must lie in [1, 16]");
+  for (int q = 0; q < bt->P; ++q) {
+    if (!x[q] || !y[q]) return fail(KF_EINVAL, "kf_batch_apply_filter: NULL block");
+    bt->h_tb.active[q] = 1;
+    bt->h_tb.src[q] = x[q];
+    bt->h_tb.lds[q] = bt->h_tb.n[q];
+    bt->h_tb.bsrc[q] = b;
+    bt->h_tb.dst[q] = y[q];
+    bt->h_tb.ld[q] = bt->h_tb.n[q];
+    bt->h_tb.bout[q] = b;
+  }
+  KF_TRY(run_batch_filter(bt, pow2ceil(b)));
+  KF_HIP(hipStreamSynchronize(bt->st));
+  return KF_OK;
+}
+
+int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t m_max, double tol,
+                   kf_result** results) {
+  if (!bt || !starts || !results) return fail(KF_EINVAL, "kf_solve_batch: NULL argument");
+  for (int q = 0; q < bt->P; ++q) results[q] = nullptr;
+  std::vector<SolveState> S((size_t)bt->P);
+  for (int q = 0; q < bt->P; ++q) {
+    int rc = solve_begin(bt->probs[(size_t)q], starts[q], b, m_max, tol, S[(size_t)q]);
+    if (rc) {
+      set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
+      return rc;
+    }
+  }
+  const int bk = pow2ceil(b);
+  double t_lf = 0.0;
+  while (true) {
+    bool any = false;
+    for (int q = 0; q < bt->P; ++q) {
+      kf_problem* p = bt->probs[(size_t)q];
+      SolveState& s = S[(size_t)q];
+      const bool act = solve_wants_filter(p, s);
+      bt->h_tb.active[q] = act ? 1 : 0;
+      if (!act) continue;
+      any = true;
+      bt->h_tb.src[q] = p->B + (int64_t)s.q0 * p->ldb;
+      bt->h_tb.lds[q] = p->ldb;
+      bt->h_tb.bsrc[q] = s.qn;
+      bt->h_tb.dst[q] = p->B + (int64_t)s.cur * p->ldb;
+      bt->h_tb.ld[q] = p->ldb;
+      bt->h_tb.bout[q] = bk;
+    }
+    if (!any) break;
+    KF_HIP(hipEventRecord(bt->ev[0], bt->st));
+    KF_TRY(run_batch_filter(bt, bk));
+    KF_HIP(hipEventRecord(bt->ev[1], bt->st));
+    for (int q = 0; q < bt->P; ++q) {
+      if (!bt->h_tb.active[q]) continue;
+      int rc = solve_after_filter(bt->probs[(size_t)q], S[(size_t)q]);
+      if (rc) {
+        set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
+        return rc;
+      }
+    }
+    KF_TRY(elapsed_acc(bt->ev[0], bt->ev[1], t_lf));
+  }
+  for (int q = 0; q < bt->P; ++q) {
+    S[(size_t)q].t_lf = t_lf;  // the batched stepping time, shared by all members
+    int rc = solve_finish(bt->probs[(size_t)q], S[(size_t)q], &results[q]);
+    if (rc) {
+      for (int r = 0; r < q; ++r) {
+        kf_result_free(results[r]);
+        results[r] = nullptr;
+      }
+      return rc;
+    }
+  }
   return KF_OK;
 }
 

@@ -70,6 +70,30 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
                     double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int xcd_remap,
                     hipStream_t st);
 
+// Per-problem tables of a batch (device memory, refreshed before every
+// batched filter application).  kMaxBatch bounds the number of problems.
+constexpr int kMaxBatch = 256;
+struct BatchTables {
+  int64_t row0[kMaxBatch];  // first stacked row of the problem (multiple of 64)
+  int32_t n[kMaxBatch];     // rows of the problem
+  int32_t L[kMaxBatch];     // rectangle-rule nodes
+  int32_t active[kMaxBatch];
+  int32_t bsrc[kMaxBatch];  // source columns (the rest of the block is zero)
+  int32_t bout[kMaxBatch];  // destination columns written
+  int64_t lds[kMaxBatch];   // source column stride
+  int64_t ld[kMaxBatch];    // destination column stride
+  const double* src[kMaxBatch];
+  double* dst[kMaxBatch];
+};
+
+// One batched fused step (step index ell >= 1) over the stacked operator.
+int launch_leapfrog_batch(const SellOp& A, int b, const int32_t* slice_problem, const BatchTables* tb,
+                          const void* wtab, int lmax, int ell, const void* cur, const void* prev, void* out, void* acc,
+                          hipStream_t st);
+// Batched load of the filter input into Y1 (and C = w0 I for L_p = 1).
+int launch_load_batch(int val_bytes, int64_t rows, int b, const int32_t* slice_problem, const BatchTables* tb,
+                      const void* wtab, int lmax, void* Y1, hipStream_t st);
+
 // dst (n x b row-major, stepping precision) = src[i*rs + j*cs] for j < bsrc, 0 beyond.
 int launch_load_block(int val_bytes, int32_t n, int b, int bsrc, const double* src, int64_t rs, int64_t cs,
                       void* dst, hipStream_t st);

@@ -170,6 +170,98 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
   }
 }
 
+// ------------------------------------------------------- batched leapfrog
+// Many independent problems stacked into one block-diagonal operator: every
+// problem owns whole 64-row slices (rows padded to a multiple of 64), slice s
+// belongs to problem sp[s].  One launch advances every problem whose step
+// count L_p - 1 reaches `ell`; first/last modes are decided per problem.  The
+// per-problem tables (active flag, column counts, source / destination basis
+// columns) live in device memory and are refreshed before each replay, so the
+// launch sequence can be captured once in a graph.
+template <typename T, typename IT, int B>
+__global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const int64_t* __restrict__ sptr,
+                                                        const T* __restrict__ val, const IT* __restrict__ idx,
+                                                        const int32_t* __restrict__ sp, const BatchTables* __restrict__ tb,
+                                                        const T* __restrict__ wtab, int lmax, int ell,
+                                                        const T* __restrict__ cur, const T* prev, T* out,
+                                                        T* __restrict__ acc) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int p = sp[slice];
+  const int Lp = tb->L[p];
+  if (!tb->active[p] || ell > Lp - 1) return;
+  const int row = slice * 64 + lane;
+  const int local = row - (int)tb->row0[p];
+  if (local >= tb->n[p]) return;
+  const bool first = ell == 1, last = ell == Lp - 1;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  const T* __restrict__ vp = val + base + lane;
+  const IT* __restrict__ ip = idx + base + lane;
+  T sum[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) sum[j] = (T)0;
+  for (int q = 0; q < width; ++q) {
+    const T a = __builtin_nontemporal_load(vp + (int64_t)q * 64);
+    const IT ci = __builtin_nontemporal_load(ip + (int64_t)q * 64);
+    const int c = relative ? row + (int)ci : (int)ci;
+    const Row<T, B> x = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) sum[j] = fma(a, x.v[j], sum[j]);
+  }
+  const T w0 = wtab[(int64_t)p * lmax], w = wtab[(int64_t)p * lmax + ell];
+  const Row<T, B> yc = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)row * B);
+  Row<T, B> yp = first ? yc : *reinterpret_cast<const Row<T, B>*>(prev + (int64_t)row * B);
+  Row<T, B> nx, r;
+#pragma unroll
+  for (int j = 0; j < B; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
+  if (!last) *reinterpret_cast<Row<T, B>*>(out + (int64_t)row * B) = nx;
+  if (first) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
+  } else {
+    r = *reinterpret_cast<const Row<T, B>*>(acc + (int64_t)row * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
+  }
+  if (last) {
+    double* __restrict__ dst = tb->dst[p];
+    const int64_t ld = tb->ld[p];
+    const int bout = tb->bout[p];
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (j < bout) dst[local + (int64_t)j * ld] = (double)r.v[j];
+  } else {
+    *reinterpret_cast<Row<T, B>*>(acc + (int64_t)row * B) = r;
+  }
+}
+
+// Batched start of a filter application: Y1 <- the problem's source columns
+// (zero beyond bsrc or for inactive problems); L_p = 1 problems get C = w0 I
+// written straight to their destination.
+template <typename T>
+__global__ __launch_bounds__(256) void k_load_batch(int64_t rows, int b, const int32_t* __restrict__ sp,
+                                                    const BatchTables* __restrict__ tb, const T* __restrict__ wtab,
+                                                    int lmax, T* __restrict__ Y1) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const int p = sp[row >> 6];
+  const int local = (int)(row - tb->row0[p]);
+  const bool on = tb->active[p] && local < tb->n[p];
+  const double* __restrict__ src = tb->src[p];
+  const int64_t lds = tb->lds[p];
+  const int bsrc = tb->bsrc[p];
+  for (int j = 0; j < b; ++j) Y1[row * b + j] = (on && j < bsrc) ? (T)src[local + (int64_t)j * lds] : (T)0;
+  if (on && tb->L[p] == 1) {
+    const double w0 = (double)wtab[(int64_t)p * lmax];
+    double* __restrict__ dst = tb->dst[p];
+    const int64_t ld = tb->ld[p];
+    for (int j = 0; j < tb->bout[p]; ++j) dst[local + (int64_t)j * ld] = j < bsrc ? w0 * src[local + (int64_t)j * lds] : 0.0;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_load_block(int32_t n, int b, int bsrc, const double* __restrict__ src,
                                                     int64_t rs, int64_t cs, T* __restrict__ dst) {
@@ -596,6 +688,71 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
   if (A.idx_bytes == 2)
     return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
   return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+}
+
+namespace {
+template <typename T, typename IT>
+int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax, int ell,
+                 const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
+  const int grid = ceil_div64(A.nslices, 4);
+  const T* v = static_cast<const T*>(A.val);
+  const IT* ix = static_cast<const IT*>(A.idx);
+  const T* w = static_cast<const T*>(wtab);
+  const T* c = static_cast<const T*>(cur);
+  const T* pr = static_cast<const T*>(prev);
+  T* o = static_cast<T*>(out);
+  T* a = static_cast<T*>(acc);
+  switch (b) {
+    case 1:
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 1>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 2>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 4>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 8>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 16>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix,
+                         sp, tb, w, lmax, ell, c, pr, o, a);
+      break;
+    default:
+      set_error("batched leapfrog: block width must be 1, 2, 4, 8 or 16");
+      return KF_EINVAL;
+  }
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+}  // namespace
+
+int launch_leapfrog_batch(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax,
+                          int ell, const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
+  if (A.val_bytes == 8) {
+    if (A.idx_bytes == 2) return launch_lfb_t<double, int16_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+    return launch_lfb_t<double, int32_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+  }
+  if (A.idx_bytes == 2) return launch_lfb_t<float, int16_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+  return launch_lfb_t<float, int32_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+}
+
+int launch_load_batch(int val_bytes, int64_t rows, int b, const int32_t* sp, const BatchTables* tb, const void* wtab,
+                      int lmax, void* Y1, hipStream_t st) {
+  const int grid = ceil_div64(rows, 256);
+  if (val_bytes == 8)
+    hipLaunchKernelGGL(k_load_batch<double>, dim3(grid), dim3(256), 0, st, rows, b, sp, tb, (const double*)wtab, lmax,
+                       (double*)Y1);
+  else
+    hipLaunchKernelGGL(k_load_batch<float>, dim3(grid), dim3(256), 0, st, rows, b, sp, tb, (const float*)wtab, lmax,
+                       (float*)Y1);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
 }
 
 int launch_load_block(int val_bytes, int32_t n, int b, int bsrc, const double* src, int64_t rs, int64_t cs,

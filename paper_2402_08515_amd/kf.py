@@ -84,6 +84,18 @@ class ResultT(C.Structure):
     ]
 
 
+class ProblemDescT(C.Structure):
+    _fields_ = [
+        ("S", CsrT),
+        ("m_diag", C.c_void_p),
+        ("omega_min", C.c_double),
+        ("omega_max", C.c_double),
+        ("tau", C.c_double),
+        ("L", C.c_int32),
+        ("target", C.c_int32),
+    ]
+
+
 _lib = None
 
 _SIGNATURES = {
@@ -106,6 +118,10 @@ _SIGNATURES = {
     "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "kf_create_batch": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(OptionsT), C.POINTER(C.c_void_p)]),
+    "kf_destroy_batch": (C.c_int, [C.c_void_p]),
+    "kf_batch_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "kf_solve_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_void_p]),
 }
 
 
@@ -194,6 +210,110 @@ class SolveResult:
     full_passes: int
 
 
+def _take_result(res, n: int) -> SolveResult:
+    """Copy a library-owned kf_result into Python objects and free it."""
+    try:
+        r = res.contents
+        na = r.n_pairs
+        vec = None
+        if r.vectors:
+            vec = np.ctypeslib.as_array(r.vectors, shape=(na, n)).T.copy()
+        return SolveResult(
+            omega2=np.ctypeslib.as_array(r.omega2, shape=(na,)).copy() if na else np.zeros(0),
+            omega=np.ctypeslib.as_array(r.omega, shape=(na,)).copy() if na else np.zeros(0),
+            residual=np.ctypeslib.as_array(r.residual, shape=(na,)).copy() if na else np.zeros(0),
+            vectors=vec,
+            ritz=np.ctypeslib.as_array(r.ritz, shape=(r.n_ritz,)).copy() if r.n_ritz else np.zeros(0),
+            krylov_steps=r.krylov_steps,
+            basis_size=r.basis_size,
+            breakdown=bool(r.breakdown),
+            status=r.status,
+            leapfrog_vector_steps=r.leapfrog_vector_steps,
+            t_total=r.t_total,
+            t_leapfrog=r.t_leapfrog,
+            t_gs=r.t_gs,
+            t_rr=r.t_rr,
+            t_refine=r.t_refine,
+            orth_error=r.orth_error,
+            full_passes=r.full_passes,
+        )
+    finally:
+        lib().kf_result_free(res)
+
+
+def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
+             drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True):
+    opt = OptionsT()
+    lib().kf_default_options(C.byref(opt))
+    opt.precision = _PREC[precision]
+    opt.check_every = check_every
+    opt.check_growth = check_growth
+    opt.full_reorth = int(full_reorth)
+    opt.target = target
+    opt.max_iters = max_iters
+    opt.drop_tol = drop_tol
+    opt.refine = int(refine)
+    opt.want_vectors = int(want_vectors)
+    opt.index_bytes = index_bytes
+    opt.xcd_remap = int(xcd_remap)
+    opt.stream = _stream_handle()
+    return opt
+
+
+class Batch:
+    """Handle of ``kf_create_batch``: independent problems whose time loops
+    advance in one batched launch.  ``members`` is a list of tuples
+    (S, m, omega_min, omega_max, tau, L, target)."""
+
+    def __init__(self, members, **options):
+        L_ = lib()
+        self._h = C.c_void_p()
+        self._keep = []
+        descs = (ProblemDescT * len(members))()
+        self.n = []
+        for i, (S, m, omin, omax, tau, L, target) in enumerate(members):
+            c, keep = _host_csr(S)
+            mm = np.ascontiguousarray(m, dtype=np.float64)
+            self._keep.append((keep, mm))
+            descs[i] = ProblemDescT(c, _ptr(mm), float(omin), float(omax), float(tau), int(L), int(target))
+            self.n.append(S.shape[0])
+        opt = _options(**options)
+        _check(L_.kf_create_batch(len(members), C.cast(descs, C.c_void_p), C.byref(opt), C.byref(self._h)))
+        self._keep = None
+        self.P = len(members)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kf_destroy_batch(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_filter(self, xs):
+        """ys[p] = C_p xs[p] for device blocks xs[p] of shape (n_p, b),
+        float64; one batched application."""
+        b = int(xs[0].shape[1])
+        cols = [x.t().contiguous() for x in xs]  # column-major n x b
+        outs = [torch.empty_like(c) for c in cols]
+        xp = (C.c_void_p * self.P)(*[c.data_ptr() for c in cols])
+        yp = (C.c_void_p * self.P)(*[o.data_ptr() for o in outs])
+        _check(lib().kf_batch_apply_filter(self._h, C.cast(xp, C.c_void_p), C.cast(yp, C.c_void_p), b))
+        return [o.t().contiguous() for o in outs]
+
+    def solve(self, starts, m_max: int, tol: float):
+        arrs = [np.ascontiguousarray(v[:, None] if v.ndim == 1 else v, dtype=np.float64) for v in starts]
+        b = arrs[0].shape[1]
+        sp = (C.c_void_p * self.P)(*[a.ctypes.data for a in arrs])
+        res = (C.POINTER(ResultT) * self.P)()
+        _check(lib().kf_solve_batch(self._h, C.cast(sp, C.c_void_p), int(b), int(m_max), float(tol),
+                                    C.cast(res, C.c_void_p)))
+        return [_take_result(res[i], self.n[i]) for i in range(self.P)]
+
+
 class Problem:
     """Handle of ``kf_create``: pencil, interval, tau, L and options."""
 
@@ -266,34 +386,7 @@ class Problem:
             V0 = V0[:, None]
         res = C.POINTER(ResultT)()
         _check(lib().kf_solve(self._h, _ptr(V0), int(V0.shape[1]), int(m_max), float(tol), C.byref(res)))
-        try:
-            r = res.contents
-            na = r.n_pairs
-            vec = None
-            if r.vectors:
-                vec = np.ctypeslib.as_array(r.vectors, shape=(na, self.n)).T.copy()
-            out = SolveResult(
-                omega2=np.ctypeslib.as_array(r.omega2, shape=(na,)).copy() if na else np.zeros(0),
-                omega=np.ctypeslib.as_array(r.omega, shape=(na,)).copy() if na else np.zeros(0),
-                residual=np.ctypeslib.as_array(r.residual, shape=(na,)).copy() if na else np.zeros(0),
-                vectors=vec,
-                ritz=np.ctypeslib.as_array(r.ritz, shape=(r.n_ritz,)).copy() if r.n_ritz else np.zeros(0),
-                krylov_steps=r.krylov_steps,
-                basis_size=r.basis_size,
-                breakdown=bool(r.breakdown),
-                status=r.status,
-                leapfrog_vector_steps=r.leapfrog_vector_steps,
-                t_total=r.t_total,
-                t_leapfrog=r.t_leapfrog,
-                t_gs=r.t_gs,
-                t_rr=r.t_rr,
-                t_refine=r.t_refine,
-                orth_error=r.orth_error,
-                full_passes=r.full_passes,
-            )
-        finally:
-            lib().kf_result_free(res)
-        return out
+        return _take_result(res, self.n)
 
     def basis(self, max_cols: int) -> np.ndarray:
         out = np.empty((max_cols, self.n))

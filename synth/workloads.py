@@ -127,6 +127,16 @@ def batch64_descriptors(count: int = 64, seed: int = 3):
     return out
 
 
+def batch64_problems(count: int = 64, seed: int = 3):
+    """The uneven batch as Problem objects (block width 4, float32 stepping);
+    start blocks use seed 3 * 1000 + index."""
+    out = []
+    for i, (dim, n, omin, omax) in enumerate(batch64_descriptors(count, seed)):
+        P = _grid(f"batch64[{i}]", dim, n, omin, omax, seed=seed * 1000 + i, block=4, precision="mixed")
+        out.append(P)
+    return out
+
+
 def grid3d_128_intervals(count: int = 32, seed: int = 4):
     """Evaluation intervals of the learned-weight comparison: stream 1 of
     seed 4 (stream 0 is reserved for training samples)."""

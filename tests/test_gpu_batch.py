@@ -1,0 +1,97 @@
+"""Batches of uneven problems: the batched, graph-captured filter
+application equals the oracle's operator C of each member, and a batched
+solve returns what each member's own solve returns."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import distinct_target, grid_spectrum, power_start, start_block
+from synth.grids import grid_problem, jittered_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _kf():
+    from paper_2402_08515_amd import kf
+
+    return kf
+
+
+def _members(spec):
+    out = []
+    for dim, n, ofrac_lo, ofrac_hi, L in spec:
+        S, m, h = grid_problem(dim, n)
+        lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], n), 30)
+        tau, Lr = oracle.time_step_rule(lam, ofrac_lo * math.sqrt(lam))
+        out.append((S, m, ofrac_lo * math.sqrt(lam), ofrac_hi * math.sqrt(lam), tau, L or Lr))
+    return out
+
+
+SPEC = [(2, 20, 0.3, 0.5, 1), (2, 33, 0.2, 0.3, 2), (3, 9, 0.3, 0.6, 5), (2, 41, 0.1, 0.2, 0), (3, 12, 0.25, 0.4, 0)]
+
+
+@pytest.mark.parametrize("precision,b", [("fp64", 1), ("fp64", 3), ("mixed", 4)])
+def test_batched_filter_matches_oracle(precision, b):
+    import torch
+
+    kf = _kf()
+    mem = _members(SPEC)
+    print(f"case batch apply_filter {precision} b={b} L={[x[5] for x in mem]}", flush=True)
+    bt = kf.Batch([(S, m, lo, hi, tau, L, 0) for S, m, lo, hi, tau, L in mem], precision=precision)
+    xs = [start_block(S.shape[0], b, 100 + i) for i, (S, *_rest) in enumerate(mem)]
+    ys = bt.apply_filter([torch.from_numpy(x).cuda() for x in xs])
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    for (S, m, lo, hi, tau, L), x, y in zip(mem, xs, ys):
+        ref = oracle.apply_filter(S, m, tau, oracle.discrete_weights(lo, hi, tau, L), x)
+        err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= tol, (L, err)
+
+
+def test_batched_solve_equals_member_solves():
+    kf = _kf()
+    spec = [(2, 24, 15.0, 24.0), (2, 31, 12.0, 20.0), (3, 10, 9.0, 14.0), (2, 18, 30.0, 40.0)]
+    members, starts, targets = [], [], []
+    b = 2
+    for i, (dim, n, lo, hi) in enumerate(spec):
+        S, m, h = grid_problem(dim, n)
+        lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], i), 30)
+        tau, L = oracle.time_step_rule(lam, lo)
+        tgt = distinct_target(grid_spectrum(dim, n), lo, hi, b)[0]
+        members.append((S, m, lo, hi, tau, L, tgt))
+        starts.append(start_block(S.shape[0], b, 50 + i))
+        targets.append(tgt)
+    print(f"case batch solve targets={targets}", flush=True)
+    bt = kf.Batch(members, check_every=1)
+    got = bt.solve(starts, m_max=200, tol=1e-9)
+    for (S, m, lo, hi, tau, L, tgt), V0, g, (dim, n, _, _) in zip(members, starts, got, spec):
+        single = kf.Problem(S, m, lo, hi, tau, L, target=tgt).solve(V0, m_max=200, tol=1e-9)
+        assert g.omega2.size == single.omega2.size == tgt
+        np.testing.assert_allclose(g.omega2, single.omega2, rtol=1e-12)
+        tg, vals, mult = distinct_target(grid_spectrum(dim, n), lo, hi, b)
+        np.testing.assert_allclose(g.omega2, np.repeat(vals, np.minimum(mult, b)), rtol=1e-10)
+        assert g.krylov_steps == single.krylov_steps
+
+
+def test_batched_solve_mixed_on_jittered_members():
+    kf = _kf()
+    members, starts, refs = [], [], []
+    for i, (n, lo, hi) in enumerate([(14, 6.0, 9.0), (10, 5.0, 8.0), (12, 7.0, 10.0)]):
+        S, m = jittered_problem(3, n, 0.05, seed=10 + i)
+        lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], i), 30)
+        tau, L = oracle.time_step_rule(lam, lo)
+        V0 = start_block(S.shape[0], 2, 60 + i)
+        ref = oracle.krylov_solve(S, m, tau, oracle.discrete_weights(lo, hi, tau, L), V0, lo, hi, tol=1e-10,
+                                  m_max=240, check_every=10)
+        members.append((S, m, lo, hi, tau, L, int(ref.omega2.size)))
+        starts.append(V0)
+        refs.append(ref)
+    bt = kf.Batch(members, precision="mixed", check_every=2)
+    got = bt.solve(starts, m_max=240, tol=1e-6)
+    for g, ref in zip(got, refs):
+        assert g.residual.max() <= 1e-6
+        err = np.array([np.min(np.abs(g.omega2 - v)) / v for v in ref.omega2])
+        print("member per-pair relative error vs FP64 oracle:", np.array2string(err, precision=2))
+        assert err.max() <= 1e-6
