@@ -52,7 +52,7 @@ def test_batched_filter_matches_oracle(precision, b):
 
 def test_batched_solve_equals_member_solves():
     kf = _kf()
-    spec = [(2, 24, 15.0, 24.0), (2, 31, 12.0, 20.0), (3, 10, 9.0, 14.0), (2, 18, 30.0, 40.0)]
+    spec = [(2, 24, 15.0, 24.0), (2, 31, 12.0, 20.0), (3, 10, 9.0, 14.0), (2, 40, 25.0, 30.0)]
     members, starts, targets = [], [], []
     b = 2
     for i, (dim, n, lo, hi) in enumerate(spec):
