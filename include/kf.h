@@ -230,6 +230,48 @@ int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y
 int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t m_max, double tol,
                    kf_result** results);
 
+/* ---- learned filter weights -------------------------------------------------
+ * Section 2.2 leaves the weight function free and names the goal |beta|
+ * large on the sought omega and small elsewhere.  A small network maps the
+ * normalised data (a = tau*omega_min, c = tau*omega_max,
+ * x_max = tau*sqrt(lambda_max)/2, L) to the L coefficients as a correction of
+ * the Fourier weights of eq. weightf; it is trained to minimise the quadratic
+ * leakage of the filter of Lemma 2.3 on a grid of x = tau*omega/2 (band
+ * [a/2, c/2] towards 1, outside the band widened by pi/(2L) towards 0).
+ * Network products run on the matrix cores in bfloat16 with float32
+ * accumulation.  Parameters are float32, count kf_mlp_param_count(), layout
+ * W1[64x128] b1[128] W2[128x128] b2 W3[128x128] b3 W4[128x512] b4[512]
+ * (row-major, input x output). */
+typedef struct kf_mlp kf_mlp; /* opaque */
+
+int32_t kf_mlp_param_count(void);
+
+/* Create a network from host parameters (copied). */
+int kf_mlp_create(const float* params, kf_mlp** out);
+int kf_mlp_destroy(kf_mlp* net);
+/* Copy the current parameters to host out[kf_mlp_param_count()]. */
+int kf_mlp_get_params(const kf_mlp* net, float* out);
+
+/* Mean loss over n samples (host, n x 4 rows omega_min, omega_max, tau,
+ * lambda_max; n a multiple of 64) and, if grad != NULL, its gradient
+ * (host float32 array of the parameter count). */
+int kf_mlp_loss_grad(kf_mlp* net, const double* samples, int32_t n, double* loss, float* grad);
+
+/* Adam training (beta1 0.9, beta2 0.999, learning rate lr decayed by a cosine
+ * to lr/100) for `epochs` passes over n host samples in the order
+ * order[epochs x n] (a permutation per epoch, drawn by the caller), batches
+ * of `batch` (multiple of 64, <= n).  epoch_loss[epochs] (optional) receives
+ * the mean training loss of each epoch. */
+int kf_mlp_train(kf_mlp* net, const double* samples, int32_t n, const int32_t* order, int32_t epochs,
+                 int32_t batch, double lr, double* epoch_loss);
+
+/* Filter coefficients for one problem: the network's weights when their loss
+ * is below that of the Fourier weights (*used_learned = 1), else the Fourier
+ * weights (*used_learned = 0; also when L > 512).  w_out[L] host; j_learned and
+ * j_fourier (optional) receive both losses. */
+int kf_weights_from_mlp(kf_mlp* net, double omega_min, double omega_max, double tau, double lambda_max, int32_t L,
+                        double* w_out, int32_t* used_learned, double* j_learned, double* j_fourier);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,8 @@ through products with tau:
   a = tau*omega_min, c = tau*omega_max, for l < L.
 
 Network: features f = [a/pi, c/pi, x_max, L/512] (x_max = tau*sqrt(lambda_max)/2),
-three GELU layers of width 128 and a linear output of 512 values;
+three GELU layers of width 128 and a linear output of 512 values (features
+padded with zeros to 64 inputs);
 w = w_Fourier + s * out (masked to l < L), s = 0.01, so the untrained
 network (output layer at zero) reproduces the Fourier weights.
 
@@ -38,7 +39,7 @@ XMAX_GRID = 0.95
 OUT_SCALE = 0.01
 GAMMA = 1.0
 NFEAT = 4
-SHAPES = [(16, HIDDEN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (HIDDEN, LMAX), (LMAX,)]
+SHAPES = [(64, HIDDEN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (HIDDEN, LMAX), (LMAX,)]
 
 
 def n_params() -> int:
@@ -74,7 +75,7 @@ def sample_params(omega_min, omega_max, tau, lambda_max):
 
 def features(omega_min, omega_max, tau, lambda_max) -> np.ndarray:
     a, c, L, xm = sample_params(omega_min, omega_max, tau, lambda_max)
-    f = np.zeros(16)
+    f = np.zeros(64)
     f[:NFEAT] = [a / math.pi, c / math.pi, xm, L / LMAX]
     return f
 

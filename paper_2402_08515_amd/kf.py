@@ -122,6 +122,16 @@ _SIGNATURES = {
     "kf_destroy_batch": (C.c_int, [C.c_void_p]),
     "kf_batch_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_solve_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_void_p]),
+    "kf_mlp_param_count": (C.c_int32, []),
+    "kf_mlp_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "kf_mlp_destroy": (C.c_int, [C.c_void_p]),
+    "kf_mlp_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kf_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
+    "kf_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_double,
+                               C.c_void_p]),
+    "kf_weights_from_mlp": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                      C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
 }
 
 
@@ -393,3 +403,59 @@ class Problem:
         nc = C.c_int32()
         _check(lib().kf_copy_basis(self._h, _ptr(out), int(max_cols), C.byref(nc)))
         return out[: nc.value].T.copy()
+
+
+class Mlp:
+    """Handle of ``kf_mlp_create``: the learned filter-weight network
+    (parameters float32, layout W1[64x128] b1 W2 b2 W3 b3 W4[128x512] b4)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != lib().kf_mlp_param_count():
+            raise ValueError("wrong parameter count")
+        self._h = C.c_void_p()
+        _check(lib().kf_mlp_create(_ptr(p), C.byref(self._h)))
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().kf_mlp_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kf_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.param_count(), dtype=np.float32)
+        _check(lib().kf_mlp_get_params(self._h, _ptr(out)))
+        return out
+
+    def loss_grad(self, samples, want_grad=True):
+        s = np.ascontiguousarray(samples, dtype=np.float64)
+        loss = C.c_double()
+        g = np.empty(self.param_count(), dtype=np.float32) if want_grad else None
+        _check(lib().kf_mlp_loss_grad(self._h, _ptr(s), int(s.shape[0]), C.byref(loss), _ptr(g) if want_grad else None))
+        return loss.value, g
+
+    def train(self, samples, order, epochs: int, batch: int, lr: float) -> np.ndarray:
+        s = np.ascontiguousarray(samples, dtype=np.float64)
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        hist = np.zeros(epochs)
+        _check(lib().kf_mlp_train(self._h, _ptr(s), int(s.shape[0]), _ptr(o), int(epochs), int(batch), float(lr),
+                                  _ptr(hist)))
+        return hist
+
+    def weights(self, omega_min, omega_max, tau, lambda_max, L):
+        w = np.empty(int(L))
+        used = C.c_int32()
+        jl = C.c_double()
+        jf = C.c_double()
+        _check(lib().kf_weights_from_mlp(self._h, omega_min, omega_max, tau, lambda_max, int(L), _ptr(w),
+                                         C.byref(used), C.byref(jl), C.byref(jf)))
+        return w, bool(used.value), jl.value, jf.value

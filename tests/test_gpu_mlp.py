@@ -1,0 +1,73 @@
+"""The learned filter network on the GPU against the FP64 reference
+(oracle.mlp): loss and gradient (bfloat16 matrix products, so compared at
+bfloat16 accuracy), the Fourier-weight fallback, and training that lands
+between the Fourier weights and the per-sample least-squares optimum."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from synth.workloads import filter_samples
+
+pytestmark = pytest.mark.gpu
+
+
+def _kf():
+    from paper_2402_08515_amd import kf
+
+    return kf
+
+
+def test_untrained_network_loss_equals_fourier_loss():
+    kf = _kf()
+    s = filter_samples(64, stream=1)
+    theta = mlp.init_params(0)
+    net = kf.Mlp(theta.astype(np.float32))
+    loss, _ = net.loss_grad(s, want_grad=False)
+    ref = np.mean([mlp.loss_of_weights(r, mlp.fourier_weights_normalised(*mlp.sample_params(*r)[:3])) for r in s])
+    assert loss == pytest.approx(ref, rel=1e-4)
+
+
+def test_gradient_matches_fp64_reference():
+    kf = _kf()
+    s = filter_samples(128, stream=0)
+    rng = np.random.default_rng(3)
+    theta = mlp.init_params(1)
+    theta[-(128 * 512 + 512):] = 0.3 * rng.standard_normal(128 * 512 + 512)  # non-zero output layer
+    net = kf.Mlp(theta.astype(np.float32))
+    loss, g = net.loss_grad(s)
+    ref_loss, ref_g = mlp.loss_and_grad(theta.astype(np.float32).astype(np.float64), s)
+    print(f"loss gpu {loss:.6e} fp64 {ref_loss:.6e}")
+    assert loss == pytest.approx(ref_loss, rel=2e-2)
+    cos = float(g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
+    rel = float(np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g))
+    print(f"gradient cosine {cos:.5f} relative error {rel:.3e}")
+    assert cos >= 0.995 and rel <= 5e-2
+
+
+def test_training_beats_fourier_and_the_judge_keeps_the_better_weights():
+    kf = _kf()
+    train = filter_samples(8192, stream=0)
+    valid = filter_samples(16, stream=1)
+    net = kf.Mlp(mlp.init_params(4).astype(np.float32))
+    rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
+    epochs = 6
+    order = np.concatenate([rng.permutation(len(train)) for _ in range(epochs)]).astype(np.int32)
+    hist = net.train(train, order, epochs, 256, 1e-3)
+    print("epoch losses", np.array2string(hist, precision=4))
+    assert hist[-1] < hist[0]
+    better = 0
+    for r in valid:
+        a, c, L, xm = mlp.sample_params(*r)
+        w, used, jl, jf = net.weights(*r, L)
+        jF = mlp.loss_of_weights(r, mlp.fourier_weights_normalised(a, c, L))
+        wt = np.zeros(mlp.LMAX)
+        wt[:L] = w
+        j = mlp.loss_of_weights(r, wt)
+        jT = mlp.loss_of_weights(r, mlp.teacher(r))
+        # the judge never returns weights worse than the Fourier ones
+        assert j <= jF * (1 + 1e-3)
+        assert jT <= j * (1 + 1e-6)
+        better += used
+    print(f"learned weights used for {better}/16 validation problems")
+    assert better >= 8

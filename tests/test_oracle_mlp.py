@@ -30,7 +30,7 @@ def test_backpropagation_matches_finite_differences():
     theta = mlp.init_params(2) + 0.05 * rng.standard_normal(mlp.n_params())
     f, g = mlp.loss_and_grad(theta, s)
     idx = rng.choice(mlp.n_params(), 40, replace=False)
-    idx = np.concatenate([idx, [mlp.n_params() - 1, 0, 16 * 128 + 5]])
+    idx = np.concatenate([idx, [mlp.n_params() - 1, 0, 64 * 128 + 5]])
     for i in idx:
         e = np.zeros_like(theta)
         h = 1e-6 * max(1.0, abs(theta[i]))
