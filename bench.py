@@ -154,6 +154,83 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_learned(args):
+    """Learned filter weights: the network is trained on the GPU (50,000
+    samples of (omega_min, omega_max, tau, lambda_max) from seed 4 stream 0),
+    then intervals from the evaluation law (seed 4 stream 1) on the 3D cube
+    with 64 cells per axis are solved to all their eigenpairs with the
+    Fourier weights and with the weights the network proposes (the judge
+    falls back to the Fourier weights when they leak less)."""
+    import numpy as np
+    import torch
+
+    from oracle import mlp as mlp_init  # initial parameters only (the seeded draw), no arithmetic of the path
+    from paper_2402_08515_amd import kf
+    from synth import distinct_target, grid_spectrum, power_start, start_block
+    from synth.grids import grid_problem
+    from synth.workloads import filter_samples, grid3d_128_intervals
+
+    train = filter_samples(args.mlp_samples, stream=0)
+    net = kf.Mlp(mlp_init.init_params(4).astype(np.float32))
+    rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
+    order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
+    t0 = time.perf_counter()
+    hist = net.train(train, order, args.mlp_epochs, 256, 1e-3)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] trained {args.mlp_epochs} epochs on {len(train)} samples in {t_train:.2f}s, "
+          f"loss {hist[0]:.4f} -> {hist[-1]:.4f}", file=sys.stderr, flush=True)
+    n = args.learned_n
+    S, m, h = grid_problem(3, n)
+    lam = kf.estimate_lambda_max(S, m, 30, power_start(S.shape[0], 4))
+    spec = grid_spectrum(3, n)
+    rows = []
+    for (lo, hi) in grid3d_128_intervals(32):
+        tgt = distinct_target(spec, lo, hi, 1)[0]
+        if tgt == 0 or tgt > args.learned_max_target:
+            continue
+        tau, L = kf.time_step_rule(lam, lo)
+        V0 = start_block(S.shape[0], 1, 4)
+        rec = {"interval": [lo, hi], "target": tgt, "L": L}
+        for kind in ("fourier", "learned"):
+            prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, check_growth=0.1)
+            if kind == "learned":
+                w, used, jl, jf = net.weights(lo, hi, tau, lam, L)
+                rec.update(used_learned=used, j_learned=jl, j_fourier=jf)
+                if not used:
+                    rec["learned"] = rec["fourier"]
+                    continue
+                prob.set_weights(w)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = prob.solve(V0, m_max=1024, tol=args.tol)
+            dt = time.perf_counter() - t1
+            rec[kind] = {"pairs": int(r.omega2.size), "krylov_steps": r.krylov_steps, "seconds": dt}
+        rows.append(rec)
+        print(f"[bench] [{lo:.2f}, {hi:.2f}] target {tgt}: fourier {rec['fourier']} learned {rec['learned']} "
+              f"used={rec['used_learned']}", file=sys.stderr, flush=True)
+        if len(rows) >= args.learned_count:
+            break
+    tf = sum(r["fourier"]["seconds"] for r in rows)
+    tl = sum(r["learned"]["seconds"] for r in rows)
+    kf_ = sum(r["fourier"]["krylov_steps"] for r in rows)
+    kl = sum(r["learned"]["krylov_steps"] for r in rows)
+    out = {
+        "metric": METRIC,
+        "value": None,
+        "unit": "s",
+        "n_gpus": 1,
+        "config": {"workload": f"grid3d_{n} learned-vs-Fourier", "intervals": len(rows), "tol": args.tol},
+        "train_seconds": t_train,
+        "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+        "fourier_seconds": tf,
+        "learned_seconds": tl,
+        "fourier_krylov_steps": kf_,
+        "learned_krylov_steps": kl,
+        "intervals": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +244,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--mlp-samples", type=int, default=50000)
+    ap.add_argument("--mlp-epochs", type=int, default=8)
+    ap.add_argument("--learned-n", type=int, default=64)
+    ap.add_argument("--learned-count", type=int, default=8)
+    ap.add_argument("--learned-max-target", type=int, default=150)
     ap.add_argument("--batch-iters", type=int, default=24,
                     help="Krylov iterations per member in the batch benchmark (the full targets need thousands)")
     ap.add_argument("--no-sequential", action="store_true")
@@ -180,6 +262,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
 
     import numpy as np

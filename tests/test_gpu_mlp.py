@@ -71,3 +71,35 @@ def test_training_beats_fourier_and_the_judge_keeps_the_better_weights():
         better += used
     print(f"learned weights used for {better}/16 validation problems")
     assert better >= 8
+
+
+def test_solve_with_learned_weights_finds_every_pair():
+    """End to end: weights from the trained network drive a full solve on the
+    3D cube (64 cells per axis); the iteration counts of both weight choices
+    are printed (leakage-trained weights are not faster here, see the design
+    notes)."""
+    kf = _kf()
+    from synth import distinct_target, grid_spectrum, power_start, start_block
+    from synth.grids import grid_problem
+
+    train = filter_samples(8192, stream=0)
+    net = kf.Mlp(mlp.init_params(4).astype(np.float32))
+    rng = np.random.default_rng(7)
+    net.train(train, np.concatenate([rng.permutation(8192) for _ in range(4)]).astype(np.int32), 4, 256, 1e-3)
+    S, m, h = grid_problem(3, 64)
+    lam = kf.estimate_lambda_max(S, m, 30, power_start(S.shape[0], 4))
+    lo, hi = 19.36, 25.11
+    tau, L = kf.time_step_rule(lam, lo)
+    tgt, vals, mult = distinct_target(grid_spectrum(3, 64), lo, hi, 1)
+    w, used, jl, jf = net.weights(lo, hi, tau, lam, L)
+    V0 = start_block(S.shape[0], 1, 4)
+    steps = {}
+    for name, ww in (("fourier", None), ("network", w)):
+        prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2)
+        if ww is not None:
+            prob.set_weights(ww)
+        r = prob.solve(V0, m_max=600, tol=1e-6)
+        assert r.omega2.size == tgt
+        np.testing.assert_allclose(r.omega2, vals, rtol=1e-10)
+        steps[name] = r.krylov_steps
+    print(f"judge used learned={used} (J {jl:.3e} vs {jf:.3e}); Krylov steps {steps}")
