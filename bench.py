@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--check-growth", type=float, default=0.15)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default fused-step variant instead of timing all of them at set-up")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mlp-samples", type=int, default=50000)
     ap.add_argument("--mlp-epochs", type=int, default=8)
@@ -282,7 +284,9 @@ def main():
     tau, L = kf.time_step_rule(lam, P.omega_min)
     print(f"[bench] lambda_est={lam:.6g} tau={tau:.6g} L={L}", file=sys.stderr, flush=True)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
-                      check_every=args.check_every, check_growth=args.check_growth)
+                      check_every=args.check_every, check_growth=args.check_growth, autotune=not args.no_autotune)
+    tuning = prob.tuning()
+    print(f"[bench] fused-step variant {tuning}", file=sys.stderr, flush=True)
     V0 = start_block(P.n, P.block, P.seed)
 
     if args.probe_traffic:
@@ -377,6 +381,7 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": bytes_step,
             "avg_launch_us": per_launch_s * 1e6,
+            "variant": tuning,
         },
         "cpu_baseline": None,
     }

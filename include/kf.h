@@ -97,6 +97,12 @@ typedef struct kf_options {
                             0 = automatic (2 when every |col - row| < 32768),
                             2 or 4 */
   int32_t xcd_remap;     /* 1: map consecutive row slices to the same XCD */
+  int32_t nt_loads;      /* 1: stream the operator with non-temporal loads in
+                            the fused time step */
+  int32_t autotune;      /* 1: kf_create times the fused step with every
+                            combination of xcd_remap, nt_loads and (when both
+                            fit) 2- and 4-byte column indices and keeps the
+                            fastest (kf_get_tuning reports it) */
   void* stream;          /* hipStream_t */
 } kf_options;
 
@@ -130,6 +136,7 @@ typedef struct kf_result {
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
  * drop_tol 1e-10, refine 1, no vectors, automatic index width, XCD remap on,
+ * cached operator loads, no autotuning,
  * default stream. */
 void kf_default_options(kf_options* opt);
 
@@ -148,6 +155,12 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
 
 /* Release a handle and all its device memory.  NULL is accepted. */
 int kf_destroy(kf_problem* p);
+
+/* The fused-step variant in use: XCD remap, non-temporal operator loads,
+ * column-index bytes, and (after autotuning) its time per step in
+ * microseconds for one vector (0 when not tuned). */
+int kf_get_tuning(const kf_problem* p, int32_t* xcd_remap, int32_t* nt_loads, int32_t* index_bytes,
+                  double* us_per_step);
 
 /* Replace the L filter coefficients w_l = tau*alpha(l*tau) (host array of
  * exactly L finite values; Section 2.2 allows any weight function). */

@@ -83,6 +83,7 @@ struct kf_problem {
   EigWork ew;
   int basis_cols = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double tuned_us = 0.0;
 };
 
 struct kf_batch {
@@ -674,6 +675,70 @@ int distinct_count(const std::vector<double>& acc, int b) {
   return cnt;
 }
 
+// Time `reps` fused steps (one vector) of operator A with the given XCD
+// mapping; returns microseconds per step.
+int time_variant(kf_problem* p, const SellOp& A, int remap, int reps, double* us) {
+  hipStream_t st = p->st;
+  KF_TRY(ensure_step_buffers(p, p->sb, 1, A.val_bytes));
+  KF_HIP(hipMemsetAsync(p->sb.Y0, 0, (size_t)p->n * A.val_bytes, st));
+  KF_HIP(hipMemsetAsync(p->sb.Y1, 0, (size_t)p->n * A.val_bytes, st));
+  KF_HIP(hipMemsetAsync(p->sb.R, 0, (size_t)p->n * A.val_bytes, st));
+  for (int w = 0; w < 3; ++w)
+    KF_TRY(launch_leapfrog(A, 1, kMid, p->sb.Y1, p->sb.Y0, p->sb.Y0, p->sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+  KF_HIP(hipEventRecord(p->ev[0], st));
+  for (int r = 0; r < reps; ++r) {
+    void* a = (r & 1) ? p->sb.Y0 : p->sb.Y1;
+    void* b = (r & 1) ? p->sb.Y1 : p->sb.Y0;
+    KF_TRY(launch_leapfrog(A, 1, kMid, a, b, b, p->sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+  }
+  KF_HIP(hipEventRecord(p->ev[1], st));
+  KF_HIP(hipEventSynchronize(p->ev[1]));
+  float ms = 0.f;
+  KF_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+  *us = 1e3 * ms / reps;
+  return KF_OK;
+}
+
+// The autotuner: every combination of XCD mapping, non-temporal loads and
+// index width (2 and 4 bytes when 2 fits) of the fused step, timed on this
+// operator; the fastest is kept.
+int autotune(kf_problem* p, DevCsr& dc, const double* d_scale) {
+  SellOp alt;
+  const bool try_alt = p->A.idx_bytes == 2;
+  if (try_alt) KF_TRY(build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, p->A.val_bytes, 4, p->st, alt));
+  double best = 1e300;
+  int best_remap = p->opt.xcd_remap, best_nt = p->A.nt_loads, best_alt = 0;
+  for (int use_alt = 0; use_alt <= (try_alt ? 1 : 0); ++use_alt) {
+    SellOp& A = use_alt ? alt : p->A;
+    for (int nt = 0; nt <= 1; ++nt) {
+      for (int remap = 0; remap <= 1; ++remap) {
+        A.nt_loads = nt;
+        double us = 0;
+        int rc = time_variant(p, A, remap, 20, &us);
+        if (rc) {
+          free_sell(alt);
+          return rc;
+        }
+        if (us < best) {
+          best = us;
+          best_remap = remap;
+          best_nt = nt;
+          best_alt = use_alt;
+        }
+      }
+    }
+  }
+  if (best_alt) {
+    std::swap(p->A, alt);
+  }
+  free_sell(alt);
+  p->A.nt_loads = best_nt;
+  p->A64.nt_loads = best_nt;
+  p->opt.xcd_remap = best_remap;
+  p->tuned_us = best;
+  return KF_OK;
+}
+
 void free_problem(kf_problem* p) {
   if (!p) return;
   free_sell(p->A);
@@ -709,6 +774,8 @@ void kf_default_options(kf_options* o) {
   o->want_vectors = 0;
   o->index_bytes = 0;
   o->xcd_remap = 1;
+  o->nt_loads = 0;
+  o->autotune = 0;
   o->stream = nullptr;
 }
 
@@ -785,10 +852,16 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     if (!rc && o.precision == KF_MIXED && o.refine)
       rc = build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, 8, o.index_bytes, p->st, p->A64);
     if (!rc) rc = build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, nullptr, 8, o.index_bytes, p->st, p->S);
-    dfree(d_scale);
-    if (rc) break;
+    if (rc) {
+      dfree(d_scale);
+      break;
+    }
+    p->A.nt_loads = o.nt_loads ? 1 : 0;
+    p->A64.nt_loads = p->A.nt_loads;
     for (hipEvent_t& e : p->ev)
       if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
+    if (!rc && o.autotune) rc = autotune(p, dc, d_scale);
+    dfree(d_scale);
     if (rc) break;
   } while (false);
   if (rc) {
@@ -796,6 +869,16 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     return rc;
   }
   *out = p;
+  return KF_OK;
+}
+
+int kf_get_tuning(const kf_problem* p, int32_t* xcd_remap, int32_t* nt_loads, int32_t* index_bytes,
+                  double* us_per_step) {
+  if (!p) return fail(KF_EINVAL, "kf_get_tuning: NULL handle");
+  if (xcd_remap) *xcd_remap = p->opt.xcd_remap;
+  if (nt_loads) *nt_loads = p->A.nt_loads;
+  if (index_bytes) *index_bytes = p->A.idx_bytes;
+  if (us_per_step) *us_per_step = p->tuned_us;
   return KF_OK;
 }
 
@@ -1306,6 +1389,7 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     rc = build_sell((int32_t)bt->rows, (int64_t)hs.col.size(), dc.rowptr, dc.col, dc.val, nullptr, vb, o.index_bytes,
                     bt->st, bt->A);
     if (rc) break;
+    bt->A.nt_loads = o.nt_loads ? 1 : 0;
     if ((rc = dalloc(&bt->d_sp, sp.size()))) break;
     if ((rc = dalloc(&bt->d_tb, 1))) break;
     std::vector<double> w64((size_t)P * bt->lmax, 0.0);

@@ -45,6 +45,7 @@ struct SellOp {
   void* val = nullptr;
   void* idx = nullptr;
   int32_t max_width = 0;
+  int nt_loads = 0;  // 1: stream the matrix with non-temporal loads in the fused step
 };
 
 void free_sell(SellOp& op);

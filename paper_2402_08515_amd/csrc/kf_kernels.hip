@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, int32_t nslices, c
 }
 
 // ------------------------------------------------------------ fused leapfrog
-template <typename T, typename IT, int B, int MODE>
+template <typename T, typename IT, int B, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
                                                   const T* __restrict__ val, const IT* __restrict__ idx,
                                                   const T* __restrict__ cur, const T* prev, T* out,
@@ -134,8 +134,8 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
   for (int j = 0; j < B; ++j) sum[j] = (T)0;
 #pragma unroll 4
   for (int q = 0; q < width; ++q) {
-    const T a = __builtin_nontemporal_load(vp + (int64_t)q * 64);
-    const IT ci = __builtin_nontemporal_load(ip + (int64_t)q * 64);
+    const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
+    const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
     const int c = relative ? row + (int)ci : (int)ci;
     const Row<T, B> x = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
 #pragma unroll
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
 // per-problem tables (active flag, column counts, source / destination basis
 // columns) live in device memory and are refreshed before each replay, so the
 // launch sequence can be captured once in a graph.
-template <typename T, typename IT, int B>
+template <typename T, typename IT, int B, bool NT>
 __global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const int64_t* __restrict__ sptr,
                                                         const T* __restrict__ val, const IT* __restrict__ idx,
                                                         const int32_t* __restrict__ sp, const BatchTables* __restrict__ tb,
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const i
 #pragma unroll
   for (int j = 0; j < B; ++j) sum[j] = (T)0;
   for (int q = 0; q < width; ++q) {
-    const T a = __builtin_nontemporal_load(vp + (int64_t)q * 64);
-    const IT ci = __builtin_nontemporal_load(ip + (int64_t)q * 64);
+    const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
+    const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
     const int c = relative ? row + (int)ci : (int)ci;
     const Row<T, B> x = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
 #pragma unroll
@@ -546,9 +546,9 @@ __global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __rest
 }
 
 // ---- host-side dispatch helpers
-template <typename T, typename IT, int B>
-int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
-                int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+template <typename T, typename IT, int B, bool NT>
+int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                 int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
   const int grid = ceil_div64(A.nslices, 4);
   const T* v = static_cast<const T*>(A.val);
   const IT* ix = static_cast<const IT*>(A.idx);
@@ -558,24 +558,32 @@ int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, vo
   T* a = static_cast<T*>(acc);
   switch (mode) {
     case kMid:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
                          v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     case kFirst:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     case kLast:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
-                         v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     default:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
   }
   KF_HIP(hipGetLastError());
   return KF_OK;
+}
+
+template <typename T, typename IT, int B>
+int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+  if (A.nt_loads)
+    return launch_lf_bn<T, IT, B, true>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+  return launch_lf_bn<T, IT, B, false>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
 }
 
 template <typename T, typename IT>
@@ -691,7 +699,7 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
 }
 
 namespace {
-template <typename T, typename IT>
+template <typename T, typename IT, bool NT>
 int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax, int ell,
                  const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
   const int grid = ceil_div64(A.nslices, 4);
@@ -704,23 +712,23 @@ int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* t
   T* a = static_cast<T*>(acc);
   switch (b) {
     case 1:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 1>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 1, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
                          tb, w, lmax, ell, c, pr, o, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 2>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 2, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
                          tb, w, lmax, ell, c, pr, o, a);
       break;
     case 4:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 4>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 4, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
                          tb, w, lmax, ell, c, pr, o, a);
       break;
     case 8:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 8>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 8, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
                          tb, w, lmax, ell, c, pr, o, a);
       break;
     case 16:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 16>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix,
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 16, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix,
                          sp, tb, w, lmax, ell, c, pr, o, a);
       break;
     default:
@@ -734,12 +742,16 @@ int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* t
 
 int launch_leapfrog_batch(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax,
                           int ell, const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
+#define KF_LFB(T, IT)                                                                                  \
+  return A.nt_loads ? launch_lfb_t<T, IT, true>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st) \
+                    : launch_lfb_t<T, IT, false>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st)
   if (A.val_bytes == 8) {
-    if (A.idx_bytes == 2) return launch_lfb_t<double, int16_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
-    return launch_lfb_t<double, int32_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+    if (A.idx_bytes == 2) KF_LFB(double, int16_t);
+    KF_LFB(double, int32_t);
   }
-  if (A.idx_bytes == 2) return launch_lfb_t<float, int16_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
-  return launch_lfb_t<float, int32_t>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st);
+  if (A.idx_bytes == 2) KF_LFB(float, int16_t);
+  KF_LFB(float, int32_t);
+#undef KF_LFB
 }
 
 int launch_load_batch(int val_bytes, int64_t rows, int b, const int32_t* sp, const BatchTables* tb, const void* wtab,

@@ -55,6 +55,8 @@ class OptionsT(C.Structure):
         ("want_vectors", C.c_int32),
         ("index_bytes", C.c_int32),
         ("xcd_remap", C.c_int32),
+        ("nt_loads", C.c_int32),
+        ("autotune", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -118,6 +120,8 @@ _SIGNATURES = {
     "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "kf_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_double)]),
     "kf_create_batch": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(OptionsT), C.POINTER(C.c_void_p)]),
     "kf_destroy_batch": (C.c_int, [C.c_void_p]),
     "kf_batch_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -252,7 +256,8 @@ def _take_result(res, n: int) -> SolveResult:
 
 
 def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
-             drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True):
+             drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
+             autotune=False):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -266,6 +271,8 @@ def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=Fals
     opt.want_vectors = int(want_vectors)
     opt.index_bytes = index_bytes
     opt.xcd_remap = int(xcd_remap)
+    opt.nt_loads = int(nt_loads)
+    opt.autotune = int(autotune)
     opt.stream = _stream_handle()
     return opt
 
@@ -327,25 +334,11 @@ class Batch:
 class Problem:
     """Handle of ``kf_create``: pencil, interval, tau, L and options."""
 
-    def __init__(self, S, m, omega_min: float, omega_max: float, tau: float, L: int, precision: str = "fp64",
-                 check_every: int = 1, check_growth: float = 0.0, full_reorth: bool = False, target: int = 0, max_iters: int = 0, drop_tol: float = 1e-10,
-                 refine: bool = True, want_vectors: bool = False, index_bytes: int = 0, xcd_remap: bool = True):
+    def __init__(self, S, m, omega_min: float, omega_max: float, tau: float, L: int, **options):
         L_ = lib()
         self._h = C.c_void_p()
-        opt = OptionsT()
-        L_.kf_default_options(C.byref(opt))
-        opt.precision = _PREC[precision]
-        opt.check_every = check_every
-        opt.check_growth = check_growth
-        opt.full_reorth = int(full_reorth)
-        opt.target = target
-        opt.max_iters = max_iters
-        opt.drop_tol = drop_tol
-        opt.refine = int(refine)
-        opt.want_vectors = int(want_vectors)
-        opt.index_bytes = index_bytes
-        opt.xcd_remap = int(xcd_remap)
-        opt.stream = _stream_handle()
+        opt = _options(**options)
+        precision = options.get("precision", "fp64")
         c, keep = _host_csr(S)
         m = np.ascontiguousarray(m, dtype=np.float64)
         _check(L_.kf_create(C.byref(c), _ptr(m), omega_min, omega_max, tau, L, C.byref(opt), C.byref(self._h)))
@@ -364,6 +357,12 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def tuning(self) -> dict:
+        r, nt, ib = C.c_int32(), C.c_int32(), C.c_int32()
+        us = C.c_double()
+        _check(lib().kf_get_tuning(self._h, C.byref(r), C.byref(nt), C.byref(ib), C.byref(us)))
+        return {"xcd_remap": r.value, "nt_loads": nt.value, "index_bytes": ib.value, "us_per_step": us.value}
 
     def weights(self) -> np.ndarray:
         w = np.empty(self.L)

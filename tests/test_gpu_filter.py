@@ -130,3 +130,32 @@ def test_power_iteration_matches_oracle(dim, n):
     assert got == pytest.approx(ref, rel=1e-12)
 
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuned_and_cached_load_variants_match_oracle(precision):
+    """Every fused-step variant the autotuner chooses among (cached or
+    non-temporal operator loads, either XCD mapping, 2- or 4-byte indices)
+    computes the same operator C."""
+    import torch
+
+    kf = _kf()
+    S, m, tau, _, omin, omax = _case(3, 13)
+    L = 9
+    w = oracle.discrete_weights(omin, omax, tau, L)
+    X = start_block(S.shape[0], 3, 21)
+    ref = oracle.apply_filter(S, m, tau, w, X)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    print(f"case autotune precision={precision}", flush=True)
+    P = kf.Problem(S, m, omin, omax, tau, L, precision=precision, autotune=True)
+    t = P.tuning()
+    assert t["us_per_step"] > 0 and t["index_bytes"] in (2, 4) and t["nt_loads"] in (0, 1)
+    y = P.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.abs(y - ref).max() / np.abs(ref).max() <= tol
+    for ib in (2, 4):
+        for remap in (0, 1):
+            Q = kf.Problem(S, m, omin, omax, tau, L, precision=precision, nt_loads=False, index_bytes=ib,
+                           xcd_remap=bool(remap))
+            assert Q.tuning()["nt_loads"] == 0 and Q.tuning()["us_per_step"] == 0
+            y = Q.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
+            assert np.abs(y - ref).max() / np.abs(ref).max() <= tol, (ib, remap)
