@@ -280,9 +280,12 @@ __global__ __launch_bounds__(256) void k_scale_copy(int32_t n, int b, int bsrc, 
 
 // ------------------------------------------------------- tall-skinny float64
 // Stage 1 of H = Bk^T diag(w) X: one workgroup per (row chunk, group of 64
-// basis columns); the weighted X chunk sits in LDS, each wavefront reduces
-// whole basis columns against it.
-template <int NR>
+// basis columns); the weighted X chunk sits in LDS.  Each wavefront streams
+// Q basis columns at once with the row loop unrolled U times, so Q*U
+// independent loads per lane are in flight (one column at a time leaves the
+// wave waiting on a single load and reaches only about half of HBM
+// bandwidth); the X values read from LDS are shared by the Q columns.
+template <int NR, int Q, int U>
 __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
                                                 const double* __restrict__ X1, int n1, int64_t ldx1,
                                                 const double* __restrict__ X2, int n2, int64_t ldx2,
@@ -303,36 +306,62 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nchunks = gridDim.x;
   const int j0 = blockIdx.y * 64;
-  for (int jj = wave; jj < 64; jj += 4) {
-    const int j = j0 + jj;
-    if (j >= k) break;
-    const double* __restrict__ bcol = Bk + (int64_t)j * ldb + r0;
-    double s[NR];
+  for (int jj = wave * Q; jj < 64; jj += 4 * Q) {
+    const int jb = j0 + jj;
+    if (jb >= k) break;
+    // columns past k repeat column k-1 (in bounds) and are not stored
+    const double* bc[Q];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) s[c] = 0.0;
-    for (int r = lane; r < rows; r += 64) {
-      const double bv = bcol[r];
+    for (int q = 0; q < Q; ++q) bc[q] = Bk + (int64_t)std::min(jb + q, k - 1) * ldb + r0;
+    double s[Q][NR];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) s[q][c] = 0.0;
+    int r = lane;
+    for (; r + 64 * (U - 1) < rows; r += 64 * U) {
+      double bv[U][Q];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) bv[u][q] = bc[q][r + 64 * u];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < nrhs) {
+            const double xv = xs[c * CH + r + 64 * u];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[u][q], xv, s[q][c]);
+          }
+    }
+    for (; r < rows; r += 64) {
+      double bv[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) bv[q] = bc[q][r];
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        if (c < nrhs) s[c] = fma(bv, xs[c * CH + r], s[c]);
-    }
+        if (c < nrhs) {
+          const double xv = xs[c * CH + r];
 #pragma unroll
-    for (int c = 0; c < NR; ++c)
-      if (c < nrhs) s[c] = wave_sum(s[c]);
-    if (lane == 0) {
-      // layout [output (j, c)][chunk]: the second pass reads each output's
-      // partials contiguously
-      const int nchunks = gridDim.x;
+          for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[q], xv, s[q][c]);
+        }
+    }
+    // layout [output (j, c)][chunk]: the second pass reads each output's
+    // partials contiguously
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        if (c < nrhs) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = s[c];
-    }
+        if (c < nrhs) {
+          const double v = wave_sum(s[q][c]);
+          if (lane == 0 && jb + q < k) partial[((int64_t)(jb + q) * nrhs + c) * nchunks + chunk] = v;
+        }
   }
 }
 
-// Second pass: one wavefront per output, lanes stride over the chunks in a
-// fixed order, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
                                                         const double* __restrict__ partial, double* __restrict__ H,
                                                         int64_t ldh) {
@@ -816,25 +845,25 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   const dim3 grid(nchunks, ceil_div64(k, 64));
   const size_t lds = sizeof(double) * CH * nrhs;
   if (nrhs == 1)
-    hipLaunchKernelGGL(k_gemv_t<1>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else if (nrhs <= 2)
-    hipLaunchKernelGGL(k_gemv_t<2>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<2, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else if (nrhs <= 4)
-    hipLaunchKernelGGL(k_gemv_t<4>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<4, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else if (nrhs <= 8)
-    hipLaunchKernelGGL(k_gemv_t<8>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<8, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else if (nrhs <= 16)
-    hipLaunchKernelGGL(k_gemv_t<16>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<16, 2, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else if (nrhs <= 32)
-    hipLaunchKernelGGL(k_gemv_t<32>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<32, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else
-    hipLaunchKernelGGL(k_gemv_t<64>, grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<64, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
