@@ -164,14 +164,14 @@ def bench_learned(args):
     import numpy as np
     import torch
 
-    from oracle import mlp as mlp_init  # initial parameters only (the seeded draw), no arithmetic of the path
     from paper_2402_08515_amd import kf
     from synth import distinct_target, grid_spectrum, power_start, start_block
     from synth.grids import grid_problem
+    from synth.netinit import init_params
     from synth.workloads import filter_samples, grid3d_128_intervals
 
     train = filter_samples(args.mlp_samples, stream=0)
-    net = kf.Mlp(mlp_init.init_params(4).astype(np.float32))
+    net = kf.Mlp(init_params(4).astype(np.float32))
     rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
     order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
     t0 = time.perf_counter()

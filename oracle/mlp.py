@@ -32,6 +32,8 @@ import math
 import numpy as np
 from scipy.special import erf
 
+from synth import netinit
+
 HIDDEN = 128
 LMAX = 512
 G = 512
@@ -157,18 +159,8 @@ def loss_and_grad(theta, samples):
 
 
 def init_params(seed: int) -> np.ndarray:
-    """He-style normal initialisation of the hidden layers, output layer at
-    zero (the untrained network returns the Fourier weights)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for s in SHAPES:
-        if len(s) == 1:
-            parts.append(np.zeros(s))
-        elif s[1] == LMAX:
-            parts.append(np.zeros(s))
-        else:
-            parts.append(rng.standard_normal(s) * math.sqrt(2.0 / s[0]))
-    return np.concatenate([p.ravel() for p in parts])
+    """The seeded initial parameters (drawn by the shared input generator)."""
+    return netinit.init_params(seed, SHAPES)
 
 
 def teacher(sample, ridge: float = 1e-6) -> np.ndarray:

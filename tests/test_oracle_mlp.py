@@ -51,3 +51,23 @@ def test_teacher_is_the_least_squares_optimum():
             d = np.zeros(mlp.LMAX)
             d[:L] = rng.standard_normal(L) * 1e-4
             assert mlp.loss_of_weights(s, wt + d) >= mlp.loss_of_weights(s, wt) - 1e-12
+
+
+def test_loss_in_frequency_terms():
+    """The loss restated in the variable omega: band = [omega_min, omega_max],
+    stop band = omega <= sqrt(lambda_max) at more than pi/(tau L) from the
+    band (half a main lobe of an L-term filter in omega), beta~ from the
+    scalar recurrence of the oracle; grid omega_g = 2 x_g / tau."""
+    for s in filter_samples(4, stream=1):
+        omin, omax, tau, lam = s
+        a, c, L, xm = mlp.sample_params(*s)
+        rng = np.random.default_rng(5)
+        w = mlp.fourier_weights_normalised(a, c, L)
+        w[:L] += 0.01 * rng.standard_normal(L)
+        om = 2.0 * mlp.x_grid() / tau
+        beta = oracle.beta_tilde(om, tau, w[:L])
+        band = (om >= omin) & (om <= omax)
+        gap = np.pi / (tau * L)
+        stop = (om <= np.sqrt(lam)) & ((om < omin - gap) | (om > omax + gap))
+        expect = np.mean((beta[band] - 1.0) ** 2) + np.mean(beta[stop] ** 2)
+        assert mlp.loss_of_weights(s, w) == pytest.approx(expect, rel=1e-9)
