@@ -156,6 +156,19 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
 /* Release a handle and all its device memory.  NULL is accepted. */
 int kf_destroy(kf_problem* p);
 
+/* The dense symmetric eigensolver that kf_solve applies to the projected
+ * pencil of eq. projevp (Section 2.1; the basis is M-orthonormal, so the
+ * pencil is the symmetric matrix B^T S B): Householder tridiagonalisation,
+ * bisection, inverse iteration, back-transformation, all on the GPU.
+ * A: host k x k column-major (the two triangles are averaged), 1 <= k <= 2048.
+ * theta[k] (host) receives all eigenvalues ascending.  If Y != NULL, the
+ * eigenvectors (unit 2-norm) of the eigenvalues in [lo, hi] go to Y (host,
+ * k x *n_sel column-major; capacity k*k) and their count to *n_sel.
+ * Works on `stream` (hipStream_t, NULL = default); blocks until done.
+ * Errors: KF_EINVAL (size, NULL, non-finite entries), KF_ENOMEM, KF_EHIP. */
+int kf_sym_eig(int32_t k, const double* A, double lo, double hi, double* theta, int32_t* n_sel, double* Y,
+               void* stream);
+
 /* The fused-step variant in use: XCD remap, non-temporal operator loads,
  * column-index bytes, and (after autotuning) its time per step in
  * microseconds for one vector (0 when not tuned). */

@@ -504,12 +504,11 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
 // eigenvalues of the k x k symmetric matrix Hm (ld ldh) into out (host), and
 // eigenvectors for those selected by keep() into ew.Y; returns the selection
 template <class Keep>
-int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector<double>& theta, Keep keep,
-                std::vector<double>& sel) {
-  hipStream_t st = p->st;
-  KF_TRY(eig_values(p->ew, k, Hm, ldh, st));
+int eig_select(EigWork& ew, int k, const double* Hm, int64_t ldh, std::vector<double>& theta, Keep keep,
+               std::vector<double>& sel, hipStream_t st) {
+  KF_TRY(eig_values(ew, k, Hm, ldh, st));
   theta.assign((size_t)k, 0.0);
-  KF_HIP(hipMemcpyAsync(theta.data(), p->ew.theta, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  KF_HIP(hipMemcpyAsync(theta.data(), ew.theta, sizeof(double) * k, hipMemcpyDeviceToHost, st));
   KF_HIP(hipStreamSynchronize(st));
   sel.clear();
   for (int i = 0; i < k; ++i)
@@ -523,7 +522,13 @@ int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector
     if (sel[(size_t)i] - sel[(size_t)i - 1] > 1e-9 * tn) cl.push_back(i);
   const int ncl = (int)cl.size();
   cl.push_back(nsel);
-  return eig_vectors(p->ew, k, sel.data(), cl.data(), ncl, nsel, st);
+  return eig_vectors(ew, k, sel.data(), cl.data(), ncl, nsel, st);
+}
+
+template <class Keep>
+int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector<double>& theta, Keep keep,
+                std::vector<double>& sel) {
+  return eig_select(p->ew, k, Hm, ldh, theta, keep, sel, p->st);
 }
 
 // Rayleigh-Ritz on the leading k basis columns.  Residuals are formed for the
@@ -870,6 +875,40 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   }
   *out = p;
   return KF_OK;
+}
+
+int kf_sym_eig(int32_t k, const double* A, double lo, double hi, double* theta, int32_t* n_sel, double* Y,
+               void* stream) {
+  if (k < 1 || k > 2048) return fail(KF_EINVAL, "kf_sym_eig: k must be in [1, 2048]");
+  if (!A || !theta) return fail(KF_EINVAL, "kf_sym_eig: NULL argument");
+  if (Y && !n_sel) return fail(KF_EINVAL, "kf_sym_eig: n_sel is needed with Y");
+  for (int64_t i = 0; i < (int64_t)k * k; ++i)
+    if (!std::isfinite(A[i])) return fail(KF_EINVAL, "kf_sym_eig: non-finite entry");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EigWork ew;
+  double* dA = nullptr;
+  int rc = KF_OK;
+  do {
+    if ((rc = dalloc(&dA, (size_t)k * k))) break;
+    if (hipMemcpyAsync(dA, A, sizeof(double) * k * k, hipMemcpyHostToDevice, st) != hipSuccess) {
+      rc = fail(KF_EHIP, "kf_sym_eig: copy failed");
+      break;
+    }
+    if ((rc = symmetrize(k, dA, k, st))) break;
+    std::vector<double> th, sel;
+    auto keep = [&](double t) { return Y != nullptr && t >= lo && t <= hi; };
+    if ((rc = eig_select(ew, k, dA, k, th, keep, sel, st))) break;
+    std::copy(th.begin(), th.end(), theta);
+    if (Y) {
+      *n_sel = (int32_t)sel.size();
+      if (!sel.empty() && hipMemcpyAsync(Y, ew.Y, sizeof(double) * k * sel.size(), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = fail(KF_EHIP, "kf_sym_eig: copy failed");
+      if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(KF_EHIP, "kf_sym_eig: synchronisation failed");
+    }
+  } while (false);
+  dfree(dA);
+  free_eig(ew);
+  return rc;
 }
 
 int kf_get_tuning(const kf_problem* p, int32_t* xcd_remap, int32_t* nt_loads, int32_t* index_bytes,

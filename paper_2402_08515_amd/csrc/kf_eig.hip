@@ -28,6 +28,9 @@ namespace {
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// matrices of this order and larger are reduced by k_tri_step
+constexpr int kTriMultiFrom = 160;
+
 __device__ __forceinline__ double wave_sum_e(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -185,6 +188,114 @@ __global__ __launch_bounds__(1024) void k_tridiag(int m, double* __restrict__ A,
     __syncthreads();
     finish_w(c, tn, vn, wn);
     cur ^= 1;
+  }
+}
+
+// One step of the same Householder reduction spread over many workgroups
+// (one launch per reflector; used for larger matrices, where a single
+// workgroup is latency-bound).  Launch k:
+//   * every workgroup finishes w_{k-1} = p_{k-1} - (tau_{k-1}/2)(p_{k-1}.v_{k-1}) v_{k-1}
+//     from the previous launch's p, applies reflector k-1 to column k on the
+//     fly and forms reflector k from it (the same arithmetic in the same
+//     order in every workgroup, so all agree bit for bit);
+//   * workgroup 0 records d_k, e_k, tau_k and v_k, and stores v_{k-1} below
+//     the subdiagonal of column k-1 (no workgroup reads that column here);
+//   * each wavefront owns whole columns j > k: it applies reflector k-1 to
+//     rows > k of column j (the matrix is symmetric, so a column is a row and
+//     the lanes read consecutive addresses) and forms p_k[j] = tau_k (A v_k)_j.
+// Column k is only read in launch k; columns > k are only touched by their
+// owner, so no two workgroups write the same entry.
+__global__ __launch_bounds__(256) void k_tri_step(int m, int k, double* __restrict__ A, double* __restrict__ d,
+                                                  double* __restrict__ e, double* __restrict__ tau,
+                                                  double* __restrict__ pv) {
+  extern __shared__ double sh[];
+  double* vp = sh;           // v_{k-1}
+  double* w = sh + m;        // w_{k-1}
+  double* vk = sh + 2 * m;   // column k after reflector k-1, then v_k
+  double* red = sh + 3 * m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* pprev = pv + (int64_t)((k + 1) & 1) * m;
+  double* pcur = pv + (int64_t)(k & 1) * m;
+  const double* vprev_g = pv + (int64_t)(2 + ((k + 1) & 1)) * m;
+  double* vcur_g = pv + (int64_t)(2 + (k & 1)) * m;
+  // w_{k-1}
+  if (k == 0) {
+    for (int i = tid; i < m; i += nt) {
+      vp[i] = 0.0;
+      w[i] = 0.0;
+    }
+    __syncthreads();
+  } else {
+    double s = 0.0;
+    for (int i = tid; i < m; i += nt) {
+      const double v = i >= k ? vprev_g[i] : 0.0;
+      vp[i] = v;
+      if (i >= k) s = fma(pprev[i], v, s);
+    }
+    s = block_sum(s, red);
+    const double K = 0.5 * tau[k - 1] * s;
+    for (int i = tid; i < m; i += nt) w[i] = i >= k ? pprev[i] - K * vp[i] : 0.0;
+    __syncthreads();
+  }
+  // column k after reflector k-1, and reflector k
+  const double wk = w[k], vpk = vp[k];
+  double s = 0.0;
+  for (int i = tid; i < m; i += nt) {
+    const double a = i >= k ? A[i + (int64_t)k * m] - vp[i] * wk - w[i] * vpk : 0.0;
+    vk[i] = a;
+    if (i >= k + 2) s = fma(a, a, s);
+  }
+  s = block_sum(s, red);
+  const double dk = vk[k];
+  const double alpha = k + 1 < m ? vk[k + 1] : 0.0;
+  double beta = alpha, tk = 0.0, v0 = 1.0;
+  if (s > 0.0) {
+    const double mu = sqrt(alpha * alpha + s);
+    beta = alpha <= 0.0 ? mu : -mu;
+    v0 = alpha - beta;
+    tk = (beta - alpha) / beta;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += nt) vk[i] = (i <= k) ? 0.0 : (i == k + 1 ? 1.0 : (tk == 0.0 ? 0.0 : vk[i] / v0));
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      d[k] = dk;
+      e[k] = beta;
+      tau[k] = tk;
+    }
+    for (int i = tid; i < m; i += nt) vcur_g[i] = vk[i];
+    if (k >= 1)
+      for (int i = k + 1 + tid; i < m; i += nt) A[i + (int64_t)(k - 1) * m] = vp[i];
+  }
+  // owned columns
+  const int lane = tid & 63;
+  const int nwaves = gridDim.x * (nt >> 6);
+  for (int j = k + 1 + blockIdx.x * (nt >> 6) + (tid >> 6); j < m; j += nwaves) {
+    double* __restrict__ col = A + (int64_t)j * m;
+    const double wj = w[j], vj = vp[j];
+    double dot = 0.0;
+    int i = k + 1 + lane;
+    for (; i + 192 < m; i += 256) {
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = col[i + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = i + 64 * u;
+        a[u] = a[u] - vp[r] * wj - w[r] * vj;
+        col[r] = a[u];
+        dot = fma(a[u], vk[r], dot);
+      }
+    }
+    for (; i < m; i += 64) {
+      const double a = col[i] - vp[i] * wj - w[i] * vj;
+      col[i] = a;
+      dot = fma(a, vk[i], dot);
+      if (k == m - 2 && i == m - 1) d[m - 1] = a;
+    }
+    dot = wave_sum_e(dot);
+    if (lane == 0) pcur[j] = tk * dot;
   }
 }
 
@@ -419,7 +530,7 @@ __global__ __launch_bounds__(256) void k_backtransform(int m, const double* __re
 }  // namespace
 
 void free_eig(EigWork& w) {
-  double* ptrs[] = {w.A, w.d, w.e, w.e2, w.bounds, w.tau, w.theta, w.Z, w.Y, w.scratch, w.sel};
+  double* ptrs[] = {w.A, w.d, w.e, w.e2, w.bounds, w.tau, w.theta, w.pv, w.Z, w.Y, w.scratch, w.sel};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.cl) (void)hipFree(w.cl);
@@ -428,7 +539,7 @@ void free_eig(EigWork& w) {
 
 int eig_reserve(EigWork& w, int m, int nsel) {
   if ((size_t)m > w.cap_m) {
-    double** ps[] = {&w.A, &w.d, &w.e, &w.e2, &w.bounds, &w.tau, &w.theta};
+    double** ps[] = {&w.A, &w.d, &w.e, &w.e2, &w.bounds, &w.tau, &w.theta, &w.pv};
     for (double** p : ps) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
@@ -437,7 +548,7 @@ int eig_reserve(EigWork& w, int m, int nsel) {
     if (hipMalloc(&w.A, sizeof(double) * mm * mm) != hipSuccess || hipMalloc(&w.d, sizeof(double) * mm) != hipSuccess ||
         hipMalloc(&w.e, sizeof(double) * mm) != hipSuccess || hipMalloc(&w.e2, sizeof(double) * mm) != hipSuccess ||
         hipMalloc(&w.bounds, sizeof(double) * 4) != hipSuccess || hipMalloc(&w.tau, sizeof(double) * mm) != hipSuccess ||
-        hipMalloc(&w.theta, sizeof(double) * mm) != hipSuccess) {
+        hipMalloc(&w.theta, sizeof(double) * mm) != hipSuccess || hipMalloc(&w.pv, sizeof(double) * 4 * mm) != hipSuccess) {
       set_error("eig_reserve: allocation failed");
       return KF_ENOMEM;
     }
@@ -475,9 +586,20 @@ int eig_values(EigWork& w, int k, const double* H, int64_t ldh, hipStream_t st) 
   KF_TRY(eig_reserve(w, k, 1));
   hipLaunchKernelGGL(k_copy_square, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, st, k, H, ldh, w.A);
   KF_HIP(hipGetLastError());
-  const size_t lds = sizeof(double) * (4 * (size_t)k + 32);
-  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lds, st, k, w.A, w.d, w.e, w.tau);
-  KF_HIP(hipGetLastError());
+  if (k < kTriMultiFrom) {
+    const size_t lds = sizeof(double) * (4 * (size_t)k + 32);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lds, st, k, w.A, w.d, w.e, w.tau);
+    KF_HIP(hipGetLastError());
+  } else {
+    // one launch per reflector; the grid shrinks with the trailing matrix
+    const size_t lds = sizeof(double) * (3 * (size_t)k + 32);
+    for (int j = 0; j + 2 <= k; ++j) {
+      const int cols = k - j - 1;
+      const int grid = std::max(1, std::min(cdiv(cols, 4), 256));
+      hipLaunchKernelGGL(k_tri_step, dim3(grid), dim3(256), lds, st, k, j, w.A, w.d, w.e, w.tau, w.pv);
+      KF_HIP(hipGetLastError());
+    }
+  }
   hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(256), 0, st, k, w.d, w.e, w.e2, w.bounds);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bisect, dim3(cdiv(k, 4)), dim3(256), 0, st, k, w.d, w.e2, w.bounds, w.theta);

@@ -158,6 +158,7 @@ struct EigWork {
   double* bounds = nullptr;  // Gershgorin bracket and pivot floor
   double* tau = nullptr;
   double* theta = nullptr;
+  double* pv = nullptr;    // 4 x m: two p vectors and two reflectors (multi-workgroup reduction)
   double* Z = nullptr;     // m x nsel (tridiagonal eigenvectors)
   double* Y = nullptr;     // m x nsel (pencil eigenvectors)
   double* scratch = nullptr;

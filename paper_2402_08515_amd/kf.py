@@ -120,6 +120,8 @@ _SIGNATURES = {
     "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "kf_sym_eig": (C.c_int, [C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int32),
+                             C.c_void_p, C.c_void_p]),
     "kf_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double)]),
     "kf_create_batch": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(OptionsT), C.POINTER(C.c_void_p)]),
@@ -185,6 +187,24 @@ def _stream_handle() -> int:
     if not torch.cuda.is_available():
         return 0
     return torch.cuda.current_stream().cuda_stream
+
+
+def sym_eig(A, lo: float = 0.0, hi: float = -1.0, vectors: bool = False):
+    """All eigenvalues (ascending) of the dense symmetric matrix A with the
+    library's GPU eigensolver; with vectors=True also the eigenvectors of the
+    eigenvalues in [lo, hi] (k x count)."""
+    a = np.asfortranarray(A, dtype=np.float64)
+    k = a.shape[0]
+    if a.shape != (k, k):
+        raise ValueError("A must be square")
+    theta = np.empty(k)
+    nsel = C.c_int32(0)
+    Y = np.empty((k, k), order="F") if vectors else None
+    _check(lib().kf_sym_eig(k, _ptr(a), lo, hi, _ptr(theta), C.byref(nsel), _ptr(Y) if vectors else None,
+                            _stream_handle()))
+    if vectors:
+        return theta, np.ascontiguousarray(Y[:, : nsel.value])
+    return theta
 
 
 def time_step_rule(lambda_est: float, omega_min: float, safety: float = 0.9):

@@ -92,3 +92,13 @@ def test_create_rejects_bad_parameters(small):
 def test_last_error_is_a_string():
     kf = _kf()
     assert isinstance(kf.last_error(), str)
+
+
+def test_sym_eig_validation():
+    from paper_2402_08515_amd import kf
+
+    _expect_einval(lambda: kf.sym_eig(np.zeros((0, 0))))
+    A = np.eye(3)
+    A[1, 2] = np.nan
+    assert "non-finite" in _expect_einval(lambda: kf.sym_eig(A))
+    _expect_einval(lambda: kf.sym_eig(np.eye(2049)))

@@ -1,0 +1,53 @@
+"""The projected-pencil eigensolver (kf_sym_eig: Householder
+tridiagonalisation on one workgroup below order 160 and one launch per
+reflector above, bisection, inverse iteration, back-transformation) on
+matrices whose spectrum is fixed by construction, A = Q diag(lam) Q^T."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _kf():
+    from paper_2402_08515_amd import kf
+
+    return kf
+
+
+def _matrix(k, seed, clusters=True):
+    rng = np.random.default_rng(seed)
+    lam = np.sort(rng.uniform(-3.0, 5.0, size=k))
+    if clusters and k >= 8:
+        lam[k // 3 : k // 3 + 3] = lam[k // 3]  # a triple eigenvalue
+        lam[k // 2 + 1] = lam[k // 2] * (1 + 1e-11)  # a tight pair
+        lam = np.sort(lam)
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    return (Q * lam) @ Q.T, lam
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 17, 159, 160, 161, 457, 1100])
+def test_eigenvalues_and_vectors(k):
+    kf = _kf()
+    print(f"case sym_eig k={k}", flush=True)
+    A, lam = _matrix(k, 40 + k)
+    lo, hi = np.quantile(lam, 0.3), np.quantile(lam, 0.6)
+    theta, Y = kf.sym_eig(A, lo, hi, vectors=True)
+    scale = np.abs(lam).max()
+    assert np.abs(theta - lam).max() <= 1e-12 * scale * max(1.0, np.sqrt(k) / 8)
+    sel = theta[(theta >= lo) & (theta <= hi)]
+    assert Y.shape == (k, sel.size)
+    if sel.size:
+        R = A @ Y - Y * sel
+        assert np.abs(R).max() <= 1e-11 * scale
+        assert np.abs(Y.T @ Y - np.eye(sel.size)).max() <= 1e-10
+
+
+def test_values_only_and_asymmetric_input_is_averaged():
+    kf = _kf()
+    A, lam = _matrix(200, 7, clusters=False)
+    rng = np.random.default_rng(8)
+    E = 1e-3 * rng.standard_normal(A.shape)
+    theta = kf.sym_eig(A + E)
+    ref = np.linalg.eigvalsh(A + 0.5 * (E + E.T))
+    assert np.abs(theta - ref).max() <= 1e-12 * np.abs(ref).max()
