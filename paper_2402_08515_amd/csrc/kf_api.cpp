@@ -107,6 +107,9 @@ struct kf_batch {
 namespace {
 
 constexpr int kSmall = 4096;
+// offsets of the device scalars in kf_problem::small used by the
+// orthogonalisation (the Rayleigh-Ritz check uses 1024.. and 2048..)
+constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kOne = 4095;
 
 int pow2ceil(int b) {
   int p = 1;
@@ -302,6 +305,8 @@ int ensure_misc(kf_problem* p) {
   KF_TRY(dalloc(&p->SV, (size_t)p->n * 64));
   KF_TRY(dalloc(&p->small, kSmall));
   KF_TRY(dalloc(&p->flags, 64));
+  const double one = 1.0;
+  KF_HIP(hipMemcpy(p->small + kOne, &one, sizeof(double), hipMemcpyHostToDevice));
   return KF_OK;
 }
 
@@ -317,89 +322,123 @@ int ensure_misc(kf_problem* p) {
 // loc0 >= 0 selects the three-term form: C is M-self-adjoint (Lemma 2.3,
 // C = beta~(M^{-1}S)), so the filtered block is M-orthogonal, in exact
 // arithmetic, to every basis block except the last two, [loc0, kb).  The
-// block is first orthogonalised (twice) against that window only, then once
-// against the whole basis; a second full pass runs only when the full pass
-// removed more than half of the M-norm of a column (the test of Daniel,
-// Gragg, Kaufman and Stewart).  loc0 < 0 runs classical Gram-Schmidt twice
-// against the whole basis.
+// block is first orthogonalised against that window, then once against the
+// whole basis (the second pass for the window's columns); another full pass
+// runs only when the full pass removed more than half of the M-norm of a
+// column (the test of Daniel, Gragg, Kaufman and Stewart).  loc0 < 0 runs
+// classical Gram-Schmidt twice against the whole basis.
+//
+// The block's own Gram matrix rides along as extra rows of the first
+// projection (the block sits right after its left operand in B: X is column
+// kb = c0), so the norms before each pass cost no launch of their own.
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
                hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr) {
+  if (c0 != kb) return fail(KF_EINVAL, "orth_block: the block must follow the basis");
   hipStream_t st = p->st;
   const int32_t n = p->n;
   const int64_t ldb = p->ldb;
   double* X = p->B + (int64_t)c0 * ldb;
-  double* Tref = p->small;           // nb x nb Gram matrix of the block (before)
-  double* post = p->small + 256;     // nb post norms
-  double* nrm2 = p->small + 512;     // nb squared norms
-  double* coef = p->T;               // kb x nb or j x 1
-  KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, Tref, nb, p->gw, st));
+  double* post = p->small + kPost;   // nb post norms
+  double* nrm2 = p->small + kNrm2;   // nb squared norms
+  double* g2 = p->small + kG2;       // nb x nb Gram after the full pass (blocks)
+  double* T1 = p->small + kT1;       // first projection [(w + nb) x nb]
+  double* coef = p->T;               // (kb + nb) x (2 pn + nb)
+  const bool local = kb > 0 && loc0 >= 0;
+  const int lw = local ? kb - loc0 : 0;
+  // first projection: the window [loc0, kb) (none without the three-term
+  // form) and the block itself; rows lw.. hold the block's Gram matrix
+  const int ld1 = lw + nb;
+  const double* L1 = p->B + (int64_t)(kb - lw) * ldb;
+  KF_TRY(gemv_t(n, ld1, L1, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, T1, ld1, p->gw, st));
+  const double* Tref = T1 + lw;  // nb x nb, leading dimension ld1
+  if (lw > 0) KF_TRY(gemv_n_sub(n, lw, L1, ldb, T1, ld1, X, ldb, nb, st));
   // pass over the whole basis; the first one also forms the pending
-  // projected-pencil columns [B^T S Q | B^T M Q] with Q = B[:, kb-pn:kb]
-  // adjacent to the block
+  // projected-pencil columns [B^T S Q | B^T M Q] with Q = B[:, kb-pn:kb]; the
+  // rows below kb give the block's Gram matrix before the pass
+  const int ldc = kb + nb;
   auto full_pass = [&](bool with_pending) -> int {
     if (with_pending && pn > 0) {
       const int p0 = kb - pn;
       const double* Q = p->B + (int64_t)p0 * ldb;
       KF_TRY(spmv_cols(p->S, Q, ldb, p->W, n, pn, nullptr, st));
-      KF_TRY(gemv_t(n, kb, p->B, ldb, p->W, pn, n, Q, pn + nb, ldb, p->d_m, coef, kb, p->gw, st));
-      KF_TRY(rr_scatter(kb, p0, pn, coef, kb, p->H, p->G, p->hcap, st));
-      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef + (int64_t)2 * pn * kb, kb, X, ldb, nb, st));
+      KF_TRY(gemv_t(n, ldc, p->B, ldb, p->W, pn, n, Q, pn + nb, ldb, p->d_m, coef, ldc, p->gw, st));
+      KF_TRY(rr_scatter(kb, p0, pn, coef, ldc, p->H, p->G, p->hcap, st));
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef + (int64_t)2 * pn * ldc, ldc, X, ldb, nb, st));
     } else {
-      KF_TRY(gemv_t(n, kb, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, kb, p->gw, st));
-      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef, kb, X, ldb, nb, st));
+      KF_TRY(gemv_t(n, ldc, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, ldc, p->gw, st));
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef, ldc, X, ldb, nb, st));
     }
     if (full_passes) ++*full_passes;
     return KF_OK;
   };
-  if (kb > 0 && loc0 < 0) {
+  const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
+  std::vector<double> hv((size_t)ld1 * nb);
+  std::vector<int32_t> fl((size_t)nb);
+  auto fetch = [&](const double* src, size_t count, void* dst) -> int {
+    KF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    return KF_OK;
+  };
+  // in-block CGS2 and normalisation of column j against ref2 (device)
+  auto finish_cols = [&](const double* ref_base, int64_t ref_ld) -> int {
+    for (int j = 0; j < nb; ++j) {
+      double* xj = X + (int64_t)j * ldb;
+      if (j > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          KF_TRY(gemv_t(n, j, X, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, coef, j, p->gw, st));
+          KF_TRY(gemv_n_sub(n, j, X, ldb, coef, j, xj, ldb, 1, st));
+        }
+      }
+      KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, nrm2 + j, 1, p->gw, st));
+      KF_TRY(normalize_col(n, xj, nrm2 + j, ref_base + (int64_t)j * ref_ld + j, drop, p->flags + j, post + j, st));
+    }
+    return KF_OK;
+  };
+  if (kb > 0 && !local) {
     KF_TRY(full_pass(true));
     KF_TRY(full_pass(false));
-  } else if (kb > 0) {
-    const int lw = kb - loc0;
-    const double* Bl = p->B + (int64_t)loc0 * ldb;
-    for (int pass = 0; pass < 2; ++pass) {
-      KF_TRY(gemv_t(n, lw, Bl, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, lw, p->gw, st));
-      KF_TRY(gemv_n_sub(n, lw, Bl, ldb, coef, lw, X, ldb, nb, st));
-    }
-    double* g1 = p->small + 768;       // column M-norms^2 before the full pass
-    double* g2 = p->small + 768 + 16;  // and after it
-    for (int j = 0; j < nb; ++j) {
-      double* xj = X + (int64_t)j * ldb;
-      KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, g1 + j, 1, p->gw, st));
-    }
+    KF_TRY(finish_cols(Tref, ld1));
+    if (done) KF_HIP(hipEventRecord(done, st));
+  } else if (kb > 0 && nb == 1) {
+    // one vector: its norm after the full pass is the normalisation norm, so
+    // the second-pass test and the drop test share one synchronisation
     KF_TRY(full_pass(true));
-    for (int j = 0; j < nb; ++j) {
-      double* xj = X + (int64_t)j * ldb;
-      KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, g2 + j, 1, p->gw, st));
+    KF_TRY(finish_cols(Tref, ld1));
+    double g1 = 0.0, g2h = 0.0;
+    KF_TRY(fetch(coef + kb + (int64_t)(2 * pn) * ldc, 1, &g1));
+    KF_TRY(fetch(nrm2, 1, &g2h));
+    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (done) KF_HIP(hipEventRecord(done, st));
+    KF_HIP(hipStreamSynchronize(st));
+    if (fl[0] && g2h < 0.25 * g1) {
+      // the column is normalised now: one more pass against the whole basis,
+      // dropped if it loses all but drop_tol of its unit norm
+      KF_TRY(full_pass(false));
+      KF_TRY(gemv_t(n, 1, X, ldb, nullptr, 0, 0, X, 1, ldb, p->d_m, nrm2, 1, p->gw, st));
+      KF_TRY(normalize_col(n, X, nrm2, p->small + kOne, drop, p->flags, post, st));
+      if (done) KF_HIP(hipEventRecord(done, st));
     }
-    double hg[32];
-    KF_HIP(hipMemcpyAsync(hg, g1, sizeof(double) * 32, hipMemcpyDeviceToHost, st));
+  } else if (kb > 0) {
+    KF_TRY(full_pass(true));
+    KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+    std::vector<double> hg1((size_t)ldc * nb), hg2((size_t)nb * nb);
+    KF_TRY(fetch(coef + (int64_t)(2 * pn) * ldc, (size_t)ldc * nb, hg1.data()));
+    KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
     KF_HIP(hipStreamSynchronize(st));
     bool again = false;
     for (int j = 0; j < nb; ++j)
-      if (hg[16 + j] < 0.25 * hg[j]) again = true;  // norm fell below half
+      if (hg2[(size_t)j * nb + j] < 0.25 * hg1[(size_t)kb + j + (size_t)j * ldc]) again = true;
     if (again) KF_TRY(full_pass(false));
+    KF_TRY(finish_cols(Tref, ld1));
+    if (done) KF_HIP(hipEventRecord(done, st));
+  } else {
+    KF_TRY(finish_cols(Tref, ld1));
+    if (done) KF_HIP(hipEventRecord(done, st));
   }
-  const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
-  for (int j = 0; j < nb; ++j) {
-    double* xj = X + (int64_t)j * ldb;
-    if (j > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        KF_TRY(gemv_t(n, j, X, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, coef, j, p->gw, st));
-        KF_TRY(gemv_n_sub(n, j, X, ldb, coef, j, xj, ldb, 1, st));
-      }
-    }
-    KF_TRY(gemv_t(n, 1, xj, ldb, nullptr, 0, 0, xj, 1, ldb, p->d_m, nrm2 + j, 1, p->gw, st));
-    KF_TRY(normalize_col(n, xj, nrm2 + j, Tref + (int64_t)j * nb + j, drop, p->flags + j, post + j, st));
-  }
-  if (done) KF_HIP(hipEventRecord(done, st));
-  std::vector<double> gram((size_t)nb * nb);
-  std::vector<int32_t> fl((size_t)nb);
-  KF_HIP(hipMemcpyAsync(gram.data(), Tref, sizeof(double) * nb * nb, hipMemcpyDeviceToHost, st));
+  KF_TRY(fetch(T1, (size_t)ld1 * nb, hv.data()));
   KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
   KF_HIP(hipStreamSynchronize(st));
   ref_out.assign((size_t)nb, 0.0);
-  for (int j = 0; j < nb; ++j) ref_out[(size_t)j] = std::sqrt(std::max(gram[(size_t)j * nb + j], 0.0));
+  for (int j = 0; j < nb; ++j) ref_out[(size_t)j] = std::sqrt(std::max(hv[(size_t)lw + j + (size_t)j * ld1], 0.0));
   int cnt = 0;
   for (int j = 0; j < nb; ++j) {
     if (!fl[(size_t)j]) continue;
