@@ -79,7 +79,7 @@ typedef struct kf_options {
                             this fraction since the last check (0: no wait);
                             checks cost O(k^3) in the basis size k */
   int32_t full_reorth;   /* 1: classical Gram-Schmidt twice against the whole
-                            basis; 0: twice against the last two blocks (C is
+                            basis; 0: once against the last two blocks (C is
                             M-self-adjoint, so the filtered block is
                             orthogonal to the older ones in exact arithmetic)
                             then once against the whole basis, a second time
@@ -90,6 +90,13 @@ typedef struct kf_options {
                             is <= drop_tol times its M-norm before is dropped
                             (breakdown test of Algorithm 2.5 with a tolerance);
                             0 selects 1e-10 */
+  double reorth_tol;     /* single-vector blocks with full_reorth 0: the
+                            coefficients against the whole basis are always
+                            computed (they are needed for B^T S B), but
+                            subtracted only when one exceeds reorth_tol times
+                            the column's M-norm, so the basis stays
+                            M-orthonormal to about that level (reported as
+                            kf_result.orth_error); 0 = always subtract */
   int32_t refine;        /* KF_MIXED only: one float64 filter application and
                             Rayleigh-Ritz on the near-interval Ritz block */
   int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
@@ -135,7 +142,7 @@ typedef struct kf_result {
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, refine 1, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-14, refine 1, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning,
  * default stream. */
 void kf_default_options(kf_options* opt);

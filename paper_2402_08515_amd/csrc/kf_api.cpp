@@ -356,19 +356,24 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   // projected-pencil columns [B^T S Q | B^T M Q] with Q = B[:, kb-pn:kb]; the
   // rows below kb give the block's Gram matrix before the pass
   const int ldc = kb + nb;
-  auto full_pass = [&](bool with_pending) -> int {
+  // gated: (one vector) subtract only when a coefficient exceeds reorth_tol
+  // times the column's M-norm; the decision is taken on the device
+  int32_t* gate = p->flags + 32;
+  auto full_pass = [&](bool with_pending, bool gated = false) -> int {
+    const double* cx = coef;
     if (with_pending && pn > 0) {
       const int p0 = kb - pn;
       const double* Q = p->B + (int64_t)p0 * ldb;
       KF_TRY(spmv_cols(p->S, Q, ldb, p->W, n, pn, nullptr, st));
       KF_TRY(gemv_t(n, ldc, p->B, ldb, p->W, pn, n, Q, pn + nb, ldb, p->d_m, coef, ldc, p->gw, st));
       KF_TRY(rr_scatter(kb, p0, pn, coef, ldc, p->H, p->G, p->hcap, st));
-      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef + (int64_t)2 * pn * ldc, ldc, X, ldb, nb, st));
+      cx = coef + (int64_t)2 * pn * ldc;
     } else {
       KF_TRY(gemv_t(n, ldc, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, ldc, p->gw, st));
-      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, coef, ldc, X, ldb, nb, st));
     }
-    if (full_passes) ++*full_passes;
+    if (gated) KF_TRY(reorth_gate(kb, cx, cx + kb, p->opt.reorth_tol, gate, st));
+    KF_TRY(gemv_n_sub(n, kb, p->B, ldb, cx, ldc, X, ldb, nb, st, gated ? gate : nullptr));
+    if (full_passes && !gated) ++*full_passes;
     return KF_OK;
   };
   const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
@@ -401,14 +406,18 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   } else if (kb > 0 && nb == 1) {
     // one vector: its norm after the full pass is the normalisation norm, so
     // the second-pass test and the drop test share one synchronisation
-    KF_TRY(full_pass(true));
+    const bool gated = p->opt.reorth_tol > 0.0;
+    KF_TRY(full_pass(true, gated));
     KF_TRY(finish_cols(Tref, ld1));
     double g1 = 0.0, g2h = 0.0;
+    int32_t gh = 1;
     KF_TRY(fetch(coef + kb + (int64_t)(2 * pn) * ldc, 1, &g1));
     KF_TRY(fetch(nrm2, 1, &g2h));
     KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (gated) KF_HIP(hipMemcpyAsync(&gh, gate, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
+    if (full_passes && gated && gh) ++*full_passes;
     if (fl[0] && g2h < 0.25 * g1) {
       // the column is normalised now: one more pass against the whole basis,
       // dropped if it loses all but drop_tol of its unit norm
@@ -814,6 +823,7 @@ void kf_default_options(kf_options* o) {
   o->target = 0;
   o->max_iters = 0;
   o->drop_tol = 1e-10;
+  o->reorth_tol = 1e-14;
   o->refine = 1;
   o->want_vectors = 0;
   o->index_bytes = 0;
@@ -856,6 +866,8 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.check_every < 1) o.check_every = 1;
   if (!(o.check_growth >= 0.0) || !std::isfinite(o.check_growth)) o.check_growth = 0.0;
   if (!(o.drop_tol > 0)) o.drop_tol = 1e-10;
+  if (!(o.reorth_tol >= 0.0) || !std::isfinite(o.reorth_tol))
+    return fail(KF_EINVAL, "kf_create: reorth_tol must be finite and >= 0");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 

@@ -115,9 +115,13 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
            const double* X2, int n2, int64_t ldx2, const double* m, double* H, int64_t ldh, GemvTWork& wk,
            hipStream_t st);
 
-// X[:, c] -= sum_j Bk[:, j] * H[j + c*ldh], c < nrhs
+// X[:, c] -= sum_j Bk[:, j] * H[j + c*ldh], c < nrhs; skipped entirely when
+// gate (device flag) is given and holds 0
 int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
-               int64_t ldx, int nrhs, hipStream_t st);
+               int64_t ldx, int nrhs, hipStream_t st, const int32_t* gate = nullptr);
+
+// *gate = 1 if max_j |c[j]| (j < k) > tol * sqrt(*g), else 0 (device values)
+int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st);
 
 // Y[:, c] = S X[:, c] (c < ncols), optional row scaling Y[i,c] *= rscale[i]
 int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,

@@ -382,7 +382,8 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int 
 template <int NR, bool SUB>
 __global__ __launch_bounds__(256) void k_gemv_n(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
                                                 const double* __restrict__ H, int64_t ldh, double* X, int64_t ldx,
-                                                int nrhs) {
+                                                int nrhs, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   constexpr int JT = 128;
   __shared__ double hs[JT * NR];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -872,17 +873,41 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   return KF_OK;
 }
 
+// The gate of the selective full subtraction: one workgroup, max |c_j|.
+__global__ __launch_bounds__(256) void k_reorth_gate(int k, const double* __restrict__ c, const double* __restrict__ g,
+                                                     double tol, int32_t* __restrict__ gate) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) mx = fmax(mx, fabs(c[j]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double nrm = sqrt(fmax(*g, 0.0));
+    // a non-finite coefficient or norm always subtracts (and is caught later)
+    *gate = (mx <= tol * nrm) ? 0 : 1;
+  }
+}
+
+int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(256), 0, st, k, c, g, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
 int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
-               int64_t ldx, int nrhs, hipStream_t st) {
+               int64_t ldx, int nrhs, hipStream_t st, const int32_t* gate) {
   if (k <= 0 || nrhs <= 0) return KF_OK;
   const int NR = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8);
   const dim3 grid(ceil_div64(n, 256), ceil_div64(nrhs, NR));
   if (NR == 1)
-    hipLaunchKernelGGL((k_gemv_n<1, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+    hipLaunchKernelGGL((k_gemv_n<1, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
   else if (NR == 4)
-    hipLaunchKernelGGL((k_gemv_n<4, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+    hipLaunchKernelGGL((k_gemv_n<4, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
   else
-    hipLaunchKernelGGL((k_gemv_n<8, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs);
+    hipLaunchKernelGGL((k_gemv_n<8, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
@@ -892,10 +917,10 @@ int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, in
   if (nc <= 0) return KF_OK;
   if (nc <= 8) {
     const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
-    hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+    hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
   } else {
     const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 32));
-    hipLaunchKernelGGL((k_gemv_n<32, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
+    hipLaunchKernelGGL((k_gemv_n<32, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
   }
   KF_HIP(hipGetLastError());
   return KF_OK;

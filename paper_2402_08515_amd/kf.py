@@ -51,6 +51,7 @@ class OptionsT(C.Structure):
         ("target", C.c_int32),
         ("max_iters", C.c_int32),
         ("drop_tol", C.c_double),
+        ("reorth_tol", C.c_double),
         ("refine", C.c_int32),
         ("want_vectors", C.c_int32),
         ("index_bytes", C.c_int32),
@@ -277,7 +278,7 @@ def _take_result(res, n: int) -> SolveResult:
 
 def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
-             autotune=False):
+             autotune=False, reorth_tol=None):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -287,6 +288,8 @@ def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=Fals
     opt.target = target
     opt.max_iters = max_iters
     opt.drop_tol = drop_tol
+    if reorth_tol is not None:
+        opt.reorth_tol = reorth_tol
     opt.refine = int(refine)
     opt.want_vectors = int(want_vectors)
     opt.index_bytes = index_bytes

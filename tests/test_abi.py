@@ -87,6 +87,8 @@ def test_create_rejects_bad_parameters(small):
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, float("nan"), 10))
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 0))
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, index_bytes=3))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, reorth_tol=-1.0))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, reorth_tol=float("inf")))
 
 
 def test_last_error_is_a_string():

@@ -41,12 +41,12 @@ def grid2d():
     return P, tau, L, w, V0, ref
 
 
-@pytest.mark.parametrize("full_reorth", [False, True])
-def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth):
+@pytest.mark.parametrize("full_reorth,reorth_tol", [(False, None), (False, 0.0), (True, None)])
+def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth, reorth_tol):
     kf = _kf()
     P, tau, L, w, V0, ref = grid2d
-    print(f"case grid2d_64 fp64 solve full_reorth={full_reorth}", flush=True)
-    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, full_reorth=full_reorth)
+    print(f"case grid2d_64 fp64 solve full_reorth={full_reorth} reorth_tol={reorth_tol}", flush=True)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, full_reorth=full_reorth, reorth_tol=reorth_tol)
     got = prob.solve(V0, m_max=40, tol=1e-9)
     tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
     assert got.basis_size == 40 and got.krylov_steps == 39
@@ -190,4 +190,7 @@ def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
     assert got.omega2.size == tgt == 110
     assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
     assert got.residual.max() <= 1e-6
-    assert got.orth_error < 1e-10
+    # the full subtraction is skipped while every coefficient is below
+    # 1e-14 of the column norm: the basis stays orthonormal to that level
+    assert got.orth_error < 1e-12
+    print("orth_error", got.orth_error, "full passes", got.full_passes, "of", got.krylov_steps)
