@@ -109,7 +109,12 @@ typedef struct kf_options {
   int32_t autotune;      /* 1: kf_create times the fused step with every
                             combination of xcd_remap, nt_loads and (when both
                             fit) 2- and 4-byte column indices and keeps the
-                            fastest (kf_get_tuning reports it) */
+                            fastest (kf_get_tuning reports it); blocks of
+                            b > 1 vectors also get lanes_per_row timed on
+                            first use */
+  int32_t lanes_per_row; /* lanes of a wavefront sharing one row in the fused
+                            step for b > 1 (1, 2 or 4, capped at b); 0 =
+                            16 bytes of the block row per lane */
   void* stream;          /* hipStream_t */
 } kf_options;
 
@@ -143,7 +148,7 @@ typedef struct kf_result {
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
  * drop_tol 1e-10, reorth_tol 1e-14, refine 1, no vectors, automatic index width, XCD remap on,
- * cached operator loads, no autotuning,
+ * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);
 

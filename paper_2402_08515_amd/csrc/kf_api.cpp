@@ -728,27 +728,52 @@ int distinct_count(const std::vector<double>& acc, int b) {
   return cnt;
 }
 
-// Time `reps` fused steps (one vector) of operator A with the given XCD
-// mapping; returns microseconds per step.
-int time_variant(kf_problem* p, const SellOp& A, int remap, int reps, double* us) {
+// Time `reps` fused steps of operator A for a block of bk vectors with the
+// given XCD mapping; returns microseconds per step.
+int time_variant(kf_problem* p, const SellOp& A, StepBufs& sb, int remap, int reps, double* us, int bk = 1) {
   hipStream_t st = p->st;
-  KF_TRY(ensure_step_buffers(p, p->sb, 1, A.val_bytes));
-  KF_HIP(hipMemsetAsync(p->sb.Y0, 0, (size_t)p->n * A.val_bytes, st));
-  KF_HIP(hipMemsetAsync(p->sb.Y1, 0, (size_t)p->n * A.val_bytes, st));
-  KF_HIP(hipMemsetAsync(p->sb.R, 0, (size_t)p->n * A.val_bytes, st));
+  KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
+  const size_t bytes = (size_t)p->n * bk * A.val_bytes;
+  KF_HIP(hipMemsetAsync(sb.Y0, 0, bytes, st));
+  KF_HIP(hipMemsetAsync(sb.Y1, 0, bytes, st));
+  KF_HIP(hipMemsetAsync(sb.R, 0, bytes, st));
   for (int w = 0; w < 3; ++w)
-    KF_TRY(launch_leapfrog(A, 1, kMid, p->sb.Y1, p->sb.Y0, p->sb.Y0, p->sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+    KF_TRY(launch_leapfrog(A, bk, kMid, sb.Y1, sb.Y0, sb.Y0, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
   KF_HIP(hipEventRecord(p->ev[0], st));
   for (int r = 0; r < reps; ++r) {
-    void* a = (r & 1) ? p->sb.Y0 : p->sb.Y1;
-    void* b = (r & 1) ? p->sb.Y1 : p->sb.Y0;
-    KF_TRY(launch_leapfrog(A, 1, kMid, a, b, b, p->sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+    void* a = (r & 1) ? sb.Y0 : sb.Y1;
+    void* b = (r & 1) ? sb.Y1 : sb.Y0;
+    KF_TRY(launch_leapfrog(A, bk, kMid, a, b, b, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
   }
   KF_HIP(hipEventRecord(p->ev[1], st));
   KF_HIP(hipEventSynchronize(p->ev[1]));
   float ms = 0.f;
   KF_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
   *us = 1e3 * ms / reps;
+  return KF_OK;
+}
+
+// Block widths above 1: the lanes sharing a row (1, 2 or 4) are timed on
+// the problem's operator the first time a width is used (autotune on).
+// Called outside the timed regions of a solve (it records ev[0], ev[1]).
+int tune_block(kf_problem* p, SellOp& A, StepBufs& sb, int bk) {
+  if (!p->opt.autotune || bk < 2) return KF_OK;
+  int lb = 0;
+  while ((1 << lb) < bk && lb < 4) ++lb;
+  if (A.lpr_tuned & (1 << lb)) return KF_OK;
+  double best = 1e300;
+  int best_l = 1;
+  for (int l = 1; l <= std::min(bk, 4); l *= 2) {
+    A.lpr[lb] = l;
+    double us = 0.0;
+    KF_TRY(time_variant(p, A, sb, p->opt.xcd_remap, 10, &us, bk));
+    if (us < best) {
+      best = us;
+      best_l = l;
+    }
+  }
+  A.lpr[lb] = best_l;
+  A.lpr_tuned |= 1 << lb;
   return KF_OK;
 }
 
@@ -767,7 +792,7 @@ int autotune(kf_problem* p, DevCsr& dc, const double* d_scale) {
       for (int remap = 0; remap <= 1; ++remap) {
         A.nt_loads = nt;
         double us = 0;
-        int rc = time_variant(p, A, remap, 20, &us);
+        int rc = time_variant(p, A, p->sb, remap, 20, &us);
         if (rc) {
           free_sell(alt);
           return rc;
@@ -830,6 +855,7 @@ void kf_default_options(kf_options* o) {
   o->xcd_remap = 1;
   o->nt_loads = 0;
   o->autotune = 0;
+  o->lanes_per_row = 0;
   o->stream = nullptr;
 }
 
@@ -868,6 +894,8 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (!(o.drop_tol > 0)) o.drop_tol = 1e-10;
   if (!(o.reorth_tol >= 0.0) || !std::isfinite(o.reorth_tol))
     return fail(KF_EINVAL, "kf_create: reorth_tol must be finite and >= 0");
+  if (o.lanes_per_row != 0 && o.lanes_per_row != 1 && o.lanes_per_row != 2 && o.lanes_per_row != 4)
+    return fail(KF_EINVAL, "kf_create: lanes_per_row must be 0, 1, 2 or 4");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 
@@ -917,6 +945,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     for (hipEvent_t& e : p->ev)
       if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
     if (!rc && o.autotune) rc = autotune(p, dc, d_scale);
+    for (int l = 0; l < 5; ++l) p->A.lpr[l] = p->A64.lpr[l] = o.lanes_per_row;
     dfree(d_scale);
     if (rc) break;
   } while (false);
@@ -1079,6 +1108,7 @@ int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b) {
   if (!p || !x || !y) return fail(KF_EINVAL, "kf_apply_filter: NULL argument");
   if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_apply_filter: b must lie in [1, 16]");
   const int bk = pow2ceil(b);
+  KF_TRY(tune_block(p, p->A, p->sb, bk));
   return run_filter(p, p->A, p->sb, x, b, 1, b, bk, y, b, 1, b, p->w);
 }
 
@@ -1133,6 +1163,7 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   s.b = b;
   s.bk = pow2ceil(b);
   s.m_max = m_max;
+  KF_TRY(tune_block(p, p->A, p->sb, s.bk));
   s.tol = tol;
   hipStream_t st = p->st;
   KF_TRY(ensure_basis(p, m_max + s.bk));

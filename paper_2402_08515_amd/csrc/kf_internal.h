@@ -46,7 +46,12 @@ struct SellOp {
   void* idx = nullptr;
   int32_t max_width = 0;
   int nt_loads = 0;  // 1: stream the matrix with non-temporal loads in the fused step
+  int lpr[5] = {0, 0, 0, 0, 0};  // lanes per row of the fused step for blocks 1..16 (0: default)
+  int lpr_tuned = 0;             // bit l: lpr[l] was chosen by timing
 };
+
+// Lanes that share one row in the fused step for block width b.
+int lanes_per_row(const SellOp& A, int b);
 
 void free_sell(SellOp& op);
 

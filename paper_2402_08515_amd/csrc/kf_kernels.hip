@@ -112,61 +112,72 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, int32_t nslices, c
 }
 
 // ------------------------------------------------------------ fused leapfrog
-template <typename T, typename IT, int B, int MODE, bool NT>
+// One step for a block of B vectors.  LPR lanes share a row, each owning B/LPR
+// consecutive vector columns, so a wavefront covers 64/LPR rows of a slice and
+// the gather of a neighbour's block row is LPR adjacent 16-byte pieces (LPR = 1:
+// one lane per row with the whole block row in registers).
+template <typename T, typename IT, int B, int MODE, bool NT, int LPR>
 __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
                                                   const T* __restrict__ val, const IT* __restrict__ idx,
                                                   const T* __restrict__ cur, const T* prev, T* out,
                                                   T* __restrict__ acc, double* __restrict__ rout, int64_t rs,
                                                   int64_t cs, int bout, T w0, T w, int remap) {
   constexpr bool relative = sizeof(IT) == 2;
+  constexpr int BL = B / LPR;   // vector columns per lane
+  constexpr int RW = 64 / LPR;  // rows per wavefront
   const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int slice = wg * 4 + (threadIdx.x >> 6);
+  const int gw = wg * 4 + (threadIdx.x >> 6);  // global wavefront
   const int lane = threadIdx.x & 63;
+  const int slice = (gw * RW) >> 6;
   if (slice >= nslices) return;
-  const int row = slice * 64 + lane;
+  const int rin = ((gw * RW) & 63) + lane / LPR;  // row within the slice
+  const int part = lane % LPR;
+  const int row = slice * 64 + rin;
   if (row >= n) return;
   const int64_t base = sptr[slice];
   const int width = (int)((sptr[slice + 1] - base) >> 6);
-  const T* __restrict__ vp = val + base + lane;
-  const IT* __restrict__ ip = idx + base + lane;
-  T sum[B];
+  const T* __restrict__ vp = val + base + rin;
+  const IT* __restrict__ ip = idx + base + rin;
+  const int col0 = part * BL;
+  T sum[BL];
 #pragma unroll
-  for (int j = 0; j < B; ++j) sum[j] = (T)0;
+  for (int j = 0; j < BL; ++j) sum[j] = (T)0;
 #pragma unroll 4
   for (int q = 0; q < width; ++q) {
     const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
     const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
     const int c = relative ? row + (int)ci : (int)ci;
-    const Row<T, B> x = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
+    const Row<T, BL> x = *reinterpret_cast<const Row<T, BL>*>(cur + (int64_t)c * B + col0);
 #pragma unroll
-    for (int j = 0; j < B; ++j) sum[j] = fma(a, x.v[j], sum[j]);
+    for (int j = 0; j < BL; ++j) sum[j] = fma(a, x.v[j], sum[j]);
   }
-  const Row<T, B> yc = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)row * B);
-  Row<T, B> yp;
+  const int64_t off = (int64_t)row * B + col0;
+  const Row<T, BL> yc = *reinterpret_cast<const Row<T, BL>*>(cur + off);
+  Row<T, BL> yp;
   if (MODE & kFirst) {
     yp = yc;
   } else {
-    yp = *reinterpret_cast<const Row<T, B>*>(prev + (int64_t)row * B);
+    yp = *reinterpret_cast<const Row<T, BL>*>(prev + off);
   }
-  Row<T, B> nx;
+  Row<T, BL> nx;
 #pragma unroll
-  for (int j = 0; j < B; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
-  if (!(MODE & kLast)) *reinterpret_cast<Row<T, B>*>(out + (int64_t)row * B) = nx;
-  Row<T, B> r;
+  for (int j = 0; j < BL; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
+  if (!(MODE & kLast)) *reinterpret_cast<Row<T, BL>*>(out + off) = nx;
+  Row<T, BL> r;
   if (MODE & kFirst) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
+    for (int j = 0; j < BL; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
   } else {
-    r = *reinterpret_cast<const Row<T, B>*>(acc + (int64_t)row * B);
+    r = *reinterpret_cast<const Row<T, BL>*>(acc + off);
 #pragma unroll
-    for (int j = 0; j < B; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
+    for (int j = 0; j < BL; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
   }
   if (MODE & kLast) {
 #pragma unroll
-    for (int j = 0; j < B; ++j)
-      if (j < bout) rout[(int64_t)row * rs + (int64_t)j * cs] = (double)r.v[j];
+    for (int j = 0; j < BL; ++j)
+      if (col0 + j < bout) rout[(int64_t)row * rs + (int64_t)(col0 + j) * cs] = (double)r.v[j];
   } else {
-    *reinterpret_cast<Row<T, B>*>(acc + (int64_t)row * B) = r;
+    *reinterpret_cast<Row<T, BL>*>(acc + off) = r;
   }
 }
 
@@ -576,10 +587,10 @@ __global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __rest
 }
 
 // ---- host-side dispatch helpers
-template <typename T, typename IT, int B, bool NT>
+template <typename T, typename IT, int B, bool NT, int LPR>
 int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
-  const int grid = ceil_div64(A.nslices, 4);
+  const int grid = ceil_div64((int64_t)A.nslices * LPR, 4);
   const T* v = static_cast<const T*>(A.val);
   const IT* ix = static_cast<const IT*>(A.idx);
   const T* c = static_cast<const T*>(cur);
@@ -588,19 +599,19 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   T* a = static_cast<T*>(acc);
   switch (mode) {
     case kMid:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr,
-                         v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     case kFirst:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     case kLast:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
     default:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
       break;
   }
@@ -608,12 +619,23 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   return KF_OK;
 }
 
+template <typename T, typename IT, int B, int LPR>
+int launch_lf_bl(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                 int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+  if (A.nt_loads)
+    return launch_lf_bn<T, IT, B, true, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+  return launch_lf_bn<T, IT, B, false, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+}
+
 template <typename T, typename IT, int B>
 int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                 int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
-  if (A.nt_loads)
-    return launch_lf_bn<T, IT, B, true>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-  return launch_lf_bn<T, IT, B, false>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+  const int lpr = lanes_per_row(A, B);
+  if (B >= 4 && lpr == 4)
+    return launch_lf_bl<T, IT, B, (B >= 4 ? 4 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+  if (B >= 2 && lpr == 2)
+    return launch_lf_bl<T, IT, B, (B >= 2 ? 2 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+  return launch_lf_bl<T, IT, B, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
 }
 
 template <typename T, typename IT>
@@ -630,6 +652,7 @@ int launch_lf_t(const SellOp& A, int b, int mode, const void* cur, const void* p
 }
 
 }  // namespace
+
 
 void free_sell(SellOp& op) {
   if (op.slice_ptr) (void)hipFree(op.slice_ptr);
@@ -713,6 +736,18 @@ int build_sell(int32_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d
   KF_HIP(hipStreamSynchronize(st));
   (void)nnz;
   return KF_OK;
+}
+
+int lanes_per_row(const SellOp& A, int b) {
+  int lb = 0;
+  while ((1 << lb) < b && lb < 4) ++lb;
+  int l = A.lpr[lb];
+  if (l <= 0) {
+    // default: 16 bytes of the block row per lane
+    l = std::max(1, b * A.val_bytes / 16);
+  }
+  l = std::min(l, std::min(b, 4));
+  return l >= 4 ? 4 : (l >= 2 ? 2 : 1);
 }
 
 int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,

@@ -159,3 +159,24 @@ def test_autotuned_and_cached_load_variants_match_oracle(precision):
             assert Q.tuning()["nt_loads"] == 0 and Q.tuning()["us_per_step"] == 0
             y = Q.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
             assert np.abs(y - ref).max() / np.abs(ref).max() <= tol, (ib, remap)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("b", [2, 4, 8, 16])
+@pytest.mark.parametrize("lpr", [1, 2, 4])
+def test_lanes_per_row_variants_match_oracle(precision, b, lpr):
+    """Blocks of b vectors with 1, 2 or 4 lanes sharing a row (capped at b),
+    on a ragged cube (last slice partly empty)."""
+    import torch
+
+    kf = _kf()
+    S, m, tau, _, omin, omax = _case(3, 11)
+    L = 7
+    w = oracle.discrete_weights(omin, omax, tau, L)
+    X = start_block(S.shape[0], b, 30 + b)
+    ref = oracle.apply_filter(S, m, tau, w, X)
+    print(f"case lanes_per_row={lpr} b={b} {precision}", flush=True)
+    P = kf.Problem(S, m, omin, omax, tau, L, precision=precision, lanes_per_row=lpr)
+    y = P.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert np.abs(y - ref).max() / np.abs(ref).max() <= tol

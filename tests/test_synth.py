@@ -46,3 +46,28 @@ def test_start_block_is_seeded():
     b = start_block(100, 3, 5)
     assert a.shape == (100, 3) and np.array_equal(a, b)
     assert not np.array_equal(a, start_block(100, 3, 6))
+
+
+def test_horn_mesh_is_valid_and_matches_the_geometry():
+    """Small horn: no tetrahedron turns over under the jitter, the mesh
+    volume approaches the solid of revolution (the disk map loses a little
+    of the circle), the Neumann stiffness annihilates constants, and every
+    neighbour lies within one layer of ids (16-bit offsets fit)."""
+    import scipy.integrate as si
+
+    from synth.horn import horn_mesh, horn_pencil, radius, tet_volumes
+
+    v0, t4, b = horn_mesh(8, 80, jitter=0.0)
+    v1, _, _ = horn_mesh(8, 80)
+    a0, a1 = tet_volumes(v0, t4), tet_volumes(v1, t4)
+    assert np.all(np.sign(a0) == np.sign(a1)) and np.all(a0 != 0)
+    exact = si.quad(lambda z: np.pi * radius(np.array(z)) ** 2, 0.0, 1.7, points=[1.5])[0]
+    assert abs(np.abs(a1).sum() - exact) / exact < 0.01
+    S, m = horn_pencil(8, 80)
+    assert m.min() > 0 and abs(m.sum() - np.abs(a1).sum()) < 1e-15
+    assert np.abs(S @ np.ones(S.shape[0])).max() < 1e-12 * S.diagonal().max()
+    assert abs(S - S.T).max() < 1e-15 * S.diagonal().max()
+    rows = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr))
+    assert np.abs(S.indices - rows).max() <= 9 * 9 + 9 + 1
+    # jittered vertices stay off the wall: the wall and caps are unmoved
+    assert np.array_equal(v0[b], v1[b]) and not np.array_equal(v0[~b], v1[~b])
