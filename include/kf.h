@@ -112,6 +112,11 @@ typedef struct kf_options {
                             fastest (kf_get_tuning reports it); blocks of
                             b > 1 vectors also get lanes_per_row timed on
                             first use */
+  int32_t batch_workers; /* batches: host threads that drive the members'
+                            Gram-Schmidt and Rayleigh-Ritz between two batched
+                            filter launches, each member on a stream of its
+                            own (0 = min(8, P); 1 = one after another on the
+                            batch stream) */
   int32_t lanes_per_row; /* lanes of a wavefront sharing one row in the fused
                             step for b > 1 (1, 2 or 4, capped at b); 0 =
                             16 bytes of the block row per lane */

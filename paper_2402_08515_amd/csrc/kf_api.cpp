@@ -17,6 +17,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "../../include/kf.h"
@@ -84,10 +86,14 @@ struct kf_problem {
   int basis_cols = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double tuned_us = 0.0;
+  // batch members with their own stream (concurrent projection work)
+  bool own_stream = false;
+  hipEvent_t sync_ev = nullptr;
 };
 
 struct kf_batch {
   int P = 0;
+  int workers = 1;  // host threads driving the members' projection work
   std::vector<kf_problem*> probs;
   hipStream_t st = nullptr;
   SellOp A;                  // stacked block-diagonal operator, stepping precision
@@ -831,6 +837,11 @@ void free_problem(kf_problem* p) {
   free_eig(p->ew);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  if (p->sync_ev) (void)hipEventDestroy(p->sync_ev);
+  if (p->own_stream && p->st) {
+    (void)hipStreamSynchronize(p->st);
+    (void)hipStreamDestroy(p->st);
+  }
   delete p;
 }
 
@@ -856,6 +867,7 @@ void kf_default_options(kf_options* o) {
   o->nt_loads = 0;
   o->autotune = 0;
   o->lanes_per_row = 0;
+  o->batch_workers = 0;
   o->stream = nullptr;
 }
 
@@ -894,6 +906,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (!(o.drop_tol > 0)) o.drop_tol = 1e-10;
   if (!(o.reorth_tol >= 0.0) || !std::isfinite(o.reorth_tol))
     return fail(KF_EINVAL, "kf_create: reorth_tol must be finite and >= 0");
+  if (o.batch_workers < 0) return fail(KF_EINVAL, "kf_create: batch_workers must be >= 0");
   if (o.lanes_per_row != 0 && o.lanes_per_row != 1 && o.lanes_per_row != 2 && o.lanes_per_row != 4)
     return fail(KF_EINVAL, "kf_create: lanes_per_row must be 0, 1, 2 or 4");
   HostCsr h;
@@ -1449,6 +1462,11 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
   kf_batch* bt = new (std::nothrow) kf_batch();
   if (!bt) return fail(KF_ENOMEM, "kf_create_batch: host allocation");
   bt->P = P;
+  if (o.batch_workers < 0) {
+    delete bt;
+    return fail(KF_EINVAL, "kf_create_batch: batch_workers must be >= 0");
+  }
+  bt->workers = o.batch_workers > 0 ? std::min<int>(o.batch_workers, P) : std::min<int>(8, P);
   int rc = KF_OK;
   do {
     if (hipStreamCreate(&bt->st) != hipSuccess) {
@@ -1472,6 +1490,20 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
         break;
       }
       bt->probs.push_back(pq);
+      if (bt->workers > 1) {
+        // the member's Gram-Schmidt and Rayleigh-Ritz run on a stream of its
+        // own so that members proceed concurrently between filter launches
+        hipStream_t ms = nullptr;
+        if (hipStreamCreateWithFlags(&ms, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&pq->sync_ev, hipEventDisableTiming) != hipSuccess) {
+          if (ms) (void)hipStreamDestroy(ms);
+          rc = fail(KF_EHIP, "kf_create_batch: member stream creation failed");
+          break;
+        }
+        (void)hipStreamSynchronize(bt->st);  // set-up work of the member was queued on the batch stream
+        pq->st = ms;
+        pq->own_stream = true;
+      }
       HostCsr h;
       rc = fetch_csr(&d.S, d.m_diag, h);
       if (rc) break;
@@ -1597,16 +1629,52 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
       bt->h_tb.bout[q] = bk;
     }
     if (!any) break;
+    const bool par = bt->workers > 1;
+    if (par) {
+      // the filter reads the members' newest basis columns
+      for (int q = 0; q < bt->P; ++q) {
+        if (!bt->h_tb.active[q]) continue;
+        kf_problem* p = bt->probs[(size_t)q];
+        KF_HIP(hipEventRecord(p->sync_ev, p->st));
+        KF_HIP(hipStreamWaitEvent(bt->st, p->sync_ev, 0));
+      }
+    }
     KF_HIP(hipEventRecord(bt->ev[0], bt->st));
     KF_TRY(run_batch_filter(bt, bk));
     KF_HIP(hipEventRecord(bt->ev[1], bt->st));
-    for (int q = 0; q < bt->P; ++q) {
-      if (!bt->h_tb.active[q]) continue;
-      int rc = solve_after_filter(bt->probs[(size_t)q], S[(size_t)q]);
-      if (rc) {
-        set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
-        return rc;
+    std::vector<int> act;
+    for (int q = 0; q < bt->P; ++q)
+      if (bt->h_tb.active[q]) act.push_back(q);
+    if (!par) {
+      for (int q : act) {
+        int rc = solve_after_filter(bt->probs[(size_t)q], S[(size_t)q]);
+        if (rc) {
+          set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
+          return rc;
+        }
       }
+    } else {
+      for (int q : act) KF_HIP(hipStreamWaitEvent(bt->probs[(size_t)q]->st, bt->ev[1], 0));
+      std::atomic<int> next{0};
+      std::vector<int> rcs(act.size(), KF_OK);
+      std::vector<std::string> msgs(act.size());
+      auto work = [&]() {
+        for (int i = next.fetch_add(1); i < (int)act.size(); i = next.fetch_add(1)) {
+          const int q = act[(size_t)i];
+          rcs[(size_t)i] = solve_after_filter(bt->probs[(size_t)q], S[(size_t)q]);
+          if (rcs[(size_t)i]) msgs[(size_t)i] = kf_last_error();
+        }
+      };
+      const int nt = std::min<int>(bt->workers, (int)act.size());
+      std::vector<std::thread> pool;
+      for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+      work();
+      for (std::thread& th : pool) th.join();
+      for (size_t i = 0; i < act.size(); ++i)
+        if (rcs[i]) {
+          set_error("kf_solve_batch: problem " + std::to_string(act[i]) + ": " + msgs[i]);
+          return rcs[i];
+        }
     }
     KF_TRY(elapsed_acc(bt->ev[0], bt->ev[1], t_lf));
   }

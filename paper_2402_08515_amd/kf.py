@@ -58,6 +58,7 @@ class OptionsT(C.Structure):
         ("xcd_remap", C.c_int32),
         ("nt_loads", C.c_int32),
         ("autotune", C.c_int32),
+        ("batch_workers", C.c_int32),
         ("lanes_per_row", C.c_int32),
         ("stream", C.c_void_p),
     ]
@@ -279,7 +280,7 @@ def _take_result(res, n: int) -> SolveResult:
 
 def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
-             autotune=False, reorth_tol=None, lanes_per_row=0):
+             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -298,6 +299,7 @@ def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=Fals
     opt.nt_loads = int(nt_loads)
     opt.autotune = int(autotune)
     opt.lanes_per_row = int(lanes_per_row)
+    opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt
 

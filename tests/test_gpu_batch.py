@@ -50,7 +50,10 @@ def test_batched_filter_matches_oracle(precision, b):
         assert err <= tol, (L, err)
 
 
-def test_batched_solve_equals_member_solves():
+@pytest.mark.parametrize("workers", [1, 0])
+def test_batched_solve_equals_member_solves(workers):
+    """Member projections one after another (workers 1) or on concurrent
+    streams driven by host threads (workers 0 = default pool)."""
     kf = _kf()
     spec = [(2, 24, 15.0, 24.0), (2, 31, 12.0, 20.0), (3, 10, 9.0, 14.0), (2, 40, 25.0, 30.0)]
     members, starts, targets = [], [], []
@@ -64,7 +67,7 @@ def test_batched_solve_equals_member_solves():
         starts.append(start_block(S.shape[0], b, 50 + i))
         targets.append(tgt)
     print(f"case batch solve targets={targets}", flush=True)
-    bt = kf.Batch(members, check_every=1)
+    bt = kf.Batch(members, check_every=1, batch_workers=workers)
     got = bt.solve(starts, m_max=200, tol=1e-9)
     for (S, m, lo, hi, tau, L, tgt), V0, g, (dim, n, _, _) in zip(members, starts, got, spec):
         single = kf.Problem(S, m, lo, hi, tau, L, target=tgt).solve(V0, m_max=200, tol=1e-9)
@@ -88,7 +91,7 @@ def test_batched_solve_mixed_on_jittered_members():
         members.append((S, m, lo, hi, tau, L, int(ref.omega2.size)))
         starts.append(V0)
         refs.append(ref)
-    bt = kf.Batch(members, precision="mixed", check_every=2)
+    bt = kf.Batch(members, precision="mixed", check_every=2, batch_workers=3)
     got = bt.solve(starts, m_max=240, tol=1e-6)
     for g, ref in zip(got, refs):
         assert g.residual.max() <= 1e-6
