@@ -219,6 +219,113 @@ def bench_horn(args):
     print(json.dumps(out))
 
 
+def bench_forms(args):
+    """The project's forms against the plain method on the same problems:
+    the squares of the uneven batch (seed 3; Dirichlet, so every eigenvalue's
+    multiplicity is at most 2 and a block of 4 sees whole eigenspaces), each
+    solved to all eigenpairs in its interval at residual <= tol:
+      plain   float64 stepping, Fourier weights, one problem after another;
+      mixed   float32 stepping + float64 projection, all problems batched;
+      learned the same with the network's weights where the judge accepts
+              them (network trained first, on the spectral range of these
+              squares; training time reported separately).
+    Every accepted eigenvalue is compared with the closed form."""
+    import numpy as np
+    import torch
+
+    from paper_2402_08515_amd import kf
+    from synth import distinct_target, grid_spectrum, power_start, start_block
+    from synth.netinit import init_params
+    from synth.workloads import batch64_problems, filter_samples
+
+    probs = [P for P in batch64_problems() if P.meta["dim"] == 2][: args.forms_count]
+    members, starts, targets, refs = [], [], [], []
+    for P in probs:
+        lam = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
+        tau, L = kf.time_step_rule(lam, P.omega_min)
+        tgt, vals, mult = distinct_target(grid_spectrum(2, P.meta["n"]), P.omega_min, P.omega_max, P.block)
+        members.append((P.S, P.m, P.omega_min, P.omega_max, tau, L, tgt, lam))
+        starts.append(start_block(P.n, P.block, P.seed))
+        targets.append(tgt)
+        refs.append(np.repeat(vals, np.minimum(mult, P.block)))
+    print(f"[bench] forms: {len(probs)} squares, n in [{min(p.n for p in probs)}, {max(p.n for p in probs)}], "
+          f"targets {sum(targets)}", file=sys.stderr, flush=True)
+
+    def score(res):
+        found = sum(min(r.omega2.size, t) for r, t in zip(res, targets))
+        errs = [np.max(np.abs(r.omega2 - ref) / ref) for r, ref, t in zip(res, refs, targets)
+                if r.omega2.size == t and t > 0]
+        return int(found), float(max(errs)) if errs else None
+
+    mm = args.m_max
+    # plain float64, one by one
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, check_growth=0.1).solve(V0, m_max=mm,
+                                                                                              tol=args.tol)
+             for (S, m, lo, hi, tau, L, tgt, lam), V0 in zip(members, starts)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # mixed, batched
+    opts = dict(precision="mixed", check_every=2, check_growth=0.1)
+    bt = kf.Batch([x[:7] for x in members], **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mixed = bt.solve(starts, m_max=mm, tol=args.tol)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    # learned weights, mixed, batched
+    lams = [x[7] for x in members]
+    train = filter_samples(args.mlp_samples, stream=0, lam_range=(0.9 * min(lams), 1.1 * max(lams)))
+    net = kf.Mlp(init_params(4).astype(np.float32))
+    rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
+    order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
+    t0 = time.perf_counter()
+    net.train(train, order, args.mlp_epochs, 256, 1e-3)
+    t_train = time.perf_counter() - t0
+    bt2 = kf.Batch([x[:7] for x in members], **opts)
+    used = 0
+    for q, (S, m, lo, hi, tau, L, tgt, lam) in enumerate(members):
+        if L <= 512:
+            w, u, jl, jf = net.weights(lo, hi, tau, lam, L)
+            bt2.set_weights(q, w)
+            used += int(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    learned = bt2.solve(starts, m_max=mm, tol=args.tol)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    rows = {}
+    for name, res, t in (("plain_fp64_one_by_one", plain, t_plain), ("mixed_batched", mixed, t_mixed),
+                         ("learned_mixed_batched", learned, t_learned)):
+        found, err = score(res)
+        rows[name] = {"seconds": t, "pairs": found, "max_rel_err_vs_closed_form": err,
+                      "krylov_steps": int(sum(r.krylov_steps for r in res)),
+                      "dof_steps": float(sum(P.n * r.leapfrog_vector_steps for P, r in zip(probs, res)))}
+        print(f"[bench] {name}: {t:.2f}s pairs {found}/{sum(targets)} max err {err}", file=sys.stderr, flush=True)
+    rows["learned_mixed_batched"]["members_with_learned_weights"] = used
+    rows["learned_mixed_batched"]["train_seconds"] = t_train
+    out = {
+        "metric": METRIC,
+        "value": t_learned,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": t_learned * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-step/f64-proj",
+        "data": "synthetic",
+        "config": {"workload": f"squares of batch64 [:{len(probs)}]", "block": 4, "tol": args.tol, "m_max": mm,
+                   "target_pairs": int(sum(targets)), "parallelism": "1 GPU"},
+        "forms": rows,
+        "speedup_vs_plain": {k: t_plain / v["seconds"] for k, v in rows.items()},
+    }
+    print(json.dumps(out))
+
+
 def bench_learned(args):
     """Learned filter weights: the network is trained on the GPU (50,000
     samples of (omega_min, omega_max, tau, lambda_max) from seed 4 stream 0),
@@ -319,6 +426,7 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=24,
                     help="Krylov iterations per member in the batch benchmark (the full targets need thousands)")
     ap.add_argument("--no-sequential", action="store_true")
+    ap.add_argument("--forms-count", type=int, default=16, help="squares in the forms comparison")
     ap.add_argument("--horn-iters", type=int, default=24,
                     help="block Krylov iterations of the horn benchmark (its interval holds thousands of pairs)")
     ap.add_argument("--probe-traffic", action="store_true",
@@ -337,6 +445,9 @@ def main():
         return
     if args.workload == "horn_4m":
         bench_horn(args)
+        return
+    if args.workload == "forms":
+        bench_forms(args)
         return
 
     import numpy as np

@@ -273,6 +273,11 @@ int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y
 int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t m_max, double tol,
                    kf_result** results);
 
+/* Replace the filter coefficients of member q (as kf_set_weights; exactly the
+ * member's L values, host array) in the batch's device weight table.
+ * Errors: KF_EINVAL (index, count, non-finite values), KF_EHIP. */
+int kf_batch_set_weights(kf_batch* bt, int32_t q, const double* w, int32_t L);
+
 /* ---- learned filter weights -------------------------------------------------
  * Section 2.2 leaves the weight function free and names the goal |beta|
  * large on the sought omega and small elsewhere.  A small network maps the

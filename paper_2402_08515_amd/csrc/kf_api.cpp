@@ -116,6 +116,8 @@ constexpr int kSmall = 4096;
 // offsets of the device scalars in kf_problem::small used by the
 // orthogonalisation (the Rayleigh-Ritz check uses 1024.. and 2048..)
 constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kOne = 4095;
+// mixed mode: refinements tried before a solve with a target gives up
+constexpr int kMaxRefines = 4;
 
 int pow2ceil(int b) {
   int p = 1;
@@ -627,6 +629,29 @@ int eig_orthonormalise(kf_problem* p, double* Z, int nz, double* out, int* r_out
                   p->gw, st));
   }
   KF_TRY(symmetrize(nz, p->Gm, nz, st));
+  {
+    // already M-orthonormal up to E = Z^T M Z - I with |E| <= 1e-8: the
+    // inverse square root is I - E/2 to O(|E|^2) (below rounding), and an
+    // eigen-decomposition of the all-ones spectrum would be one large cluster
+    std::vector<double> Gh((size_t)nz * nz);
+    KF_HIP(hipMemcpyAsync(Gh.data(), p->Gm, sizeof(double) * nz * nz, hipMemcpyDeviceToHost, st));
+    KF_HIP(hipStreamSynchronize(st));
+    double emax = 0.0;
+    for (int j = 0; j < nz; ++j)
+      for (int i = 0; i < nz; ++i) emax = std::max(emax, std::fabs(Gh[(size_t)j * nz + i] - (i == j ? 1.0 : 0.0)));
+    if (emax <= 1e-8) {
+      for (int j = 0; j < nz; ++j)
+        for (int i = 0; i < nz; ++i) {
+          double& g = Gh[(size_t)j * nz + i];
+          g = (i == j ? 1.0 : 0.0) - 0.5 * (g - (i == j ? 1.0 : 0.0));
+        }
+      KF_HIP(hipMemcpyAsync(p->Ysel, Gh.data(), sizeof(double) * nz * nz, hipMemcpyHostToDevice, st));
+      KF_TRY(gemm_nn(n, nz, Z, ld, p->Ysel, nz, out, ld, nz, st));
+      KF_HIP(hipStreamSynchronize(st));
+      *r_out = nz;
+      return KF_OK;
+    }
+  }
   std::vector<double> g, gsel;
   KF_TRY(small_eigen(p, nz, p->Gm, nz, g, [](double) { return true; }, gsel));
   const double gmax = g.empty() ? 0.0 : g.back();
@@ -1154,12 +1179,31 @@ struct SolveState {
   double wsum = 0, t0 = 0, t_lf = 0, t_gs = 0, t_rr = 0, t_ref = 0;
   CheckOut chk;
   std::vector<double> ref;
+  // mixed mode: refinement already run at basis size fin_at
+  CheckOut fin;
+  int fin_at = -1, refines = 0, next_refine = 0;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
   float ms = 0.f;
   KF_HIP(hipEventElapsedTime(&ms, a, b));
   acc += ms * 1e-3;
+  return KF_OK;
+}
+
+// Mixed mode with a target: the float64 refinement of the current Ritz block.
+int solve_refine_now(kf_problem* p, SolveState& s) {
+  hipStream_t st = p->st;
+  KF_HIP(hipEventSynchronize(p->ev[4]));
+  if (s.rr_pending) KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
+  s.rr_pending = false;
+  KF_HIP(hipEventRecord(p->ev[3], st));
+  KF_TRY(refine_mixed(p, s.cur, s.tol, s.chk, p->opt.want_vectors != 0, s.fin));
+  KF_HIP(hipEventRecord(p->ev[4], st));
+  KF_HIP(hipEventSynchronize(p->ev[4]));
+  KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_ref));
+  s.fin_at = s.cur;
+  ++s.refines;
   return KF_OK;
 }
 
@@ -1263,7 +1307,18 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
     KF_TRY(solve_check_now(p, s));
     s.next_check = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));
-    if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) s.done = true;
+    if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
+      if (!s.refine) {
+        s.done = true;
+      } else if (s.cur >= s.next_refine) {
+        // the loop reached the target at its own tolerance: refine now, and
+        // keep iterating (up to kMaxRefines refinements) if some pairs
+        // still miss the requested tolerance
+        KF_TRY(solve_refine_now(p, s));
+        s.next_refine = (int)std::ceil(s.cur * 1.1);
+        if (distinct_count(s.fin.acc_theta, s.b) >= s.target || s.refines >= kMaxRefines) s.done = true;
+      }
+    }
   }
   (void)st;
   return KF_OK;
@@ -1281,11 +1336,8 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   p->basis_cols = s.cur;
   CheckOut fin;
   if (s.refine) {
-    KF_HIP(hipEventRecord(p->ev[3], st));
-    KF_TRY(refine_mixed(p, s.cur, s.tol, chk, p->opt.want_vectors != 0, fin));
-    KF_HIP(hipEventRecord(p->ev[4], st));
-    KF_HIP(hipEventSynchronize(p->ev[4]));
-    KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_ref));
+    if (s.fin_at != s.cur) KF_TRY(solve_refine_now(p, s));
+    fin = s.fin;
   } else if (p->opt.want_vectors) {
     KF_TRY(rr_check(p, s.cur, s.tol, fin, s.margin, true));
   } else {
@@ -1572,6 +1624,21 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     return rc;
   }
   *out = bt;
+  return KF_OK;
+}
+
+int kf_batch_set_weights(kf_batch* bt, int32_t q, const double* w, int32_t L) {
+  if (!bt || q < 0 || q >= bt->P) return fail(KF_EINVAL, "kf_batch_set_weights: bad handle or member index");
+  KF_TRY(kf_set_weights(bt->probs[(size_t)q], w, L));
+  KF_HIP(hipStreamSynchronize(bt->st));
+  const int vb = bt->A.val_bytes;
+  char* row = static_cast<char*>(bt->wtab) + (size_t)q * bt->lmax * vb;
+  if (vb == 8) {
+    KF_HIP(hipMemcpy(row, w, sizeof(double) * L, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> w32(w, w + L);
+    KF_HIP(hipMemcpy(row, w32.data(), sizeof(float) * L, hipMemcpyHostToDevice));
+  }
   return KF_OK;
 }
 

@@ -129,6 +129,7 @@ _SIGNATURES = {
                                 C.POINTER(C.c_double)]),
     "kf_create_batch": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(OptionsT), C.POINTER(C.c_void_p)]),
     "kf_destroy_batch": (C.c_int, [C.c_void_p]),
+    "kf_batch_set_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     "kf_batch_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_solve_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_void_p]),
     "kf_mlp_param_count": (C.c_int32, []),
@@ -336,6 +337,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_weights(self, q: int, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(lib().kf_batch_set_weights(self._h, int(q), _ptr(w), int(w.size)))
 
     def apply_filter(self, xs):
         """ys[p] = C_p xs[p] for device blocks xs[p] of shape (n_p, b),

@@ -163,14 +163,14 @@ def workload(name: str) -> Problem:
 WORKLOADS = ("grid2d_64", "grid3d_96", "horn_4m", "batch64", "grid3d_128")
 
 
-def filter_samples(count: int, seed: int = 4, stream: int = 0) -> np.ndarray:
+def filter_samples(count: int, seed: int = 4, stream: int = 0, lam_range=(5e4, 3e5)) -> np.ndarray:
     """(count, 4) rows (omega_min, omega_max, tau, lambda_max) for the learned
-    filter weights: lambda_max log-uniform in [5e4, 3e5] (the spectral bound
-    of the 3D grids of the workloads), tau = 0.9*2/sqrt(lambda_max),
-    omega_min ~ U[5, 50], width ~ U[5, 20].  Stream 0 of the seed trains,
-    stream 1 evaluates."""
+    filter weights: lambda_max log-uniform in lam_range (default [5e4, 3e5],
+    the spectral bound of the 3D grids of the workloads),
+    tau = 0.9*2/sqrt(lambda_max), omega_min ~ U[5, 50], width ~ U[5, 20].
+    Stream 0 of the seed trains, stream 1 evaluates."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[stream])
-    lam = np.exp(rng.uniform(np.log(5e4), np.log(3e5), size=count))
+    lam = np.exp(rng.uniform(np.log(lam_range[0]), np.log(lam_range[1]), size=count))
     tau = 0.9 * 2.0 / np.sqrt(lam)
     omin = rng.uniform(5.0, 50.0, size=count)
     width = rng.uniform(5.0, 20.0, size=count)

@@ -98,3 +98,24 @@ def test_batched_solve_mixed_on_jittered_members():
         err = np.array([np.min(np.abs(g.omega2 - v)) / v for v in ref.omega2])
         print("member per-pair relative error vs FP64 oracle:", np.array2string(err, precision=2))
         assert err.max() <= 1e-6
+
+
+def test_member_weights_can_be_replaced():
+    """kf_batch_set_weights: the batched filter of a member follows its new
+    coefficients (here the Fourier weights of another interval)."""
+    import torch
+
+    kf = _kf()
+    mem = _members(SPEC[:3])
+    bt = kf.Batch([(S, m, lo, hi, tau, L, 0) for S, m, lo, hi, tau, L in mem], precision="fp64")
+    S, m, lo, hi, tau, L = mem[1]
+    w_new = oracle.discrete_weights(0.5 * lo, 0.8 * hi, tau, L)
+    bt.set_weights(1, w_new)
+    xs = [start_block(M[0].shape[0], 2, 200 + i) for i, M in enumerate(mem)]
+    ys = bt.apply_filter([torch.from_numpy(x).cuda() for x in xs])
+    for i, ((S, m, lo, hi, tau, L), x, y) in enumerate(zip(mem, xs, ys)):
+        w = w_new if i == 1 else oracle.discrete_weights(lo, hi, tau, L)
+        ref = oracle.apply_filter(S, m, tau, w, x)
+        assert np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max() <= 1e-12
+    with pytest.raises(kf.KfError):
+        bt.set_weights(1, w_new[:-1])
