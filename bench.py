@@ -512,7 +512,7 @@ def main():
     per_launch_s = t_lf / max(launches, 1)
     bytes_step = algorithmic_bytes_per_step(P.n, P.nnz, P.block, vb)
     achieved = bytes_step / per_launch_s / 1e9
-    src = open(os.path.join(ROOT, "paper_2402_08515_amd", "csrc", "kf_kernels.hip"), "rb").read()
+    src = open(os.path.join(ROOT, "paper_2402_08515_amd", "csrc", "kf_step.hip"), "rb").read()
     traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(), P.name)
 
     out = {

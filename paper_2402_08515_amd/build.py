@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkf.so")
-SOURCES = ["kf_kernels.hip", "kf_eig.hip", "kf_mlp.hip", "kf_api.cpp"]
+SOURCES = ["kf_step.hip", "kf_blas.hip", "kf_eig.hip", "kf_mlp.hip", "kf_api.cpp"]
 ARCH = "gfx950"
 
 

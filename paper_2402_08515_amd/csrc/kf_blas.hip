@@ -1,0 +1,549 @@
+// Float64 kernels around the hot path: tall-skinny products for M-inner
+// Gram-Schmidt and the projected pencil (Section 2.1 eq. projevp; the
+// orthogonalisation loop of Algorithm 2.5), SpMV with S, and the residuals of
+// Section 2.4 (eq. res).  All reductions are two-pass with a fixed summation
+// order (bitwise repeatable).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kf_internal.h"
+
+namespace kf {
+
+namespace {
+
+inline int ceil_div64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber
+// them so that each XCD receives one contiguous range of row slices and its
+// L2 keeps the neighbouring rows it gathers.
+__device__ __forceinline__ int xcd_map(int i, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = i & 7, t = i >> 3;
+  return (x < r) ? x * (q + 1) + t : r * (q + 1) + (x - r) * q + t;
+}
+
+template <typename T, int B>
+struct alignas((B * sizeof(T)) >= 16 ? 16 : (B * sizeof(T))) Row {
+  T v[B];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ------------------------------------------------------- tall-skinny float64
+// Stage 1 of H = Bk^T diag(w) X: one workgroup per (row chunk, group of 64
+// basis columns); the weighted X chunk sits in LDS.  Each wavefront streams
+// Q basis columns at once with the row loop unrolled U times, so Q*U
+// independent loads per lane are in flight (one column at a time leaves the
+// wave waiting on a single load and reaches only about half of HBM
+// bandwidth); the X values read from LDS are shared by the Q columns.
+template <int NR, int Q, int U>
+__global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                const double* __restrict__ X1, int n1, int64_t ldx1,
+                                                const double* __restrict__ X2, int n2, int64_t ldx2,
+                                                const double* __restrict__ m, double* __restrict__ partial, int CH) {
+  extern __shared__ double xs[];
+  const int nrhs = n1 + n2;
+  const int chunk = blockIdx.x;
+  const int64_t r0 = (int64_t)chunk * CH;
+  const int rows = (int)std::min<int64_t>(CH, (int64_t)n - r0);
+  for (int t = threadIdx.x; t < CH * nrhs; t += blockDim.x) {
+    const int c = t / CH, r = t - c * CH;
+    double v = 0.0;
+    if (r < rows) {
+      const int64_t i = r0 + r;
+      v = c < n1 ? X1[i + (int64_t)c * ldx1] : X2[i + (int64_t)(c - n1) * ldx2] * m[i];
+    }
+    xs[t] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nchunks = gridDim.x;
+  const int j0 = blockIdx.y * 64;
+  for (int jj = wave * Q; jj < 64; jj += 4 * Q) {
+    const int jb = j0 + jj;
+    if (jb >= k) break;
+    // columns past k repeat column k-1 (in bounds) and are not stored
+    const double* bc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) bc[q] = Bk + (int64_t)std::min(jb + q, k - 1) * ldb + r0;
+    double s[Q][NR];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) s[q][c] = 0.0;
+    int r = lane;
+    for (; r + 64 * (U - 1) < rows; r += 64 * U) {
+      double bv[U][Q];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) bv[u][q] = bc[q][r + 64 * u];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < nrhs) {
+            const double xv = xs[c * CH + r + 64 * u];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[u][q], xv, s[q][c]);
+          }
+    }
+    for (; r < rows; r += 64) {
+      double bv[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) bv[q] = bc[q][r];
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nrhs) {
+          const double xv = xs[c * CH + r];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[q], xv, s[q][c]);
+        }
+    }
+    // layout [output (j, c)][chunk]: the second pass reads each output's
+    // partials contiguously
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nrhs) {
+          const double v = wave_sum(s[q][c]);
+          if (lane == 0 && jb + q < k) partial[((int64_t)(jb + q) * nrhs + c) * nchunks + chunk] = v;
+        }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
+                                                        const double* __restrict__ partial, double* __restrict__ H,
+                                                        int64_t ldh) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= k * nrhs) return;
+  const double* p = partial + (int64_t)t * nchunks;
+  double s = 0.0;
+  for (int ch = lane; ch < nchunks; ch += 64) s += p[ch];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int j = t / nrhs, c = t - j * nrhs;
+    H[j + (int64_t)c * ldh] = s;
+  }
+}
+
+// X[:, c] (-)= Bk * H[:, c]   (SUB: subtract from X; else V = Bk H)
+template <int NR, bool SUB>
+__global__ __launch_bounds__(256) void k_gemv_n(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                const double* __restrict__ H, int64_t ldh, double* X, int64_t ldx,
+                                                int nrhs, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  constexpr int JT = 128;
+  __shared__ double hs[JT * NR];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c0 = blockIdx.y * NR;
+  const int nc = std::min(NR, nrhs - c0);
+  double acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+  for (int j0 = 0; j0 < k; j0 += JT) {
+    const int jt = std::min(JT, k - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < jt * NR; t += blockDim.x) {
+      const int j = t / NR, c = t - j * NR;
+      hs[t] = c < nc ? H[(j0 + j) + (int64_t)(c0 + c) * ldh] : 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+      const double* __restrict__ bp = Bk + i + (int64_t)j0 * ldb;
+      for (int j = 0; j < jt; ++j) {
+        const double bv = bp[(int64_t)j * ldb];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = fma(bv, hs[j * NR + c], acc[c]);
+      }
+    }
+  }
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      if (c < nc) {
+        double* xp = X + i + (int64_t)(c0 + c) * ldx;
+        if (SUB)
+          *xp -= acc[c];
+        else
+          *xp = acc[c];
+      }
+    }
+  }
+}
+
+template <typename IT, int NC>
+__global__ __launch_bounds__(256) void k_spmv_cols(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                   const double* __restrict__ val, const IT* __restrict__ idx,
+                                                   const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                                   int64_t ldy, int ncols, const double* __restrict__ rscale) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int row = slice * 64 + lane;
+  if (row >= n) return;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int q = 0; q < width; ++q) {
+    const double a = val[base + (int64_t)q * 64 + lane];
+    const IT ci = idx[base + (int64_t)q * 64 + lane];
+    const int64_t col = relative ? row + (int)ci : (int)ci;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) acc[c] = fma(a, X[col + (int64_t)c * ldx], acc[c]);
+  }
+  const double sc = rscale ? rscale[row] : 1.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c < ncols) Y[row + (int64_t)c * ldy] = acc[c] * sc;
+}
+
+__global__ __launch_bounds__(256) void k_normalize_col(int32_t n, double* __restrict__ x,
+                                                       const double* __restrict__ nrm2,
+                                                       const double* __restrict__ ref2, double drop,
+                                                       int32_t* __restrict__ flag, double* __restrict__ out_norm) {
+  const double nr = sqrt(fmax(*nrm2, 0.0));
+  const double rf = ref2 ? sqrt(fmax(*ref2, 0.0)) : 0.0;
+  const bool keep = isfinite(nr) && nr > 0.0 && nr > drop * rf;
+  const double sc = keep ? 1.0 / nr : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = keep ? x[i] * sc : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (flag) *flag = keep ? 1 : 0;
+    if (out_norm) *out_norm = nr;
+  }
+}
+
+// partial[(chunk*nc + c)*2 + {0,1}] = sums over the chunk of
+// (SV - theta m V)^2 and SV^2 for column c
+__global__ __launch_bounds__(256) void k_resid_partial(int32_t n, const double* __restrict__ SV,
+                                                       const double* __restrict__ V, int64_t ld,
+                                                       const double* __restrict__ m,
+                                                       const double* __restrict__ theta, int nc, int CH,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[2][4];
+  const int chunk = blockIdx.x, c = blockIdx.y;
+  const int64_t r0 = (int64_t)chunk * CH;
+  const int64_t r1 = std::min<int64_t>(r0 + CH, n);
+  const double th = theta[c];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const double sv = SV[i + (int64_t)c * ld];
+    const double t = sv - th * m[i] * V[i + (int64_t)c * ld];
+    a = fma(t, t, a);
+    b = fma(sv, sv, b);
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[((int64_t)chunk * nc + c) * 2 + 0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    partial[((int64_t)chunk * nc + c) * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_resid_reduce(int nchunks, int nc, const double* __restrict__ partial,
+                                                      double* __restrict__ num, double* __restrict__ den) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    a += partial[((int64_t)ch * nc + c) * 2 + 0];
+    b += partial[((int64_t)ch * nc + c) * 2 + 1];
+  }
+  num[c] = a;
+  den[c] = b;
+}
+
+__global__ __launch_bounds__(256) void k_copy_cols(int32_t n, const double* __restrict__ src, int64_t lds,
+                                                   double* __restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) dst[i + (int64_t)c * ldd] = src[i + (int64_t)c * lds];
+}
+
+__global__ __launch_bounds__(256) void k_rr_scatter(int k, int c0, int nc, const double* __restrict__ T,
+                                                    int64_t ldt, double* __restrict__ H, double* __restrict__ G,
+                                                    int64_t ldh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * nc) return;
+  const int c = t / k, j = t - c * k;
+  const int col = c0 + c;
+  double h, g;
+  if (j < c0) {
+    h = T[j + (int64_t)c * ldt];
+    g = T[j + (int64_t)(nc + c) * ldt];
+  } else {
+    const int cj = j - c0;  // j is itself a new column
+    h = 0.5 * (T[j + (int64_t)c * ldt] + T[col + (int64_t)cj * ldt]);
+    g = 0.5 * (T[j + (int64_t)(nc + c) * ldt] + T[col + (int64_t)(nc + cj) * ldt]);
+  }
+  H[j + (int64_t)col * ldh] = h;
+  H[col + (int64_t)j * ldh] = h;
+  G[j + (int64_t)col * ldh] = g;
+  G[col + (int64_t)j * ldh] = g;
+}
+
+__global__ __launch_bounds__(256) void k_symmetrize(int k, double* __restrict__ A, int64_t lda) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  const int64_t j = t / k, i = t - j * k;
+  if (i <= j) return;
+  const double v = 0.5 * (A[i + j * lda] + A[j + i * lda]);
+  A[i + j * lda] = v;
+  A[j + i * lda] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __restrict__ G, int64_t ldg,
+                                                     double* __restrict__ out) {
+  __shared__ double red[16];
+  double mx = 0.0;
+  const int64_t tot = (int64_t)k * k;
+  for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int64_t c = t / k, j = t - c * k;
+    const double v = fabs(G[j + c * ldg] - (j == c ? 1.0 : 0.0));
+    mx = v > mx ? v : mx;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    *out = r;
+  }
+}
+
+
+}  // namespace
+
+int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, int n1, int64_t ldx1,
+           const double* X2, int n2, int64_t ldx2, const double* m, double* H, int64_t ldh, GemvTWork& wk,
+           hipStream_t st) {
+  const int nrhs = n1 + n2;
+  if (k <= 0 || nrhs <= 0) return KF_OK;
+  if (nrhs > 64) {
+    set_error("gemv_t: at most 64 right-hand sides");
+    return KF_EINVAL;
+  }
+  if (n2 > 0 && m == nullptr) {
+    set_error("gemv_t: weighted columns need the mass vector");
+    return KF_EINVAL;
+  }
+  const int CH = nrhs <= 8 ? 1024 : (nrhs <= 16 ? 512 : (nrhs <= 32 ? 256 : 128));
+  const int nchunks = ceil_div64(n, CH);
+  const size_t need = (size_t)nchunks * k * nrhs;
+  if (wk.cap < need) {
+    if (wk.partial) (void)hipFree(wk.partial);
+    wk.partial = nullptr;
+    wk.cap = 0;
+    const size_t cap = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&wk.partial, cap * sizeof(double)) != hipSuccess) {
+      set_error("gemv_t: cannot allocate the partial-sum buffer");
+      return KF_ENOMEM;
+    }
+    wk.cap = cap;
+  }
+  const dim3 grid(nchunks, ceil_div64(k, 64));
+  const size_t lds = sizeof(double) * CH * nrhs;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 2)
+    hipLaunchKernelGGL((k_gemv_t<2, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL((k_gemv_t<4, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_gemv_t<8, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 16)
+    hipLaunchKernelGGL((k_gemv_t<16, 2, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else if (nrhs <= 32)
+    hipLaunchKernelGGL((k_gemv_t<32, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  else
+    hipLaunchKernelGGL((k_gemv_t<64, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                       wk.partial, CH);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
+                     wk.partial, H, ldh);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+// The gate of the selective full subtraction: one workgroup, max |c_j|.
+__global__ __launch_bounds__(256) void k_reorth_gate(int k, const double* __restrict__ c, const double* __restrict__ g,
+                                                     double tol, int32_t* __restrict__ gate) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) mx = fmax(mx, fabs(c[j]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double nrm = sqrt(fmax(*g, 0.0));
+    // a non-finite coefficient or norm always subtracts (and is caught later)
+    *gate = (mx <= tol * nrm) ? 0 : 1;
+  }
+}
+
+int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(256), 0, st, k, c, g, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
+               int64_t ldx, int nrhs, hipStream_t st, const int32_t* gate) {
+  if (k <= 0 || nrhs <= 0) return KF_OK;
+  const int NR = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8);
+  const dim3 grid(ceil_div64(n, 256), ceil_div64(nrhs, NR));
+  if (NR == 1)
+    hipLaunchKernelGGL((k_gemv_n<1, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
+  else if (NR == 4)
+    hipLaunchKernelGGL((k_gemv_n<4, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
+  else
+    hipLaunchKernelGGL((k_gemv_n<8, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, int64_t ldy, double* V, int64_t ldv,
+            int nc, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  if (nc <= 8) {
+    const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
+    hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
+  } else {
+    const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 32));
+    hipLaunchKernelGGL((k_gemv_n<32, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
+  }
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols, const double* rscale,
+              hipStream_t st) {
+  if (S.val_bytes != 8) {
+    set_error("spmv_cols: needs the float64 operator");
+    return KF_EINVAL;
+  }
+  const int grid = ceil_div64(S.nslices, 4);
+  for (int c0 = 0; c0 < ncols; c0 += 16) {
+    const int nc = std::min(16, ncols - c0);
+    const double* x = X + (int64_t)c0 * ldx;
+    double* y = Y + (int64_t)c0 * ldy;
+    if (S.idx_bytes == 2) {
+      if (nc == 1)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 1>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 4)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+    } else {
+      if (nc == 1)
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 1>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 4)
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+    }
+    KF_HIP(hipGetLastError());
+  }
+  return KF_OK;
+}
+
+int normalize_col(int32_t n, double* x, const double* nrm2, const double* ref2, double drop, int32_t* flag,
+                  double* out_norm, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize_col, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, x, nrm2, ref2, drop, flag,
+                     out_norm);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int residual_norms(int32_t n, const double* SV, const double* V, int64_t ld, const double* m, const double* theta,
+                   int nc, double* num, double* den, GemvTWork& wk, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  const int CH = 8192;
+  const int nchunks = ceil_div64(n, CH);
+  const size_t need = (size_t)nchunks * nc * 2;
+  if (wk.cap < need) {
+    if (wk.partial) (void)hipFree(wk.partial);
+    wk.partial = nullptr;
+    wk.cap = 0;
+    if (hipMalloc(&wk.partial, need * sizeof(double)) != hipSuccess) {
+      set_error("residual_norms: allocation failed");
+      return KF_ENOMEM;
+    }
+    wk.cap = need;
+  }
+  hipLaunchKernelGGL(k_resid_partial, dim3(nchunks, nc), dim3(256), 0, st, n, SV, V, ld, m, theta, nc, CH,
+                     wk.partial);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_resid_reduce, dim3(ceil_div64(nc, 256)), dim3(256), 0, st, nchunks, nc, wk.partial, num, den);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ldd, int nc, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div64(n, 256), nc), dim3(256), 0, st, n, src, lds, dst, ldd);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, double* G, int64_t ldh,
+               hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  hipLaunchKernelGGL(k_rr_scatter, dim3(ceil_div64((int64_t)k * nc, 256)), dim3(256), 0, st, k, c0, nc, T, ldt, H, G,
+                     ldh);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int symmetrize(int k, double* A, int64_t lda, hipStream_t st) {
+  if (k <= 1) return KF_OK;
+  hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div64((int64_t)k * k, 256)), dim3(256), 0, st, k, A, lda);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int orth_error(int k, const double* G, int64_t ldg, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_orth_error, dim3(1), dim3(1024), 0, st, k, G, ldg, out);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+}  // namespace kf
