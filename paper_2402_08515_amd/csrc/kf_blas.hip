@@ -52,11 +52,14 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
                                                 const double* __restrict__ m, double* __restrict__ partial, int CH) {
   extern __shared__ double xs[];
   const int nrhs = n1 + n2;
+  // right-hand sides g0 .. g0 + nloc - 1 (groups of NR along the grid's z)
+  const int g0 = blockIdx.z * NR;
+  const int nloc = min(NR, nrhs - g0);
   const int chunk = blockIdx.x;
   const int64_t r0 = (int64_t)chunk * CH;
   const int rows = (int)std::min<int64_t>(CH, (int64_t)n - r0);
-  for (int t = threadIdx.x; t < CH * nrhs; t += blockDim.x) {
-    const int c = t / CH, r = t - c * CH;
+  for (int t = threadIdx.x; t < CH * nloc; t += blockDim.x) {
+    const int c = g0 + t / CH, r = t % CH;
     double v = 0.0;
     if (r < rows) {
       const int64_t i = r0 + r;
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-          if (c < nrhs) {
+          if (c < nloc) {
             const double xv = xs[c * CH + r + 64 * u];
 #pragma unroll
             for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[u][q], xv, s[q][c]);
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
       for (int q = 0; q < Q; ++q) bv[q] = bc[q][r];
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        if (c < nrhs) {
+        if (c < nloc) {
           const double xv = xs[c * CH + r];
 #pragma unroll
           for (int q = 0; q < Q; ++q) s[q][c] = fma(bv[q], xv, s[q][c]);
@@ -115,9 +118,9 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int c = 0; c < NR; ++c)
-        if (c < nrhs) {
+        if (c < nloc) {
           const double v = wave_sum(s[q][c]);
-          if (lane == 0 && jb + q < k) partial[((int64_t)(jb + q) * nrhs + c) * nchunks + chunk] = v;
+          if (lane == 0 && jb + q < k) partial[((int64_t)(jb + q) * nrhs + g0 + c) * nchunks + chunk] = v;
         }
   }
 }
@@ -351,7 +354,10 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     set_error("gemv_t: weighted columns need the mass vector");
     return KF_EINVAL;
   }
-  const int CH = nrhs <= 8 ? 1024 : (nrhs <= 16 ? 512 : (nrhs <= 32 ? 256 : 128));
+  // up to 8 right-hand sides in one group; wider sets in groups of 16 along
+  // the grid's z (each group re-reads the basis, but keeps its 4 x 16
+  // accumulators in registers instead of reading LDS for every product)
+  const int CH = nrhs <= 8 ? 1024 : 256;
   const int nchunks = ceil_div64(n, CH);
   const size_t need = (size_t)nchunks * k * nrhs;
   if (wk.cap < need) {
@@ -365,8 +371,9 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     }
     wk.cap = cap;
   }
-  const dim3 grid(nchunks, ceil_div64(k, 64));
-  const size_t lds = sizeof(double) * CH * nrhs;
+  const int groups = nrhs <= 8 ? 1 : ceil_div64(nrhs, 16);
+  const dim3 grid(nchunks, ceil_div64(k, 64), groups);
+  const size_t lds = sizeof(double) * CH * std::min(nrhs, 16);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
@@ -379,14 +386,8 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   else if (nrhs <= 8)
     hipLaunchKernelGGL((k_gemv_t<8, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
-  else if (nrhs <= 16)
-    hipLaunchKernelGGL((k_gemv_t<16, 2, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
-  else if (nrhs <= 32)
-    hipLaunchKernelGGL((k_gemv_t<32, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
   else
-    hipLaunchKernelGGL((k_gemv_t<64, 1, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+    hipLaunchKernelGGL((k_gemv_t<16, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
