@@ -97,6 +97,18 @@ typedef struct kf_options {
                             the column's M-norm, so the basis stays
                             M-orthonormal to about that level (reported as
                             kf_result.orth_error); 0 = always subtract */
+  int32_t proj_every;    /* KF_FP64, single-vector blocks, full_reorth 0: the
+                            projection onto the whole basis (which forms the
+                            new columns of B^T S B and B^T M B and the
+                            orthogonalisation coefficients) runs every
+                            proj_every steps; in between a step is
+                            orthogonalised against the last two columns only
+                            (three-term form).  Columns found more than 1e-8
+                            off M-orthogonal at a projection are orthogonalised
+                            again and proj_every is halved from then on.  The
+                            Rayleigh-Ritz step corrects to first order for the
+                            remaining non-orthogonality (E = B^T M B - I: the
+                            eigenvalues of H - (E H + H E)/2); 1 = every step */
   int32_t refine;        /* KF_MIXED only: one float64 filter application and
                             Rayleigh-Ritz on the near-interval Ritz block */
   int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
@@ -152,7 +164,7 @@ typedef struct kf_result {
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, reorth_tol 1e-14, refine 1, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-10, proj_every 4, refine 1, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);

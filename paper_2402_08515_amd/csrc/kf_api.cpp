@@ -86,6 +86,9 @@ struct kf_problem {
   int basis_cols = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double tuned_us = 0.0;
+  // k x k work arrays of the pencil correction (E, E H, corrected H)
+  double* rr_work = nullptr;
+  size_t rr_cap = 0;
   // batch members with their own stream (concurrent projection work)
   bool own_stream = false;
   hipEvent_t sync_ev = nullptr;
@@ -118,6 +121,10 @@ constexpr int kSmall = 4096;
 constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kOne = 4095;
 // mixed mode: refinements tried before a solve with a target gives up
 constexpr int kMaxRefines = 4;
+// columns projected only every proj_every steps must be M-orthogonal to the
+// older basis to this level, else they are orthogonalised again and the
+// projection interval is halved
+constexpr double kPendingTol = 1e-8;
 
 int pow2ceil(int b) {
   int p = 1;
@@ -339,8 +346,12 @@ int ensure_misc(kf_problem* p) {
 // The block's own Gram matrix rides along as extra rows of the first
 // projection (the block sits right after its left operand in B: X is column
 // kb = c0), so the norms before each pass cost no launch of their own.
+int rr_update(kf_problem* p, int c0, int nc);
+int repair_block(kf_problem* p, int p0, int pn);
+
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
-               hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr) {
+               hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr,
+               bool monitor = true, bool* pending_loose = nullptr) {
   if (c0 != kb) return fail(KF_EINVAL, "orth_block: the block must follow the basis");
   hipStream_t st = p->st;
   const int32_t n = p->n;
@@ -411,22 +422,58 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     KF_TRY(full_pass(false));
     KF_TRY(finish_cols(Tref, ld1));
     if (done) KF_HIP(hipEventRecord(done, st));
+  } else if (kb > 0 && nb == 1 && !monitor) {
+    // between projections: the window pass only; the coefficients against
+    // the older basis are formed at the next projection (every proj_every
+    // steps), which also checks how far this column is from orthogonal
+    KF_TRY(finish_cols(Tref, ld1));
+    double g2h = 0.0;
+    KF_TRY(fetch(nrm2, 1, &g2h));
+    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    std::vector<double> t1((size_t)ld1);
+    KF_TRY(fetch(T1, (size_t)ld1, t1.data()));
+    if (done) KF_HIP(hipEventRecord(done, st));
+    KF_HIP(hipStreamSynchronize(st));
+    if (fl[0] && g2h < 1e-4 * t1[(size_t)lw]) {
+      // the window pass removed all but 1 % of the norm: its rounding is no
+      // longer negligible, so this column gets a pass against the whole basis
+      KF_TRY(full_pass(false));
+      KF_TRY(gemv_t(n, 1, X, ldb, nullptr, 0, 0, X, 1, ldb, p->d_m, nrm2, 1, p->gw, st));
+      KF_TRY(normalize_col(n, X, nrm2, p->small + kOne, drop, p->flags, post, st));
+      if (done) KF_HIP(hipEventRecord(done, st));
+    }
   } else if (kb > 0 && nb == 1) {
     // one vector: its norm after the full pass is the normalisation norm, so
     // the second-pass test and the drop test share one synchronisation
     const bool gated = p->opt.reorth_tol > 0.0;
     KF_TRY(full_pass(true, gated));
+    int32_t* loose = p->flags + 33;
+    if (pending_loose && pn > 0) KF_TRY(block_gate(kb, kb - pn, pn, coef + (int64_t)pn * ldc, ldc, kPendingTol, loose, st));
     KF_TRY(finish_cols(Tref, ld1));
     double g1 = 0.0, g2h = 0.0;
-    int32_t gh = 1;
+    int32_t gh = 1, lh = 0;
     KF_TRY(fetch(coef + kb + (int64_t)(2 * pn) * ldc, 1, &g1));
     KF_TRY(fetch(nrm2, 1, &g2h));
     KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (gated) KF_HIP(hipMemcpyAsync(&gh, gate, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (pending_loose && pn > 0) KF_HIP(hipMemcpyAsync(&lh, loose, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
+    if (pending_loose) *pending_loose = lh != 0;
     if (full_passes && gated && gh) ++*full_passes;
-    if (fl[0] && g2h < 0.25 * g1) {
+    if (lh) {
+      // the columns formed since the previous projection drifted from
+      // M-orthogonality: repair them, then orthogonalise the new column
+      // against the repaired ones
+      KF_TRY(repair_block(p, kb - pn, pn));
+      KF_TRY(full_pass(false));
+      KF_TRY(full_pass(false));
+      KF_TRY(gemv_t(n, 1, X, ldb, nullptr, 0, 0, X, 1, ldb, p->d_m, nrm2, 1, p->gw, st));
+      KF_TRY(normalize_col(n, X, nrm2, p->small + kOne, drop, p->flags, post, st));
+      if (done) KF_HIP(hipEventRecord(done, st));
+      KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KF_HIP(hipStreamSynchronize(st));
+    } else if (fl[0] && g2h < 0.25 * g1) {
       // the column is normalised now: one more pass against the whole basis,
       // dropped if it loses all but drop_tol of its unit norm
       KF_TRY(full_pass(false));
@@ -478,6 +525,32 @@ int rr_update(kf_problem* p, int c0, int nc) {
   KF_TRY(gemv_t(p->n, k, p->B, p->ldb, p->W, nc, p->n, Q, nc, p->ldb, p->d_m, p->T, k, p->gw, st));
   KF_TRY(rr_scatter(k, c0, nc, p->T, k, p->H, p->G, p->hcap, st));
   return KF_OK;
+}
+
+// Basis columns [p0, p0 + pn) that drifted from M-orthogonality: classical
+// Gram-Schmidt twice against the older columns and twice among themselves,
+// normalisation, and their projected-pencil columns again.
+int repair_block(kf_problem* p, int p0, int pn) {
+  hipStream_t st = p->st;
+  const int32_t n = p->n;
+  const int64_t ldb = p->ldb;
+  double* Q = p->B + (int64_t)p0 * ldb;
+  double* coef = p->T;
+  double* nrm2 = p->small + kNrm2 + 32;
+  for (int pass = 0; pass < 2 && p0 > 0; ++pass) {
+    KF_TRY(gemv_t(n, p0, p->B, ldb, nullptr, 0, 0, Q, pn, ldb, p->d_m, coef, p0, p->gw, st));
+    KF_TRY(gemv_n_sub(n, p0, p->B, ldb, coef, p0, Q, ldb, pn, st));
+  }
+  for (int j = 0; j < pn; ++j) {
+    double* qj = Q + (int64_t)j * ldb;
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      KF_TRY(gemv_t(n, j, Q, ldb, nullptr, 0, 0, qj, 1, ldb, p->d_m, coef, j, p->gw, st));
+      KF_TRY(gemv_n_sub(n, j, Q, ldb, coef, j, qj, ldb, 1, st));
+    }
+    KF_TRY(gemv_t(n, 1, qj, ldb, nullptr, 0, 0, qj, 1, ldb, p->d_m, nrm2 + j, 1, p->gw, st));
+    KF_TRY(normalize_col(n, qj, nrm2 + j, nullptr, 0.0, p->flags + 40, nrm2 + 16 + j, st));
+  }
+  return rr_update(p, p0, pn);
 }
 
 struct CheckOut {
@@ -594,15 +667,38 @@ int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, boo
   hipStream_t st = p->st;
   KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
   KF_HIP(hipMemcpyAsync(&out.orth, p->small + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+  // The pencil is (H, G) with G = I + E, E at the orthogonality level of the
+  // basis: its eigenvalues are those of H - (E H + H E)/2 up to O(|E|^2).
+  const double* Hm = p->H;
+  int64_t ldh = p->hcap;
+  double *E = nullptr, *EH = nullptr;
+  if (k >= 2) {
+    const size_t need = (size_t)3 * k * k;
+    if (p->rr_cap < need) {
+      dfree(p->rr_work);
+      p->rr_work = nullptr;
+      p->rr_cap = 0;
+      const size_t cap = (size_t)3 * p->hcap * p->hcap;
+      KF_TRY(dalloc(&p->rr_work, cap));
+      p->rr_cap = cap;
+    }
+    E = p->rr_work;
+    EH = E + (size_t)k * k;
+    double* Hc = EH + (size_t)k * k;
+    KF_TRY(pencil_correct(k, p->H, p->G, p->hcap, E, EH, Hc, st));
+    Hm = Hc;
+    ldh = k;
+  }
   const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
   std::vector<double> sel;
   KF_TRY(small_eigen(
-      p, k, p->H, p->hcap, out.ritz,
+      p, k, Hm, ldh, out.ritz,
       [&](double th) {
         const double om = std::sqrt(std::max(th, 0.0));
         return om >= lo && om <= hi;
       },
       sel));
+  if (E) KF_TRY(vectors_correct(k, (int)sel.size(), E, p->ew.Y, EH, st));
   return ritz_residuals(p, p->B, p->ldb, k, sel, tol, want_vectors, out);
 }
 
@@ -853,7 +949,8 @@ void free_problem(kf_problem* p) {
   free_sell(p->A);
   free_sell(p->A64);
   free_sell(p->S);
-  void* ptrs[] = {p->d_m, p->B, p->H, p->G, p->T, p->W, p->V, p->SV, p->small, p->flags, p->Vx, p->Yy, p->Ysel, p->Gm};
+  void* ptrs[] = {p->d_m, p->B,  p->H,  p->G,  p->T,  p->W,    p->V,      p->SV,
+                  p->small, p->flags, p->Vx, p->Yy, p->Ysel, p->Gm, p->rr_work};
   for (void* q : ptrs) dfree(q);
   free_step_buffers(p->sb);
   free_step_buffers(p->sb64);
@@ -884,7 +981,8 @@ void kf_default_options(kf_options* o) {
   o->target = 0;
   o->max_iters = 0;
   o->drop_tol = 1e-10;
-  o->reorth_tol = 1e-14;
+  o->reorth_tol = 1e-10;
+  o->proj_every = 4;
   o->refine = 1;
   o->want_vectors = 0;
   o->index_bytes = 0;
@@ -932,6 +1030,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (!(o.reorth_tol >= 0.0) || !std::isfinite(o.reorth_tol))
     return fail(KF_EINVAL, "kf_create: reorth_tol must be finite and >= 0");
   if (o.batch_workers < 0) return fail(KF_EINVAL, "kf_create: batch_workers must be >= 0");
+  if (o.proj_every < 1) o.proj_every = 1;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 1 && o.lanes_per_row != 2 && o.lanes_per_row != 4)
     return fail(KF_EINVAL, "kf_create: lanes_per_row must be 0, 1, 2 or 4");
   HostCsr h;
@@ -1182,6 +1281,7 @@ struct SolveState {
   // mixed mode: refinement already run at basis size fin_at
   CheckOut fin;
   int fin_at = -1, refines = 0, next_refine = 0;
+  int proj_every = 1, since_proj = 0;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -1220,6 +1320,9 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   s.b = b;
   s.bk = pow2ceil(b);
   s.m_max = m_max;
+  // float32 steps leave components of relative size ~1e-7 along the whole
+  // basis in every new column: those are removed at every step
+  s.proj_every = p->opt.precision == KF_MIXED ? 1 : std::min(p->opt.proj_every, 15);
   KF_TRY(tune_block(p, p->A, p->sb, s.bk));
   s.tol = tol;
   hipStream_t st = p->st;
@@ -1262,7 +1365,21 @@ bool solve_wants_filter(const kf_problem* p, const SolveState& s) {
 int solve_check_now(kf_problem* p, SolveState& s) {
   hipStream_t st = p->st;
   if (!s.rr_pending) KF_HIP(hipEventRecord(p->ev[3], st));
-  if (s.pending > 0) KF_TRY(rr_update(p, s.cur - s.pending, s.pending));
+  if (s.pending > 0) {
+    const int c0 = s.cur - s.pending, nc = s.pending;
+    KF_TRY(rr_update(p, c0, nc));
+    if (s.proj_every > 1) {
+      // columns never projected since they were formed: check them too
+      int32_t lh = 0;
+      KF_TRY(block_gate(s.cur, c0, nc, p->T + (int64_t)nc * s.cur, s.cur, kPendingTol, p->flags + 33, st));
+      KF_HIP(hipMemcpyAsync(&lh, p->flags + 33, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KF_HIP(hipStreamSynchronize(st));
+      if (lh) {
+        KF_TRY(repair_block(p, c0, nc));
+        s.proj_every = std::max(1, s.proj_every / 2);
+      }
+    }
+  }
   s.pending = 0;
   KF_TRY(rr_check(p, s.cur, s.tol_loop, s.chk, s.margin, false));
   KF_HIP(hipEventRecord(p->ev[4], st));
@@ -1277,9 +1394,22 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   ++s.iters;
   s.lf_steps += (int64_t)s.qn * (p->L - 1);
   int kept = 0;
-  KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], s.pending, p->opt.full_reorth ? -1 : s.prev0,
-                    &s.full_passes));  // synchronises the stream
-  s.pending = 0;
+  // single vectors in the three-term form project onto the whole basis every
+  // proj_every steps; columns that drifted beyond kPendingTol are repaired
+  // and the interval halved
+  const bool three = !p->opt.full_reorth && s.bk == 1 && s.cur > 0;
+  const bool monitor = !three || s.proj_every <= 1 || s.since_proj + 1 >= s.proj_every ||
+                       s.pending + s.bk > 15;
+  bool loose = false;
+  KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], monitor ? s.pending : 0,
+                    p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose));  // synchronises the stream
+  if (loose) s.proj_every = std::max(1, s.proj_every / 2);
+  if (monitor) {
+    s.pending = 0;
+    s.since_proj = 0;
+  } else {
+    ++s.since_proj;
+  }
   if (s.rr_pending) {
     KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
     s.rr_pending = false;
@@ -1303,7 +1433,7 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   s.q0 = s.cur;
   s.qn = kept;
   s.cur += kept;
-  s.pending = kept;
+  s.pending += kept;
   if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
     KF_TRY(solve_check_now(p, s));
     s.next_check = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));

@@ -339,6 +339,31 @@ __global__ __launch_bounds__(1024) void k_orth_error(int k, const double* __rest
 }
 
 
+// First-order correction of the projected pencil for a basis that is
+// M-orthonormal only up to E = G - I: (H, G) has, to O(|E|^2), the
+// eigenvalues of Hc = H - (E H + H E)/2 and the eigenvectors (I - E/2) y.
+__global__ __launch_bounds__(256) void k_sub_identity(int k, const double* __restrict__ G, int64_t ldg,
+                                                      double* __restrict__ E) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  const int j = (int)(t / k), i = (int)(t - (int64_t)j * k);
+  E[t] = G[i + (int64_t)j * ldg] - (i == j ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_h_correct(int k, const double* __restrict__ H, int64_t ldh,
+                                                   const double* __restrict__ EH, double* __restrict__ Hc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  const int j = (int)(t / k), i = (int)(t - (int64_t)j * k);
+  Hc[t] = H[i + (int64_t)j * ldh] - 0.5 * (EH[t] + EH[j + (int64_t)i * k]);
+}
+
+__global__ __launch_bounds__(256) void k_axpy(int64_t count, double a, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) y[t] = fma(a, x[t], y[t]);
+}
+
 }  // namespace
 
 int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, int n1, int64_t ldx1,
@@ -412,6 +437,30 @@ __global__ __launch_bounds__(256) void k_reorth_gate(int k, const double* __rest
     // a non-finite coefficient or norm always subtracts (and is caught later)
     *gate = (mx <= tol * nrm) ? 0 : 1;
   }
+}
+
+// Orthogonality of np basis columns p0.. against the whole basis: G[:, c]
+// (c < np, leading dimension ldg, rows < k) against the identity.
+__global__ __launch_bounds__(256) void k_block_gate(int k, int p0, int np, const double* __restrict__ G, int64_t ldg,
+                                                    double tol, int32_t* __restrict__ flag) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int64_t t = threadIdx.x; t < (int64_t)k * np; t += blockDim.x) {
+    const int c = (int)(t / k), j = (int)(t - (int64_t)c * k);
+    const double v = G[j + (int64_t)c * ldg] - (j == p0 + c ? 1.0 : 0.0);
+    mx = fmax(mx, isfinite(v) ? fabs(v) : INFINITY);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) > tol ? 1 : 0;
+}
+
+int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_gate, dim3(1), dim3(256), 0, st, k, p0, np, G, ldg, tol, flag);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
 }
 
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st) {
@@ -521,6 +570,25 @@ int residual_norms(int32_t n, const double* SV, const double* V, int64_t ld, con
 int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ldd, int nc, hipStream_t st) {
   if (nc <= 0) return KF_OK;
   hipLaunchKernelGGL(k_copy_cols, dim3(ceil_div64(n, 256), nc), dim3(256), 0, st, n, src, lds, dst, ldd);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int pencil_correct(int k, const double* H, const double* G, int64_t ldh, double* E, double* EH, double* Hc,
+                   hipStream_t st) {
+  const int grid = ceil_div64((int64_t)k * k, 256);
+  hipLaunchKernelGGL(k_sub_identity, dim3(grid), dim3(256), 0, st, k, G, ldh, E);
+  KF_HIP(hipGetLastError());
+  KF_TRY(gemm_nn(k, k, E, k, H, ldh, EH, k, k, st));
+  hipLaunchKernelGGL(k_h_correct, dim3(grid), dim3(256), 0, st, k, H, ldh, EH, Hc);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int vectors_correct(int k, int nc, const double* E, double* Y, double* tmp, hipStream_t st) {
+  if (nc <= 0) return KF_OK;
+  KF_TRY(gemm_nn(k, k, E, k, Y, k, tmp, k, nc, st));
+  hipLaunchKernelGGL(k_axpy, dim3(ceil_div64((int64_t)k * nc, 256)), dim3(256), 0, st, (int64_t)k * nc, -0.5, tmp, Y);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

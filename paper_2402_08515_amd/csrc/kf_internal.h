@@ -125,6 +125,10 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
 int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
                int64_t ldx, int nrhs, hipStream_t st, const int32_t* gate = nullptr);
 
+// *flag = 1 if some G[j + c*ldg] (j < k, c < np) differs from the identity
+// entry of basis column p0 + c by more than tol (device values)
+int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, int32_t* flag, hipStream_t st);
+
 // *gate = 1 if max_j |c[j]| (j < k) > tol * sqrt(*g), else 0 (device values)
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st);
 
@@ -151,6 +155,14 @@ int copy_cols(int32_t n, const double* src, int64_t lds, double* dst, int64_t ld
 // H, next nc of G) into the symmetric k x k matrices (ld ldh).
 int rr_scatter(int k, int c0, int nc, const double* T, int64_t ldt, double* H, double* G, int64_t ldh,
                hipStream_t st);
+
+// Basis M-orthonormal only up to E = G - I: Hc = H - (E H + H E)/2 (k x k,
+// leading dimension k; E and EH are k x k work arrays) has the eigenvalues of
+// the pencil (H, G) to O(|E|^2); vectors_correct turns eigenvectors y of Hc
+// (k x nc, leading dimension k) into (I - E/2) y (tmp: k x nc work).
+int pencil_correct(int k, const double* H, const double* G, int64_t ldh, double* E, double* EH, double* Hc,
+                   hipStream_t st);
+int vectors_correct(int k, int nc, const double* E, double* Y, double* tmp, hipStream_t st);
 
 // A = (A + A^T)/2 for the leading k x k block
 int symmetrize(int k, double* A, int64_t lda, hipStream_t st);

@@ -52,6 +52,7 @@ class OptionsT(C.Structure):
         ("max_iters", C.c_int32),
         ("drop_tol", C.c_double),
         ("reorth_tol", C.c_double),
+        ("proj_every", C.c_int32),
         ("refine", C.c_int32),
         ("want_vectors", C.c_int32),
         ("index_bytes", C.c_int32),
@@ -281,7 +282,7 @@ def _take_result(res, n: int) -> SolveResult:
 
 def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=True, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
-             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0):
+             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -293,6 +294,8 @@ def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=Fals
     opt.drop_tol = drop_tol
     if reorth_tol is not None:
         opt.reorth_tol = reorth_tol
+    if proj_every is not None:
+        opt.proj_every = proj_every
     opt.refine = int(refine)
     opt.want_vectors = int(want_vectors)
     opt.index_bytes = index_bytes

@@ -41,12 +41,14 @@ def grid2d():
     return P, tau, L, w, V0, ref
 
 
-@pytest.mark.parametrize("full_reorth,reorth_tol", [(False, None), (False, 0.0), (True, None)])
-def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth, reorth_tol):
+@pytest.mark.parametrize("full_reorth,reorth_tol,proj_every", [(False, None, None), (False, 0.0, 1), (False, 1e-14, 1),
+                                                                (False, 0.0, 7), (True, None, None)])
+def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth, reorth_tol, proj_every):
     kf = _kf()
     P, tau, L, w, V0, ref = grid2d
     print(f"case grid2d_64 fp64 solve full_reorth={full_reorth} reorth_tol={reorth_tol}", flush=True)
-    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, full_reorth=full_reorth, reorth_tol=reorth_tol)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, full_reorth=full_reorth, reorth_tol=reorth_tol,
+                      proj_every=proj_every)
     got = prob.solve(V0, m_max=40, tol=1e-9)
     tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
     assert got.basis_size == 40 and got.krylov_steps == 39
@@ -56,7 +58,11 @@ def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth, reorth_
     assert got.residual.max() <= 1e-9
     # unconverged Ritz values after many iterations follow rounding noise in
     # the late basis vectors and are not compared (only accepted pairs are)
-    assert got.orth_error < 1e-12
+    # with projections every few steps the basis is held M-orthonormal to
+    # 1e-8 (the Rayleigh-Ritz step corrects for that to second order); with
+    # a projection at every step and a tight subtraction threshold, to 1e-12
+    tight = full_reorth or (proj_every == 1 and reorth_tol is not None and reorth_tol <= 1e-14)
+    assert got.orth_error < (1e-12 if tight else 1e-8), got.orth_error
     assert got.leapfrog_vector_steps == 39 * (L - 1)
 
 
@@ -190,7 +196,8 @@ def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
     assert got.omega2.size == tgt == 110
     assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
     assert got.residual.max() <= 1e-6
-    # the full subtraction is skipped while every coefficient is below
-    # 1e-14 of the column norm: the basis stays orthonormal to that level
-    assert got.orth_error < 1e-12
+    # the projection onto the whole basis runs every 4 steps and subtracts
+    # only coefficients above 1e-10; the Rayleigh-Ritz step corrects for the
+    # remaining non-orthogonality to first order
+    assert got.orth_error < 1e-8
     print("orth_error", got.orth_error, "full passes", got.full_passes, "of", got.krylov_steps)
