@@ -398,6 +398,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   const double drop = p->opt.drop_tol > 0 ? p->opt.drop_tol : 1e-10;
   std::vector<double> hv((size_t)ld1 * nb);
   std::vector<int32_t> fl((size_t)nb);
+  bool have = false;  // hv and fl hold the final device values
   auto fetch = [&](const double* src, size_t count, void* dst) -> int {
     KF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
     return KF_OK;
@@ -430,11 +431,12 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     double g2h = 0.0;
     KF_TRY(fetch(nrm2, 1, &g2h));
     KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    std::vector<double> t1((size_t)ld1);
-    KF_TRY(fetch(T1, (size_t)ld1, t1.data()));
+    KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
-    if (fl[0] && g2h < 1e-4 * t1[(size_t)lw]) {
+    have = true;
+    if (fl[0] && g2h < 1e-4 * hv[(size_t)lw]) {
+      have = false;
       // the window pass removed all but 1 % of the norm: its rounding is no
       // longer negligible, so this column gets a pass against the whole basis
       KF_TRY(full_pass(false));
@@ -457,8 +459,10 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (gated) KF_HIP(hipMemcpyAsync(&gh, gate, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (pending_loose && pn > 0) KF_HIP(hipMemcpyAsync(&lh, loose, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
+    have = true;
     if (pending_loose) *pending_loose = lh != 0;
     if (full_passes && gated && gh) ++*full_passes;
     if (lh) {
@@ -476,6 +480,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     } else if (fl[0] && g2h < 0.25 * g1) {
       // the column is normalised now: one more pass against the whole basis,
       // dropped if it loses all but drop_tol of its unit norm
+      have = false;
       KF_TRY(full_pass(false));
       KF_TRY(gemv_t(n, 1, X, ldb, nullptr, 0, 0, X, 1, ldb, p->d_m, nrm2, 1, p->gw, st));
       KF_TRY(normalize_col(n, X, nrm2, p->small + kOne, drop, p->flags, post, st));
@@ -498,9 +503,12 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     KF_TRY(finish_cols(Tref, ld1));
     if (done) KF_HIP(hipEventRecord(done, st));
   }
-  KF_TRY(fetch(T1, (size_t)ld1 * nb, hv.data()));
-  KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
-  KF_HIP(hipStreamSynchronize(st));
+  if (!have) {
+    // (single vectors usually have both from their one synchronisation)
+    KF_TRY(fetch(T1, (size_t)ld1 * nb, hv.data()));
+    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+    KF_HIP(hipStreamSynchronize(st));
+  }
   ref_out.assign((size_t)nb, 0.0);
   for (int j = 0; j < nb; ++j) ref_out[(size_t)j] = std::sqrt(std::max(hv[(size_t)lw + j + (size_t)j * ld1], 0.0));
   int cnt = 0;

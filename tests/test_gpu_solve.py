@@ -201,3 +201,20 @@ def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
     # remaining non-orthogonality to first order
     assert got.orth_error < 1e-8
     print("orth_error", got.orth_error, "full passes", got.full_passes, "of", got.krylov_steps)
+
+
+def test_loose_orthogonality_is_corrected_in_rayleigh_ritz(grid2d):
+    """With projections only every 8 steps and subtractions only above 1e-6
+    of a column's norm the basis is far from M-orthonormal, yet the
+    eigenvalues stay at the float64 bar: the pencil is solved as
+    H - (E H + H E)/2 with E = B^T M B - I (second-order error)."""
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, proj_every=8, reorth_tol=1e-6)
+    got = prob.solve(V0, m_max=40, tol=1e-9)
+    tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
+    print("orth_error", got.orth_error)
+    assert got.omega2.size == tgt
+    assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
+    assert got.residual.max() <= 1e-9
+    assert got.orth_error < 1e-5
