@@ -109,8 +109,11 @@ typedef struct kf_options {
                             Rayleigh-Ritz step corrects to first order for the
                             remaining non-orthogonality (E = B^T M B - I: the
                             eigenvalues of H - (E H + H E)/2); 1 = every step */
-  int32_t refine;        /* KF_MIXED only: one float64 filter application and
-                            Rayleigh-Ritz on the near-interval Ritz block */
+  int32_t refine;        /* KF_MIXED only: passes of float64 refinement
+                            (0 = none): each applies the filter in float64 to
+                            the near-interval Ritz block of the previous one
+                            and solves the pencil on its span; a second pass
+                            runs only while pairs of the target are missing */
   int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
   int32_t index_bytes;   /* column-index width of the device operator:
                             0 = automatic (2 when every |col - row| < 32768),
@@ -164,7 +167,7 @@ typedef struct kf_result {
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, reorth_tol 1e-10, proj_every 4, refine 1, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-10, proj_every 4, refine 2, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);

@@ -778,7 +778,12 @@ int eig_orthonormalise(kf_problem* p, double* Z, int nz, double* out, int* r_out
   return KF_OK;
 }
 
-int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out) {
+int distinct_count(const std::vector<double>& acc, int b);
+
+// passes: up to opt.refine; a further pass runs only while fewer than
+// `target` pairs (counted as distinct_count with block width b) are accepted
+int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out, int target = 0,
+                 int b = 1) {
   hipStream_t st = p->st;
   const int n = p->n;
   const int64_t ld = p->ldb;
@@ -810,39 +815,55 @@ int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want
     KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)i * k, p->ew.Y + (int64_t)pick[(size_t)i] * k, sizeof(double) * k,
                           hipMemcpyDeviceToDevice, st));
   KF_TRY(gemm_nn(n, k, p->B, p->ldb, p->Ysel, k, p->Vx, ld, nc, st));
-  // Yy = C X in float64
-  for (int c0 = 0; c0 < nc; c0 += 16) {
-    const int nb = std::min(16, nc - c0);
-    KF_TRY(run_filter(p, p->A64, p->sb64, p->Vx + (int64_t)c0 * ld, 1, ld, nb, pow2ceil(nb), p->Yy + (int64_t)c0 * ld,
-                      1, ld, nb, p->w));
+  const int passes = std::max(1, p->opt.refine);
+  int ncur = nc;
+  for (int pass = 0; pass < passes; ++pass) {
+    // Yy = C X in float64
+    for (int c0 = 0; c0 < ncur; c0 += 16) {
+      const int nb = std::min(16, ncur - c0);
+      KF_TRY(run_filter(p, p->A64, p->sb64, p->Vx + (int64_t)c0 * ld, 1, ld, nb, pow2ceil(nb),
+                        p->Yy + (int64_t)c0 * ld, 1, ld, nb, p->w));
+    }
+    int r = 0, r2 = 0;
+    KF_TRY(eig_orthonormalise(p, p->Yy, ncur, p->Vx, &r));
+    if (r == 0) return KF_OK;
+    KF_TRY(eig_orthonormalise(p, p->Vx, r, p->Yy, &r2));
+    if (r2 == 0) return KF_OK;
+    // projected pencil Z^T S Z with Z = Yy[:, :r2]; S Z into Vx
+    for (int c0 = 0; c0 < r2; c0 += 16) {
+      const int nb = std::min(16, r2 - c0);
+      KF_TRY(spmv_cols(p->S, p->Yy + (int64_t)c0 * ld, ld, p->Vx + (int64_t)c0 * ld, ld, nb, nullptr, st));
+    }
+    for (int c0 = 0; c0 < r2; c0 += 32) {
+      const int nb = std::min(32, r2 - c0);
+      KF_TRY(gemv_t(n, r2, p->Yy, ld, p->Vx + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr,
+                    p->Gm + (int64_t)c0 * r2, r2, p->gw, st));
+    }
+    KF_TRY(symmetrize(r2, p->Gm, r2, st));
+    const double margin = 0.05 * (p->omega_max - p->omega_min);
+    const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+    std::vector<double> th, sel;
+    KF_TRY(small_eigen(
+        p, r2, p->Gm, r2, th,
+        [&](double t) {
+          const double om = std::sqrt(std::max(t, 0.0));
+          return om >= lo && om <= hi;
+        },
+        sel));
+    KF_TRY(ritz_residuals(p, p->Yy, ld, r2, sel, tol, want_vectors, out, true));
+    if (pass + 1 == passes || (target > 0 && distinct_count(out.acc_theta, b) >= target)) break;
+    // next pass: the filter again on the Ritz vectors of this one that are
+    // still near (residual <= 0.1)
+    std::vector<int> pk;
+    for (size_t q = 0; q < out.cand_res.size(); ++q)
+      if (out.cand_res[q] <= 0.1) pk.push_back((int)q);
+    if (pk.empty()) break;
+    for (size_t i = 0; i < pk.size(); ++i)
+      KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)i * r2, p->ew.Y + (int64_t)pk[i] * r2, sizeof(double) * r2,
+                            hipMemcpyDeviceToDevice, st));
+    ncur = (int)pk.size();
+    KF_TRY(gemm_nn(n, r2, p->Yy, ld, p->Ysel, r2, p->Vx, ld, ncur, st));
   }
-  int r = 0, r2 = 0;
-  KF_TRY(eig_orthonormalise(p, p->Yy, nc, p->Vx, &r));
-  if (r == 0) return KF_OK;
-  KF_TRY(eig_orthonormalise(p, p->Vx, r, p->Yy, &r2));
-  if (r2 == 0) return KF_OK;
-  // projected pencil Z^T S Z with Z = Yy[:, :r2]; S Z into Vx
-  for (int c0 = 0; c0 < r2; c0 += 16) {
-    const int nb = std::min(16, r2 - c0);
-    KF_TRY(spmv_cols(p->S, p->Yy + (int64_t)c0 * ld, ld, p->Vx + (int64_t)c0 * ld, ld, nb, nullptr, st));
-  }
-  for (int c0 = 0; c0 < r2; c0 += 32) {
-    const int nb = std::min(32, r2 - c0);
-    KF_TRY(gemv_t(n, r2, p->Yy, ld, p->Vx + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr,
-                  p->Gm + (int64_t)c0 * r2, r2, p->gw, st));
-  }
-  KF_TRY(symmetrize(r2, p->Gm, r2, st));
-  const double margin = 0.05 * (p->omega_max - p->omega_min);
-  const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
-  std::vector<double> th, sel;
-  KF_TRY(small_eigen(
-      p, r2, p->Gm, r2, th,
-      [&](double t) {
-        const double om = std::sqrt(std::max(t, 0.0));
-        return om >= lo && om <= hi;
-      },
-      sel));
-  KF_TRY(ritz_residuals(p, p->Yy, ld, r2, sel, tol, want_vectors, out, true));
   out.ritz = in.ritz;
   out.orth = in.orth;
   return KF_OK;
@@ -991,7 +1012,7 @@ void kf_default_options(kf_options* o) {
   o->drop_tol = 1e-10;
   o->reorth_tol = 1e-10;
   o->proj_every = 4;
-  o->refine = 1;
+  o->refine = 2;
   o->want_vectors = 0;
   o->index_bytes = 0;
   o->xcd_remap = 1;
@@ -1306,7 +1327,7 @@ int solve_refine_now(kf_problem* p, SolveState& s) {
   if (s.rr_pending) KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
   s.rr_pending = false;
   KF_HIP(hipEventRecord(p->ev[3], st));
-  KF_TRY(refine_mixed(p, s.cur, s.tol, s.chk, p->opt.want_vectors != 0, s.fin));
+  KF_TRY(refine_mixed(p, s.cur, s.tol, s.chk, p->opt.want_vectors != 0, s.fin, s.target, s.b));
   KF_HIP(hipEventRecord(p->ev[4], st));
   KF_HIP(hipEventSynchronize(p->ev[4]));
   KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_ref));
