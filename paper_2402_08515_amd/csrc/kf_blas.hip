@@ -125,6 +125,112 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
   }
 }
 
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// H = Bk^T diag(w) X for many right-hand sides on the float64 matrix cores
+// (v_mfma_f64_16x16x4f64: a 16 x 4 by 4 x 16 product per instruction, the
+// sum over rows happening inside the accumulator, so no cross-lane
+// reductions).  Workgroup: a chunk of TCH rows, 64 basis columns (one 16-column
+// tile per wavefront), 16 right-hand sides (grid z); the X chunk is staged in
+// LDS in sub-chunks of 256 rows.  Lane l supplies A[j = l%16][r = l/16] =
+// Bk[r][j] and B[r = l/16][c = l%16] = X[r][c]; its accumulator register v holds
+// D[j = 4v + l/16][c = l%16] (the f64 layout interleaves rows by register).
+constexpr int kMfmaSub = 256;
+__global__ __launch_bounds__(256) void k_gemv_t_mfma(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                     const double* __restrict__ X1, int n1, int64_t ldx1,
+                                                     const double* __restrict__ X2, int n2, int64_t ldx2,
+                                                     const double* __restrict__ m, double* __restrict__ partial,
+                                                     int TCH) {
+  __shared__ double xs[16][kMfmaSub + 4];
+  const int nrhs = n1 + n2;
+  const int g0 = blockIdx.z * 16;
+  const int nloc = min(16, nrhs - g0);
+  const int chunk = blockIdx.x;
+  const int64_t r0 = (int64_t)chunk * TCH;
+  const int rows = (int)std::min<int64_t>(TCH, (int64_t)n - r0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int jt = blockIdx.y * 64 + wave * 16;  // first column of this wavefront's tile
+  const int ja = jt + (lane & 15);             // column this lane feeds
+  const bool jok = ja < k;
+  const double* __restrict__ bcol = Bk + (int64_t)(jok ? ja : 0) * ldb + r0;
+  const int kr = lane >> 4;  // row within a group of 4
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < rows; s0 += kMfmaSub) {
+    const int srows = min(kMfmaSub, rows - s0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < 16 * kMfmaSub; t += blockDim.x) {
+      const int c = t / kMfmaSub, r = t % kMfmaSub;
+      double v = 0.0;
+      if (c < nloc && r < srows) {
+        const int64_t i = r0 + s0 + r;
+        const int cg = g0 + c;
+        v = cg < n1 ? X1[i + (int64_t)cg * ldx1] : X2[i + (int64_t)(cg - n1) * ldx2] * m[i];
+      }
+      xs[c][r] = v;
+    }
+    __syncthreads();
+    if (jt < k) {
+#pragma unroll 4
+      for (int rb = 0; rb < srows; rb += 4) {
+        const int r = rb + kr;
+        const double a = (jok && r < srows) ? bcol[s0 + r] : 0.0;
+        const double b = xs[lane & 15][r];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+    }
+  }
+  if (jt >= k) return;
+  const int nchunks = gridDim.x;
+  const int c = g0 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = jt + 4 * v + (lane >> 4);
+    if (j < k && (lane & 15) < nloc) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = acc[v];
+  }
+}
+
+// V = Bk Y (n x k times k x nc) on the float64 matrix cores: a wavefront owns
+// 16 rows and up to 64 columns (four 16 x 16 tiles sharing the Bk operand, so
+// Bk is streamed once per 64 columns).  Lane l supplies A[r = l%16][j = l/16] =
+// Bk[r][j] (four 128-byte row runs per instruction) and B[j = l/16][c = l%16] = Y[j][c];
+// its accumulator register v holds D[r = 4v + l/16][c = l%16].
+__global__ __launch_bounds__(256) void k_gemm_nn_mfma(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
+                                                      const double* __restrict__ Y, int64_t ldy, double* __restrict__ V,
+                                                      int64_t ldv, int nc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t rt = ((int64_t)blockIdx.x * 4 + wave) * 16;  // first row of this wavefront
+  if (rt >= n) return;
+  const int c0 = blockIdx.y * 64;
+  const int64_t ra = rt + (lane & 15);
+  const bool rok = ra < n;
+  const int kr = lane >> 4;
+  f64x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < k; j0 += 4) {
+    const int j = j0 + kr;
+    const bool jok = j < k;
+    const double a = (rok && jok) ? Bk[ra + (int64_t)j * ldb] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = c0 + 16 * t + (lane & 15);
+      const double b = (jok && c < nc) ? Y[j + (int64_t)c * ldy] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = c0 + 16 * t + (lane & 15);
+    if (c >= nc) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rt + 4 * v + (lane >> 4);
+      if (r < n) V[r + (int64_t)c * ldv] = acc[t][v];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
                                                         const double* __restrict__ partial, double* __restrict__ H,
                                                         int64_t ldh) {
@@ -379,10 +485,10 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     set_error("gemv_t: weighted columns need the mass vector");
     return KF_EINVAL;
   }
-  // up to 8 right-hand sides in one group; wider sets in groups of 16 along
-  // the grid's z (each group re-reads the basis, but keeps its 4 x 16
-  // accumulators in registers instead of reading LDS for every product)
-  const int CH = nrhs <= 8 ? 1024 : 256;
+  // up to 8 right-hand sides: vector FMAs, rows of a chunk reduced across
+  // lanes; wider sets: the matrix cores in groups of 16 along the grid's z,
+  // chunks of 2048 rows (the sums over rows stay in the accumulators)
+  const int CH = nrhs <= 8 ? 1024 : 2048;
   const int nchunks = ceil_div64(n, CH);
   const size_t need = (size_t)nchunks * k * nrhs;
   if (wk.cap < need) {
@@ -398,7 +504,7 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   }
   const int groups = nrhs <= 8 ? 1 : ceil_div64(nrhs, 16);
   const dim3 grid(nchunks, ceil_div64(k, 64), groups);
-  const size_t lds = sizeof(double) * CH * std::min(nrhs, 16);
+  const size_t lds = nrhs <= 8 ? sizeof(double) * CH * nrhs : 0;
   if (nrhs == 1)
     hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
@@ -412,8 +518,8 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     hipLaunchKernelGGL((k_gemv_t<8, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
                        wk.partial, CH);
   else
-    hipLaunchKernelGGL((k_gemv_t<16, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
+    hipLaunchKernelGGL(k_gemv_t_mfma, grid, dim3(256), 0, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial,
+                       CH);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
                      wk.partial, H, ldh);
@@ -491,8 +597,9 @@ int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, in
     const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 8));
     hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
   } else {
-    const dim3 grid(ceil_div64(n, 256), ceil_div64(nc, 32));
-    hipLaunchKernelGGL((k_gemv_n<32, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
+    // a dense product: on the float64 matrix cores, Bk streamed once per 64 columns
+    const dim3 grid(ceil_div64(n, 64), ceil_div64(nc, 64));
+    hipLaunchKernelGGL(k_gemm_nn_mfma, grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
   }
   KF_HIP(hipGetLastError());
   return KF_OK;
