@@ -193,14 +193,17 @@ __global__ __launch_bounds__(256) void k_gemv_t_mfma(int32_t n, int k, const dou
 // V = Bk Y (n x k times k x nc) on the float64 matrix cores: a wavefront owns
 // 16 rows and up to 64 columns (four 16 x 16 tiles sharing the Bk operand, so
 // Bk is streamed once per 64 columns).  Lane l supplies A[r = l%16][j = l/16] =
-// Bk[r][j] (four 128-byte row runs per instruction) and B[j = l/16][c = l%16] = Y[j][c];
-// its accumulator register v holds D[r = 4v + l/16][c = l%16].
+// Bk[r][j] (four 128-byte row runs per instruction) and B[j = l/16][c = l%16] =
+// Y[j][c], read from a 32 x 64 slice of Y staged in LDS with c contiguous; its
+// accumulator register v holds D[r = 4v + l/16][c = l%16].
+constexpr int kGemmJ = 32;
 __global__ __launch_bounds__(256) void k_gemm_nn_mfma(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
                                                       const double* __restrict__ Y, int64_t ldy, double* __restrict__ V,
                                                       int64_t ldv, int nc) {
+  __shared__ double ys[kGemmJ][64 + 2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t rt = ((int64_t)blockIdx.x * 4 + wave) * 16;  // first row of this wavefront
-  if (rt >= n) return;
+  const bool live = rt < n;
   const int c0 = blockIdx.y * 64;
   const int64_t ra = rt + (lane & 15);
   const bool rok = ra < n;
@@ -208,17 +211,24 @@ __global__ __launch_bounds__(256) void k_gemm_nn_mfma(int32_t n, int k, const do
   f64x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < k; j0 += 4) {
-    const int j = j0 + kr;
-    const bool jok = j < k;
-    const double a = (rok && jok) ? Bk[ra + (int64_t)j * ldb] : 0.0;
+  for (int jb = 0; jb < k; jb += kGemmJ) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kGemmJ * 64; t += blockDim.x) {
+      const int c = t / kGemmJ, j = t % kGemmJ;  // consecutive threads: consecutive j (coalesced)
+      ys[j][c] = (jb + j < k && c0 + c < nc) ? Y[(jb + j) + (int64_t)(c0 + c) * ldy] : 0.0;
+    }
+    __syncthreads();
+    if (!live) continue;
+    const int jn = min(kGemmJ, k - jb);
+#pragma unroll 2
+    for (int j0 = 0; j0 < jn; j0 += 4) {
+      const int j = j0 + kr;
+      const double a = (rok && j < jn) ? Bk[ra + (int64_t)(jb + j) * ldb] : 0.0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = c0 + 16 * t + (lane & 15);
-      const double b = (jok && c < nc) ? Y[j + (int64_t)c * ldy] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ys[j][16 * t + (lane & 15)], acc[t], 0, 0, 0);
     }
   }
+  if (!live) return;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int c = c0 + 16 * t + (lane & 15);
