@@ -391,101 +391,110 @@ __global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict_
 }
 
 // Inverse iteration, one lane per cluster of selected eigenvalues; the
-// recurrences carry their running values in registers so that only
-// independent loads and stores touch memory.
+// recurrences carry their running values in registers.  The lane's work
+// arrays (LU factors and the iterate) are interleaved across lanes, element i
+// of lane c at [i * ldw + c], so that at every step the lanes of a wavefront
+// touch consecutive addresses.  Finished vectors go to Z (m x nsel).
 __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ d, const double* __restrict__ e,
                                               const double* __restrict__ bounds, int ncl,
                                               const int32_t* __restrict__ cstart, const double* __restrict__ sel,
-                                              double* __restrict__ Z, double* __restrict__ scratch) {
+                                              double* __restrict__ Z, double* __restrict__ scratch, int ldw) {
   const int cl = blockIdx.x * blockDim.x + threadIdx.x;
   if (cl >= ncl) return;
   const double tn = fmax(fabs(bounds[0]), fabs(bounds[1]));
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
+  const int64_t blk = (int64_t)m * ldw;
+  double* __restrict__ rinv = scratch + cl;
+  double* __restrict__ u1 = rinv + blk;
+  double* __restrict__ u2 = u1 + blk;
+  double* __restrict__ lm = u2 + blk;
+  double* __restrict__ pv = lm + blk;
+  double* __restrict__ z = pv + blk;
   double prev_lam = -INFINITY;
   for (int s = cstart[cl]; s < cstart[cl + 1]; ++s) {
     double lam = sel[s];
     if (s > cstart[cl] && lam - prev_lam < 10.0 * tiny) lam = prev_lam + 10.0 * tiny;
     prev_lam = lam;
-    double* __restrict__ rinv = scratch + (int64_t)s * 5 * m;
-    double* __restrict__ u1 = rinv + m;
-    double* __restrict__ u2 = u1 + m;
-    double* __restrict__ lm = u2 + m;
-    double* __restrict__ pv = lm + m;
-    double* __restrict__ z = Z + (int64_t)s * m;
     // LU of T - lam I with partial pivoting; row i is (a, b, c) at columns
     // (i, i+1, i+2) while it is being eliminated
     double a = d[0] - lam;
     double b = m > 1 ? e[0] : 0.0;
     for (int i = 0; i + 1 < m; ++i) {
+      const int64_t o = (int64_t)i * ldw;
       const double bi = e[i];
       const double ai1 = d[i + 1] - lam;
       const double ci1 = (i + 2 < m) ? e[i + 1] : 0.0;
       double na, nb;
       if (fabs(a) >= fabs(bi)) {
         const double l = (a != 0.0) ? bi / a : 0.0;
-        pv[i] = 0.0;
-        lm[i] = l;
-        u2[i] = 0.0;
-        u1[i] = b;
+        pv[o] = 0.0;
+        lm[o] = l;
+        u2[o] = 0.0;
+        u1[o] = b;
         if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-        rinv[i] = 1.0 / a;
+        rinv[o] = 1.0 / a;
         na = ai1 - l * b;
         nb = ci1;
       } else {
         const double l = a / bi;
-        pv[i] = 1.0;
-        lm[i] = l;
-        u1[i] = ai1;
-        u2[i] = ci1;
-        rinv[i] = 1.0 / bi;
+        pv[o] = 1.0;
+        lm[o] = l;
+        u1[o] = ai1;
+        u2[o] = ci1;
+        rinv[o] = 1.0 / bi;
         na = b - l * ai1;
         nb = -l * ci1;
       }
       a = na;
       b = nb;
     }
+    const int64_t ol = (int64_t)(m - 1) * ldw;
     if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-    rinv[m - 1] = 1.0 / a;
-    u1[m - 1] = 0.0;
-    u2[m - 1] = 0.0;
-    if (m >= 2) u2[m - 2] = 0.0;
-    for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * (s - cstart[cl]) + 0.1);
+    rinv[ol] = 1.0 / a;
+    u1[ol] = 0.0;
+    u2[ol] = 0.0;
+    if (m >= 2) u2[ol - ldw] = 0.0;
+    for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * (s - cstart[cl]) + 0.1);
     for (int it = 0; it < 3; ++it) {
       // forward: row swaps and elimination, running value in a register
       double y = z[0];
       for (int i = 0; i + 1 < m; ++i) {
-        double nx = z[i + 1];
-        if (pv[i] != 0.0) {
+        const int64_t o = (int64_t)i * ldw;
+        double nx = z[o + ldw];
+        if (pv[o] != 0.0) {
           const double t = y;
           y = nx;
           nx = t;
         }
-        z[i] = y;
-        y = nx - lm[i] * y;
+        z[o] = y;
+        y = nx - lm[o] * y;
       }
-      z[m - 1] = y;
+      z[ol] = y;
       // backward substitution with U (diagonal inverse, two superdiagonals)
       double x1 = 0.0, x2 = 0.0, mx = 0.0;
       for (int i = m - 1; i >= 0; --i) {
-        const double x = (z[i] - u1[i] * x1 - u2[i] * x2) * rinv[i];
-        z[i] = x;
+        const int64_t o = (int64_t)i * ldw;
+        const double x = (z[o] - u1[o] * x1 - u2[o] * x2) * rinv[o];
+        z[o] = x;
         mx = fmax(mx, fabs(x));
         x2 = x1;
         x1 = x;
       }
       const double r = mx > 0.0 ? 1.0 / mx : 0.0;
-      for (int i = 0; i < m; ++i) z[i] *= r;
+      for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] *= r;
       for (int q = cstart[cl]; q < s; ++q) {
         const double* zq = Z + (int64_t)q * m;
         double dot = 0.0;
-        for (int i = 0; i < m; ++i) dot = fma(zq[i], z[i], dot);
-        for (int i = 0; i < m; ++i) z[i] -= dot * zq[i];
+        for (int i = 0; i < m; ++i) dot = fma(zq[i], z[(int64_t)i * ldw], dot);
+        for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] -= dot * zq[i];
       }
       double nrm = 0.0;
-      for (int i = 0; i < m; ++i) nrm = fma(z[i], z[i], nrm);
+      for (int i = 0; i < m; ++i) nrm = fma(z[(int64_t)i * ldw], z[(int64_t)i * ldw], nrm);
       const double rn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-      for (int i = 0; i < m; ++i) z[i] *= rn;
+      for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] *= rn;
     }
+    double* __restrict__ zs = Z + (int64_t)s * m;
+    for (int i = 0; i < m; ++i) zs[i] = z[(int64_t)i * ldw];
   }
 }
 
@@ -566,7 +575,7 @@ int eig_reserve(EigWork& w, int m, int nsel) {
     const size_t ns = std::max<size_t>(nsel, 16);
     if (hipMalloc(&w.Z, sizeof(double) * w.cap_m * ns) != hipSuccess ||
         hipMalloc(&w.Y, sizeof(double) * w.cap_m * ns) != hipSuccess ||
-        hipMalloc(&w.scratch, sizeof(double) * 5 * w.cap_m * ns) != hipSuccess ||
+        hipMalloc(&w.scratch, sizeof(double) * 6 * w.cap_m * (ns + 64)) != hipSuccess ||
         hipMalloc(&w.sel, sizeof(double) * ns) != hipSuccess ||
         hipMalloc(&w.cl, sizeof(int32_t) * (ns + 1)) != hipSuccess) {
       set_error("eig_reserve: allocation failed");
@@ -613,8 +622,9 @@ int eig_vectors(EigWork& w, int k, const double* theta_sel, const int32_t* clust
   KF_TRY(eig_reserve(w, k, nsel));
   KF_HIP(hipMemcpyAsync(w.sel, theta_sel, sizeof(double) * nsel, hipMemcpyHostToDevice, st));
   KF_HIP(hipMemcpyAsync(w.cl, cluster_start, sizeof(int32_t) * (nclusters + 1), hipMemcpyHostToDevice, st));
+  const int ldw = cdiv(nclusters, 64) * 64;  // <= nsel + 63
   hipLaunchKernelGGL(k_invit, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters, w.cl,
-                     w.sel, w.Z, w.scratch);
+                     w.sel, w.Z, w.scratch, ldw);
   KF_HIP(hipGetLastError());
   const int grid = cdiv(nsel, 4);
   const int mt = cdiv(k, 64);
