@@ -189,8 +189,9 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
 int kf_destroy(kf_problem* p);
 
 /* The dense symmetric eigensolver that kf_solve applies to the projected
- * pencil of eq. projevp (Section 2.1; the basis is M-orthonormal, so the
- * pencil is the symmetric matrix B^T S B): Householder tridiagonalisation,
+ * pencil of eq. projevp (Section 2.1; the basis is M-orthonormal up to
+ * E = B^T M B - I, so the pencil is the symmetric matrix
+ * B^T S B - (E B^T S B + B^T S B E)/2 to second order): Householder tridiagonalisation,
  * bisection, inverse iteration, back-transformation, all on the GPU.
  * A: host k x k column-major (the two triangles are averaged), 1 <= k <= 2048.
  * theta[k] (host) receives all eigenvalues ascending.  If Y != NULL, the
@@ -248,8 +249,8 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
 int kf_result_free(kf_result* r);
 
 /* Copy up to max_cols columns of the current Krylov basis B (n x k,
- * M-orthonormal) to host memory out[n x max_cols] column-major; *ncols
- * receives the number copied. */
+ * M-orthonormal to the level reported as kf_result.orth_error) to host memory
+ * out[n x max_cols] column-major; *ncols receives the number copied. */
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols);
 
 /* ---- batches of independent problems (one batched time-stepping launch) ----
@@ -257,7 +258,8 @@ int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* n
  * members advance together: one filter application of the whole batch is a
  * captured graph of max(L)-1 fused-step launches over the stacked
  * (block-diagonal) operator, replayed once per Krylov iteration.
- * Orthogonalisation and Rayleigh-Ritz run per member. */
+ * Orthogonalisation and Rayleigh-Ritz run per member, on one stream per
+ * member driven by kf_options.batch_workers host threads. */
 typedef struct kf_problem_desc {
   kf_csr S;
   const double* m_diag;  /* host (or device, with S.on_device) */
