@@ -411,8 +411,8 @@ def main():
     ap.add_argument("--workload", default="grid3d_96")
     ap.add_argument("--m-max", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--check-every", type=int, default=4)
-    ap.add_argument("--check-growth", type=float, default=0.15)
+    ap.add_argument("--check-every", type=int, default=2)
+    ap.add_argument("--check-growth", type=float, default=0.3)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

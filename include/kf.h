@@ -77,7 +77,10 @@ typedef struct kf_options {
                             (>= 1); the final state is always checked */
   double check_growth;   /* additionally wait until the basis has grown by
                             this fraction since the last check (0: no wait);
-                            checks cost O(k^3) in the basis size k */
+                            once pairs have converged the wait is halved, and
+                            it is shortened further when the residuals of the
+                            missing pairs predict convergence sooner; checks
+                            cost O(k^3) in the basis size k */
   int32_t full_reorth;   /* 1: classical Gram-Schmidt twice against the whole
                             basis; 0: once against the last two blocks (C is
                             M-self-adjoint, so the filtered block is
@@ -165,7 +168,7 @@ typedef struct kf_result {
   int32_t full_passes;    /* Gram-Schmidt passes over the whole basis */
 } kf_result;
 
-/* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0, three-term
+/* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0.3, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
  * drop_tol 1e-10, reorth_tol 1e-9, proj_every 4, refine 2, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,

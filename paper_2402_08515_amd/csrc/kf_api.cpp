@@ -1005,7 +1005,7 @@ void kf_default_options(kf_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = KF_FP64;
   o->check_every = 1;
-  o->check_growth = 0.0;
+  o->check_growth = 0.3;
   o->full_reorth = 0;
   o->target = 0;
   o->max_iters = 0;
@@ -1311,6 +1311,8 @@ struct SolveState {
   CheckOut fin;
   int fin_at = -1, refines = 0, next_refine = 0;
   int proj_every = 1, since_proj = 0;
+  int pred_k = -1;  // basis size and unconverged candidates at the previous check
+  std::vector<double> pred_theta, pred_res;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -1318,6 +1320,58 @@ int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
   KF_HIP(hipEventElapsedTime(&ms, a, b));
   acc += ms * 1e-3;
   return KF_OK;
+}
+
+// Basis size of the next Rayleigh-Ritz check: after growth by check_growth,
+// or sooner when the residuals of the pairs still missing from the target
+// predict convergence sooner.  Each unconverged candidate in the interval is
+// matched with the nearest Ritz value of the previous check; from the
+// geometric decrease of its residual per basis column it gets a predicted
+// number of columns to the tolerance, and the check is placed where the
+// missing-th fastest of them arrives (with 10 % to spare).
+int next_check_at(const kf_problem* p, SolveState& s) {
+  int next = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));
+  if (s.target <= 0 || p->opt.check_growth <= 0.0) return next;
+  const int missing = s.target - distinct_count(s.chk.acc_theta, s.b);
+  const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
+  std::vector<double> th_now, res_now;
+  for (size_t i = 0; i < s.chk.cand_theta.size(); ++i) {
+    const double th = s.chk.cand_theta[i], res = s.chk.cand_res[i];
+    if (th >= lo2 && th <= hi2 && res > s.tol_loop && std::isfinite(res)) {
+      th_now.push_back(th);
+      res_now.push_back(res);
+    }
+  }
+  if (missing > 0 && s.pred_k >= 0 && s.cur > s.pred_k && !s.pred_theta.empty()) {
+    std::vector<double> cols;
+    size_t q = 0;
+    for (size_t i = 0; i < th_now.size(); ++i) {
+      while (q + 1 < s.pred_theta.size() &&
+             std::fabs(s.pred_theta[q + 1] - th_now[i]) <= std::fabs(s.pred_theta[q] - th_now[i]))
+        ++q;
+      if (std::fabs(s.pred_theta[q] - th_now[i]) > 1e-2 * th_now[i] || !(res_now[i] < s.pred_res[q])) continue;
+      const double rate = std::log(res_now[i] / s.pred_res[q]) / (s.cur - s.pred_k);  // per column, < 0
+      const double c = std::log(s.tol_loop / res_now[i]) / rate;
+      if (std::isfinite(c) && c > 0.0) cols.push_back(c);
+    }
+    if (!cols.empty()) {
+      // (pairs without a Ritz value in the interval yet are not predictable:
+      // then the slowest predictable one sets an early check, which is cheap
+      // next to overshooting by a growth step)
+      std::sort(cols.begin(), cols.end());
+      const size_t r = (size_t)std::min<int>(missing, (int)cols.size()) - 1;
+      next = std::min(next, s.cur + (int)std::ceil(1.1 * cols[r]));
+    }
+  }
+  // once pairs converge, a growth step is halved: the rest typically follow
+  // within a fraction of the basis, Krylov convergence accelerates (so the
+  // geometric prediction above runs late), and an early check costs less
+  // than an overshoot
+  if (missing > 0 && missing < s.target) next = s.cur + std::max(1, (next - s.cur + 1) / 2);
+  s.pred_k = s.cur;
+  s.pred_theta = th_now;
+  s.pred_res = res_now;
+  return next;
 }
 
 // Mixed mode with a target: the float64 refinement of the current Ritz block.
@@ -1465,7 +1519,7 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   s.pending += kept;
   if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
     KF_TRY(solve_check_now(p, s));
-    s.next_check = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));
+    s.next_check = next_check_at(p, s);
     if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
       if (!s.refine) {
         s.done = true;

@@ -280,7 +280,7 @@ def _take_result(res, n: int) -> SolveResult:
         lib().kf_result_free(res)
 
 
-def _options(precision="fp64", check_every=1, check_growth=0.0, full_reorth=False, target=0, max_iters=0,
+def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=2, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
              autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None):
     opt = OptionsT()
