@@ -18,20 +18,6 @@ namespace {
 
 inline int ceil_div64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber
-// them so that each XCD receives one contiguous range of row slices and its
-// L2 keeps the neighbouring rows it gathers.
-__device__ __forceinline__ int xcd_map(int i, int nblk) {
-  const int q = nblk >> 3, r = nblk & 7;
-  const int x = i & 7, t = i >> 3;
-  return (x < r) ? x * (q + 1) + t : r * (q + 1) + (x - r) * q + t;
-}
-
-template <typename T, int B>
-struct alignas((B * sizeof(T)) >= 16 ? 16 : (B * sizeof(T))) Row {
-  T v[B];
-};
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -171,7 +157,6 @@ __global__ __launch_bounds__(256) void k_gemv_t_mfma(int32_t n, int k, const dou
     }
     __syncthreads();
     if (jt < k) {
-#pragma unroll 4
       for (int rb = 0; rb < srows; rb += 4) {
         const int r = rb + kr;
         const double a = (jok && r < srows) ? bcol[s0 + r] : 0.0;
@@ -220,7 +205,6 @@ __global__ __launch_bounds__(256) void k_gemm_nn_mfma(int32_t n, int k, const do
     __syncthreads();
     if (!live) continue;
     const int jn = min(kGemmJ, k - jb);
-#pragma unroll 2
     for (int j0 = 0; j0 < jn; j0 += 4) {
       const int j = j0 + kr;
       const double a = (rok && j < jn) ? Bk[ra + (int64_t)(jb + j) * ldb] : 0.0;

@@ -37,12 +37,6 @@ struct alignas((B * sizeof(T)) >= 16 ? 16 : (B * sizeof(T))) Row {
   T v[B];
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
 // ---------------------------------------------------------------- SELL build
 __global__ __launch_bounds__(256) void k_sell_stats(int32_t n, int32_t nslices, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col, int32_t* __restrict__ width,
