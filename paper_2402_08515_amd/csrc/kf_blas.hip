@@ -114,38 +114,47 @@ __global__ __launch_bounds__(256) void k_gemv_t(int32_t n, int k, const double* 
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// H = Bk^T diag(w) X for many right-hand sides on the float64 matrix cores
-// (v_mfma_f64_16x16x4f64: a 16 x 4 by 4 x 16 product per instruction, the
-// sum over rows happening inside the accumulator, so no cross-lane
-// reductions).  Workgroup: a chunk of TCH rows, 64 basis columns (one 16-column
-// tile per wavefront), 16 right-hand sides (grid z); the X chunk is staged in
-// LDS in sub-chunks of 256 rows.  Lane l supplies A[j = l%16][r = l/16] =
-// Bk[r][j] and B[r = l/16][c = l%16] = X[r][c]; its accumulator register v holds
-// D[j = 4v + l/16][c = l%16] (the f64 layout interleaves rows by register).
+// H = Bk^T diag(w) X for four or more right-hand sides on the float64 matrix
+// cores (v_mfma_f64_16x16x4f64: a 16 x 4 by 4 x 16 product per instruction,
+// the sum over rows happening inside the accumulator, so no cross-lane
+// reductions).  Workgroup: a chunk of TCH rows and 128 basis columns (eight
+// wavefronts, one 16-column tile each), NX right-hand sides of group
+// blockIdx.z (NX = 8 or 16; absent ones are zero).  The weighted X chunk is
+// staged in LDS 256 rows at a time as [row/4][c][row%4].  Within each 16-row
+// block, lane l (c = l%16, q = l/16) owns rows 4q .. 4q+3: it loads them as
+// one 32-byte run of basis column c of its tile and reads the matching four
+// X values of right-hand side c as one 32-byte LDS run; instruction t of the
+// four takes A[j = c][r = q] = Bk[4q+t][c] and B[r = q][c] = X[4q+t][c].
+// Its accumulator register v holds D[j = 4v + l/16][c = l%16] (the f64
+// layout interleaves rows by register).  `vec`: Bk's columns are 32-byte
+// aligned (else the run is loaded one element at a time).
 constexpr int kMfmaSub = 256;
-__global__ __launch_bounds__(256) void k_gemv_t_mfma(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
-                                                     const double* __restrict__ X1, int n1, int64_t ldx1,
-                                                     const double* __restrict__ X2, int n2, int64_t ldx2,
-                                                     const double* __restrict__ m, double* __restrict__ partial,
-                                                     int TCH) {
-  __shared__ double xs[16][kMfmaSub + 4];
+constexpr int kMfmaWaves = 8;
+template <int NX, int PF>
+__global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma(
+    int32_t n, int k, const double* __restrict__ Bk, int64_t ldb, const double* __restrict__ X1, int n1, int64_t ldx1,
+    const double* __restrict__ X2, int n2, int64_t ldx2, const double* __restrict__ m, double* __restrict__ partial,
+    int TCH, int vec) {
+  static_assert(kMfmaSub % (16 * PF) == 0, "a batch of PF 16-row blocks must divide the staged rows");
+  __shared__ double4 xs[kMfmaSub / 4][NX];
+  double* xsd = reinterpret_cast<double*>(&xs[0][0]);
   const int nrhs = n1 + n2;
-  const int g0 = blockIdx.z * 16;
-  const int nloc = min(16, nrhs - g0);
+  const int g0 = blockIdx.z * NX;
+  const int nloc = min(NX, nrhs - g0);
   const int chunk = blockIdx.x;
   const int64_t r0 = (int64_t)chunk * TCH;
   const int rows = (int)std::min<int64_t>(TCH, (int64_t)n - r0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int jt = blockIdx.y * 64 + wave * 16;  // first column of this wavefront's tile
-  const int ja = jt + (lane & 15);             // column this lane feeds
-  const bool jok = ja < k;
-  const double* __restrict__ bcol = Bk + (int64_t)(jok ? ja : 0) * ldb + r0;
-  const int kr = lane >> 4;  // row within a group of 4
+  const int jt = (blockIdx.y * kMfmaWaves + wave) * 16;  // first column of this wavefront's tile
+  const int q = lane >> 4, cl = lane & 15;
+  const bool jok = jt + cl < k;
+  const bool cok = cl < nloc;
+  const double* __restrict__ bcol = Bk + (int64_t)(jok ? jt + cl : 0) * ldb + r0;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int s0 = 0; s0 < rows; s0 += kMfmaSub) {
     const int srows = min(kMfmaSub, rows - s0);
     __syncthreads();
-    for (int t = threadIdx.x; t < 16 * kMfmaSub; t += blockDim.x) {
+    for (int t = threadIdx.x; t < NX * kMfmaSub; t += 64 * kMfmaWaves) {
       const int c = t / kMfmaSub, r = t % kMfmaSub;
       double v = 0.0;
       if (c < nloc && r < srows) {
@@ -153,25 +162,41 @@ __global__ __launch_bounds__(256) void k_gemv_t_mfma(int32_t n, int k, const dou
         const int cg = g0 + c;
         v = cg < n1 ? X1[i + (int64_t)cg * ldx1] : X2[i + (int64_t)(cg - n1) * ldx2] * m[i];
       }
-      xs[c][r] = v;
+      xsd[((r >> 2) * NX + c) * 4 + (r & 3)] = v;
     }
     __syncthreads();
-    if (jt < k) {
-      for (int rb = 0; rb < srows; rb += 4) {
-        const int r = rb + kr;
-        const double a = (jok && r < srows) ? bcol[s0 + r] : 0.0;
-        const double b = xs[lane & 15][r];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    if (jt >= k) continue;
+    for (int rb = 0; rb < srows; rb += 16 * PF) {
+      double4 a[PF];
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int r = rb + 16 * p + 4 * q;
+        if (vec && jok && r + 3 < srows) {
+          a[p] = *reinterpret_cast<const double4*>(bcol + s0 + r);
+        } else {
+          a[p].x = (jok && r < srows) ? bcol[s0 + r] : 0.0;
+          a[p].y = (jok && r + 1 < srows) ? bcol[s0 + r + 1] : 0.0;
+          a[p].z = (jok && r + 2 < srows) ? bcol[s0 + r + 2] : 0.0;
+          a[p].w = (jok && r + 3 < srows) ? bcol[s0 + r + 3] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        // rows past srows hold zeros in LDS
+        const double4 x = cok ? xs[(rb >> 2) + 4 * p + q][cl] : (double4){0.0, 0.0, 0.0, 0.0};
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].x, x.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].y, x.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].z, x.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].w, x.w, acc, 0, 0, 0);
       }
     }
   }
   if (jt >= k) return;
   const int nchunks = gridDim.x;
-  const int c = g0 + (lane & 15);
-#pragma unroll
+  const int c = g0 + cl;
   for (int v = 0; v < 4; ++v) {
-    const int j = jt + 4 * v + (lane >> 4);
-    if (j < k && (lane & 15) < nloc) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = acc[v];
+    const int j = jt + 4 * v + q;
+    if (j < k && cok) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = acc[v];
   }
 }
 
@@ -479,10 +504,12 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     set_error("gemv_t: weighted columns need the mass vector");
     return KF_EINVAL;
   }
-  // up to 8 right-hand sides: vector FMAs, rows of a chunk reduced across
-  // lanes; wider sets: the matrix cores in groups of 16 along the grid's z,
-  // chunks of 2048 rows (the sums over rows stay in the accumulators)
-  const int CH = nrhs <= 8 ? 1024 : 2048;
+  // up to 3 right-hand sides: vector FMAs, rows of a chunk reduced across
+  // lanes; wider sets: the matrix cores in groups of 8 or 16 along the
+  // grid's z, chunks of 2048 rows (the sums over rows stay in the
+  // accumulators)
+  const bool mfma = nrhs > 3;
+  const int CH = mfma ? 2048 : 1024;
   const int nchunks = ceil_div64(n, CH);
   const size_t need = (size_t)nchunks * k * nrhs;
   if (wk.cap < need) {
@@ -496,24 +523,29 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     }
     wk.cap = cap;
   }
-  const int groups = nrhs <= 8 ? 1 : ceil_div64(nrhs, 16);
-  const dim3 grid(nchunks, ceil_div64(k, 64), groups);
-  const size_t lds = nrhs <= 8 ? sizeof(double) * CH * nrhs : 0;
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
-  else if (nrhs <= 2)
-    hipLaunchKernelGGL((k_gemv_t<2, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
-  else if (nrhs <= 4)
-    hipLaunchKernelGGL((k_gemv_t<4, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
-  else if (nrhs <= 8)
-    hipLaunchKernelGGL((k_gemv_t<8, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
-                       wk.partial, CH);
-  else
-    hipLaunchKernelGGL(k_gemv_t_mfma, grid, dim3(256), 0, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial,
-                       CH);
+  if (!mfma) {
+    const dim3 grid(nchunks, ceil_div64(k, 64), 1);
+    const size_t lds = sizeof(double) * CH * nrhs;
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_gemv_t<1, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                         wk.partial, CH);
+    else if (nrhs == 2)
+      hipLaunchKernelGGL((k_gemv_t<2, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                         wk.partial, CH);
+    else
+      hipLaunchKernelGGL((k_gemv_t<4, 4, 2>), grid, dim3(256), lds, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m,
+                         wk.partial, CH);
+  } else {
+    const int vec = ((uintptr_t)Bk % 32 == 0 && ldb % 4 == 0) ? 1 : 0;
+    const int cols = 16 * kMfmaWaves;
+    if (nrhs <= 8)
+      hipLaunchKernelGGL((k_gemv_t_mfma<8, 4>), dim3(nchunks, ceil_div64(k, cols), 1), dim3(64 * kMfmaWaves), 0, st, n,
+                         k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH, vec);
+    else
+      hipLaunchKernelGGL((k_gemv_t_mfma<16, 2>), dim3(nchunks, ceil_div64(k, cols), ceil_div64(nrhs, 16)),
+                         dim3(64 * kMfmaWaves), 0, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH,
+                         vec);
+  }
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
                      wk.partial, H, ldh);
