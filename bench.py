@@ -330,9 +330,14 @@ def bench_learned(args):
     """Learned filter weights: the network is trained on the GPU (50,000
     samples of (omega_min, omega_max, tau, lambda_max) from seed 4 stream 0),
     then intervals from the evaluation law (seed 4 stream 1) on the 3D cube
-    with 64 cells per axis are solved to all their eigenpairs with the
-    Fourier weights and with the weights the network proposes (the judge
-    falls back to the Fourier weights when they leak less)."""
+    with 128 cells per axis (2,048,383 DOFs) are solved to all their
+    eigenpairs with the Fourier weights and with the weights the network
+    proposes (the judge falls back to the Fourier weights when they leak
+    less).  Intervals holding more distinct eigenvalues than
+    --learned-max-target are skipped (a single start vector needs a basis
+    several times the target).  Stepping is fp64 by default: the cube's
+    eigenvalues of multiplicity 6 defeat fp32 stepping from one start vector
+    (round-off seeds the directions the start vector lacks)."""
     import numpy as np
     import torch
 
@@ -357,14 +362,15 @@ def bench_learned(args):
     spec = grid_spectrum(3, n)
     rows = []
     for (lo, hi) in grid3d_128_intervals(32):
-        tgt = distinct_target(spec, lo, hi, 1)[0]
+        tgt, vals, _ = distinct_target(spec, lo, hi, 1)
         if tgt == 0 or tgt > args.learned_max_target:
             continue
         tau, L = kf.time_step_rule(lam, lo)
         V0 = start_block(S.shape[0], 1, 4)
         rec = {"interval": [lo, hi], "target": tgt, "L": L}
         for kind in ("fourier", "learned"):
-            prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, check_growth=0.1)
+            prob = kf.Problem(S, m, lo, hi, tau, L, precision=args.learned_precision, target=tgt, check_every=2,
+                              check_growth=0.1)
             if kind == "learned":
                 w, used, jl, jf = net.weights(lo, hi, tau, lam, L)
                 rec.update(used_learned=used, j_learned=jl, j_fourier=jf)
@@ -376,7 +382,12 @@ def bench_learned(args):
             t1 = time.perf_counter()
             r = prob.solve(V0, m_max=1024, tol=args.tol)
             dt = time.perf_counter() - t1
-            rec[kind] = {"pairs": int(r.omega2.size), "krylov_steps": r.krylov_steps, "seconds": dt}
+            err = None
+            if r.omega2.size:
+                near = vals[np.abs(r.omega2[:, None] - vals[None, :]).argmin(axis=1)]
+                err = float(np.max(np.abs(r.omega2 - near) / near))
+            rec[kind] = {"pairs": int(r.omega2.size), "krylov_steps": r.krylov_steps, "seconds": dt,
+                         "max_rel_err_vs_closed_form": err}
         rows.append(rec)
         print(f"[bench] [{lo:.2f}, {hi:.2f}] target {tgt}: fourier {rec['fourier']} learned {rec['learned']} "
               f"used={rec['used_learned']}", file=sys.stderr, flush=True)
@@ -391,7 +402,8 @@ def bench_learned(args):
         "value": None,
         "unit": "s",
         "n_gpus": 1,
-        "config": {"workload": f"grid3d_{n} learned-vs-Fourier", "intervals": len(rows), "tol": args.tol},
+        "config": {"workload": f"grid3d_{n} learned-vs-Fourier", "intervals": len(rows), "tol": args.tol,
+                   "precision": args.learned_precision, "max_target": args.learned_max_target},
         "train_seconds": t_train,
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
         "fourier_seconds": tf,
@@ -420,9 +432,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--mlp-samples", type=int, default=50000)
     ap.add_argument("--mlp-epochs", type=int, default=8)
-    ap.add_argument("--learned-n", type=int, default=64)
-    ap.add_argument("--learned-count", type=int, default=8)
-    ap.add_argument("--learned-max-target", type=int, default=150)
+    ap.add_argument("--learned-n", type=int, default=128)
+    ap.add_argument("--learned-count", type=int, default=32)
+    ap.add_argument("--learned-max-target", type=int, default=200)
+    ap.add_argument("--learned-precision", default="fp64", choices=("mixed", "fp64"))
     ap.add_argument("--batch-iters", type=int, default=24,
                     help="Krylov iterations per member in the batch benchmark (the full targets need thousands)")
     ap.add_argument("--no-sequential", action="store_true")
