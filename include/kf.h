@@ -170,7 +170,7 @@ typedef struct kf_result {
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0.3, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, reorth_tol 1e-9, proj_every 4, refine 2, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-9, proj_every 12, refine 2, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);

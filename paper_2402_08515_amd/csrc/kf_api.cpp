@@ -1011,7 +1011,7 @@ void kf_default_options(kf_options* o) {
   o->max_iters = 0;
   o->drop_tol = 1e-10;
   o->reorth_tol = 1e-9;
-  o->proj_every = 4;
+  o->proj_every = 12;
   o->refine = 2;
   o->want_vectors = 0;
   o->index_bytes = 0;

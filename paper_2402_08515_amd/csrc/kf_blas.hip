@@ -119,24 +119,26 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // the sum over rows happening inside the accumulator, so no cross-lane
 // reductions).  Workgroup: a chunk of TCH rows and 128 basis columns (eight
 // wavefronts, one 16-column tile each), NX right-hand sides of group
-// blockIdx.z (NX = 8 or 16; absent ones are zero).  The weighted X chunk is
-// staged in LDS 256 rows at a time as [row/4][c][row%4].  Within each 16-row
-// block, lane l (c = l%16, q = l/16) owns rows 4q .. 4q+3: it loads them as
-// one 32-byte run of basis column c of its tile and reads the matching four
-// X values of right-hand side c as one 32-byte LDS run; instruction t of the
-// four takes A[j = c][r = q] = Bk[4q+t][c] and B[r = q][c] = X[4q+t][c].
-// Its accumulator register v holds D[j = 4v + l/16][c = l%16] (the f64
-// layout interleaves rows by register).  `vec`: Bk's columns are 32-byte
-// aligned (else the run is loaded one element at a time).
-constexpr int kMfmaSub = 256;
+// blockIdx.z (NX = 8, 16 or 32; absent ones are zero; 32 = two 16-wide
+// accumulators sharing each basis operand).  The weighted X chunk is staged
+// in LDS SUB rows at a time as [row/4][c][row%4].  Within each 16-row block,
+// lane l (c = l%16, q = l/16) owns rows 4q .. 4q+3: it loads them as one
+// 32-byte run of basis column c of its tile and reads the matching four X
+// values of right-hand side c (and c + 16) as one 32-byte LDS run each;
+// instruction t of the four takes A[j = c][r = q] = Bk[4q+t][c] and
+// B[r = q][c] = X[4q+t][c].  Its accumulator register v holds
+// D[j = 4v + l/16][c = l%16] (the f64 layout interleaves rows by register).
+// `vec`: Bk's columns are 32-byte aligned (else the run is loaded one
+// element at a time).
 constexpr int kMfmaWaves = 8;
-template <int NX, int PF>
+template <int NX, int SUB, int PF>
 __global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma(
     int32_t n, int k, const double* __restrict__ Bk, int64_t ldb, const double* __restrict__ X1, int n1, int64_t ldx1,
     const double* __restrict__ X2, int n2, int64_t ldx2, const double* __restrict__ m, double* __restrict__ partial,
     int TCH, int vec) {
-  static_assert(kMfmaSub % (16 * PF) == 0, "a batch of PF 16-row blocks must divide the staged rows");
-  __shared__ double4 xs[kMfmaSub / 4][NX];
+  static_assert(SUB % (16 * PF) == 0, "a batch of PF 16-row blocks must divide the staged rows");
+  constexpr int NA = NX > 16 ? 2 : 1;  // accumulators per lane
+  __shared__ double4 xs[SUB / 4][NX];
   double* xsd = reinterpret_cast<double*>(&xs[0][0]);
   const int nrhs = n1 + n2;
   const int g0 = blockIdx.z * NX;
@@ -148,14 +150,16 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma(
   const int jt = (blockIdx.y * kMfmaWaves + wave) * 16;  // first column of this wavefront's tile
   const int q = lane >> 4, cl = lane & 15;
   const bool jok = jt + cl < k;
-  const bool cok = cl < nloc;
+  bool cok[NA];
+  for (int h = 0; h < NA; ++h) cok[h] = cl + 16 * h < nloc;
   const double* __restrict__ bcol = Bk + (int64_t)(jok ? jt + cl : 0) * ldb + r0;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s0 = 0; s0 < rows; s0 += kMfmaSub) {
-    const int srows = min(kMfmaSub, rows - s0);
+  f64x4 acc[NA];
+  for (int h = 0; h < NA; ++h) acc[h] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < rows; s0 += SUB) {
+    const int srows = min(SUB, rows - s0);
     __syncthreads();
-    for (int t = threadIdx.x; t < NX * kMfmaSub; t += 64 * kMfmaWaves) {
-      const int c = t / kMfmaSub, r = t % kMfmaSub;
+    for (int t = threadIdx.x; t < NX * SUB; t += 64 * kMfmaWaves) {
+      const int c = t / SUB, r = t % SUB;
       double v = 0.0;
       if (c < nloc && r < srows) {
         const int64_t i = r0 + s0 + r;
@@ -182,21 +186,27 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma(
       }
 #pragma unroll
       for (int p = 0; p < PF; ++p) {
-        // rows past srows hold zeros in LDS
-        const double4 x = cok ? xs[(rb >> 2) + 4 * p + q][cl] : (double4){0.0, 0.0, 0.0, 0.0};
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].x, x.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].y, x.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].z, x.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].w, x.w, acc, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < NA; ++h) {
+          // rows past srows hold zeros in LDS
+          const double4 x = cok[h] ? xs[(rb >> 2) + 4 * p + q][cl + 16 * h] : (double4){0.0, 0.0, 0.0, 0.0};
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].x, x.x, acc[h], 0, 0, 0);
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].y, x.y, acc[h], 0, 0, 0);
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].z, x.z, acc[h], 0, 0, 0);
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p].w, x.w, acc[h], 0, 0, 0);
+        }
       }
     }
   }
   if (jt >= k) return;
   const int nchunks = gridDim.x;
-  const int c = g0 + cl;
-  for (int v = 0; v < 4; ++v) {
-    const int j = jt + 4 * v + q;
-    if (j < k && cok) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = acc[v];
+  for (int h = 0; h < NA; ++h) {
+    if (!cok[h]) continue;
+    const int c = g0 + cl + 16 * h;
+    for (int v = 0; v < 4; ++v) {
+      const int j = jt + 4 * v + q;
+      if (j < k) partial[((int64_t)j * nrhs + c) * nchunks + chunk] = acc[h][v];
+    }
   }
 }
 
@@ -505,9 +515,9 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     return KF_EINVAL;
   }
   // up to 3 right-hand sides: vector FMAs, rows of a chunk reduced across
-  // lanes; wider sets: the matrix cores in groups of 8 or 16 along the
-  // grid's z, chunks of 2048 rows (the sums over rows stay in the
-  // accumulators)
+  // lanes; wider sets: the matrix cores, one group of 8 or 16, else groups
+  // of 32 along the grid's z, chunks of 2048 rows (the sums over rows stay
+  // in the accumulators)
   const bool mfma = nrhs > 3;
   const int CH = mfma ? 2048 : 1024;
   const int nchunks = ceil_div64(n, CH);
@@ -538,13 +548,16 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   } else {
     const int vec = ((uintptr_t)Bk % 32 == 0 && ldb % 4 == 0) ? 1 : 0;
     const int cols = 16 * kMfmaWaves;
+    const dim3 block(64 * kMfmaWaves);
     if (nrhs <= 8)
-      hipLaunchKernelGGL((k_gemv_t_mfma<8, 4>), dim3(nchunks, ceil_div64(k, cols), 1), dim3(64 * kMfmaWaves), 0, st, n,
-                         k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH, vec);
+      hipLaunchKernelGGL((k_gemv_t_mfma<8, 256, 4>), dim3(nchunks, ceil_div64(k, cols), 1), block, 0, st, n, k, Bk,
+                         ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH, vec);
+    else if (nrhs <= 16)
+      hipLaunchKernelGGL((k_gemv_t_mfma<16, 256, 2>), dim3(nchunks, ceil_div64(k, cols), 1), block, 0, st, n, k, Bk,
+                         ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH, vec);
     else
-      hipLaunchKernelGGL((k_gemv_t_mfma<16, 2>), dim3(nchunks, ceil_div64(k, cols), ceil_div64(nrhs, 16)),
-                         dim3(64 * kMfmaWaves), 0, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH,
-                         vec);
+      hipLaunchKernelGGL((k_gemv_t_mfma<32, 128, 2>), dim3(nchunks, ceil_div64(k, cols), ceil_div64(nrhs, 32)), block,
+                         0, st, n, k, Bk, ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH, vec);
   }
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_partial, dim3(ceil_div64((int64_t)k * nrhs, 4)), dim3(256), 0, st, nchunks, k, nrhs,
