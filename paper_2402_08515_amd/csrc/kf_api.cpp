@@ -92,6 +92,10 @@ struct kf_problem {
   // batch members with their own stream (concurrent projection work)
   bool own_stream = false;
   hipEvent_t sync_ev = nullptr;
+  // pinned host staging for the values read back at every Krylov step
+  // (copies into it are queued without blocking the host)
+  char* pin = nullptr;
+  size_t pin_cap = 0;
 };
 
 struct kf_batch {
@@ -115,6 +119,7 @@ struct kf_batch {
 
 namespace {
 
+constexpr size_t kPinBytes = (size_t)64 << 10;  // pinned staging for per-step readbacks
 constexpr int kSmall = 4096;
 // offsets of the device scalars in kf_problem::small used by the
 // orthogonalisation (the Rayleigh-Ritz check uses 1024.. and 2048..)
@@ -320,6 +325,11 @@ int ensure_misc(kf_problem* p) {
   KF_TRY(dalloc(&p->SV, (size_t)p->n * 64));
   KF_TRY(dalloc(&p->small, kSmall));
   KF_TRY(dalloc(&p->flags, 64));
+  if (hipHostMalloc((void**)&p->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+    p->pin = nullptr;
+    return fail(KF_ENOMEM, "kf: cannot allocate the pinned staging buffer");
+  }
+  p->pin_cap = kPinBytes;
   const double one = 1.0;
   KF_HIP(hipMemcpy(p->small + kOne, &one, sizeof(double), hipMemcpyHostToDevice));
   return KF_OK;
@@ -348,6 +358,40 @@ int ensure_misc(kf_problem* p) {
 // kb = c0), so the norms before each pass cost no launch of their own.
 int rr_update(kf_problem* p, int c0, int nc);
 int repair_block(kf_problem* p, int p0, int pn);
+
+// Device-to-host reads of a few values through the problem's pinned staging
+// buffer: `get` queues the copy without blocking the host (a copy into
+// pageable memory waits for the stream, so a step's three or four reads
+// would cost as many round trips), `land` moves the values to their
+// destinations after the caller has synchronised the stream.  Reads that do
+// not fit go straight to their destination.
+struct Readback {
+  kf_problem* p;
+  size_t off = 0;
+  struct Item {
+    void* dst;
+    size_t off, bytes;
+  };
+  Item items[16];
+  int nitems = 0;
+  explicit Readback(kf_problem* q) : p(q) {}
+  int get(void* dst, const void* src, size_t bytes) {
+    off = (off + 15) & ~(size_t)15;
+    if (!p->pin || off + bytes > p->pin_cap || nitems == 16) {
+      KF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->st));
+      return KF_OK;
+    }
+    KF_HIP(hipMemcpyAsync(p->pin + off, src, bytes, hipMemcpyDeviceToHost, p->st));
+    items[nitems++] = Item{dst, off, bytes};
+    off += bytes;
+    return KF_OK;
+  }
+  void land() {
+    for (int i = 0; i < nitems; ++i) std::memcpy(items[i].dst, p->pin + items[i].off, items[i].bytes);
+    nitems = 0;
+    off = 0;
+  }
+};
 
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
                hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr,
@@ -399,10 +443,8 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   std::vector<double> hv((size_t)ld1 * nb);
   std::vector<int32_t> fl((size_t)nb);
   bool have = false;  // hv and fl hold the final device values
-  auto fetch = [&](const double* src, size_t count, void* dst) -> int {
-    KF_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-    return KF_OK;
-  };
+  Readback rb(p);
+  auto fetch = [&](const double* src, size_t count, void* dst) -> int { return rb.get(dst, src, sizeof(double) * count); };
   // in-block CGS2 and normalisation of column j against ref2 (device)
   auto finish_cols = [&](const double* ref_base, int64_t ref_ld) -> int {
     for (int j = 0; j < nb; ++j) {
@@ -430,10 +472,11 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     KF_TRY(finish_cols(Tref, ld1));
     double g2h = 0.0;
     KF_TRY(fetch(nrm2, 1, &g2h));
-    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t)));
     KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
+    rb.land();
     have = true;
     if (fl[0] && g2h < 1e-4 * hv[(size_t)lw]) {
       have = false;
@@ -456,12 +499,13 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     int32_t gh = 1, lh = 0;
     KF_TRY(fetch(coef + kb + (int64_t)(2 * pn) * ldc, 1, &g1));
     KF_TRY(fetch(nrm2, 1, &g2h));
-    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (gated) KF_HIP(hipMemcpyAsync(&gh, gate, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (pending_loose && pn > 0) KF_HIP(hipMemcpyAsync(&lh, loose, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t)));
+    if (gated) KF_TRY(rb.get(&gh, gate, sizeof(int32_t)));
+    if (pending_loose && pn > 0) KF_TRY(rb.get(&lh, loose, sizeof(int32_t)));
     KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
     if (done) KF_HIP(hipEventRecord(done, st));
     KF_HIP(hipStreamSynchronize(st));
+    rb.land();
     have = true;
     if (pending_loose) *pending_loose = lh != 0;
     if (full_passes && gated && gh) ++*full_passes;
@@ -475,8 +519,9 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       KF_TRY(gemv_t(n, 1, X, ldb, nullptr, 0, 0, X, 1, ldb, p->d_m, nrm2, 1, p->gw, st));
       KF_TRY(normalize_col(n, X, nrm2, p->small + kOne, drop, p->flags, post, st));
       if (done) KF_HIP(hipEventRecord(done, st));
-      KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t)));
       KF_HIP(hipStreamSynchronize(st));
+      rb.land();
     } else if (fl[0] && g2h < 0.25 * g1) {
       // the column is normalised now: one more pass against the whole basis,
       // dropped if it loses all but drop_tol of its unit norm
@@ -493,6 +538,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     KF_TRY(fetch(coef + (int64_t)(2 * pn) * ldc, (size_t)ldc * nb, hg1.data()));
     KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
     KF_HIP(hipStreamSynchronize(st));
+    rb.land();
     bool again = false;
     for (int j = 0; j < nb; ++j)
       if (hg2[(size_t)j * nb + j] < 0.25 * hg1[(size_t)kb + j + (size_t)j * ldc]) again = true;
@@ -506,8 +552,9 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   if (!have) {
     // (single vectors usually have both from their one synchronisation)
     KF_TRY(fetch(T1, (size_t)ld1 * nb, hv.data()));
-    KF_HIP(hipMemcpyAsync(fl.data(), p->flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+    KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t) * nb));
     KF_HIP(hipStreamSynchronize(st));
+    rb.land();
   }
   ref_out.assign((size_t)nb, 0.0);
   for (int j = 0; j < nb; ++j) ref_out[(size_t)j] = std::sqrt(std::max(hv[(size_t)lw + j + (size_t)j * ld1], 0.0));
@@ -993,6 +1040,7 @@ void free_problem(kf_problem* p) {
     (void)hipStreamSynchronize(p->st);
     (void)hipStreamDestroy(p->st);
   }
+  if (p->pin) (void)hipHostFree(p->pin);
   delete p;
 }
 
