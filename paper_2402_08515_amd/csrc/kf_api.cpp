@@ -648,8 +648,10 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
         KF_TRY(gemv_t(p->n, 1, p->V + (int64_t)c * p->n, p->n, p->SV + (int64_t)c * p->n, 1, p->n,
                       p->V + (int64_t)c * p->n, 1, p->n, p->d_m, q + 2 * c, 1, p->gw, st));
       std::vector<double> hq((size_t)2 * nc);
-      KF_HIP(hipMemcpyAsync(hq.data(), q, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, st));
+      Readback rq(p);
+      KF_TRY(rq.get(hq.data(), q, sizeof(double) * 2 * nc));
       KF_HIP(hipStreamSynchronize(st));
+      rq.land();
       for (int c = 0; c < nc; ++c)
         if (hq[(size_t)2 * c + 1] > 0.0) sel[(size_t)c0 + c] = hq[(size_t)2 * c] / hq[(size_t)2 * c + 1];
       out.cand_theta = sel;
@@ -657,9 +659,11 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
     KF_HIP(hipMemcpyAsync(d_theta, sel.data() + c0, sizeof(double) * nc, hipMemcpyHostToDevice, st));
     KF_TRY(residual_norms(p->n, p->SV, p->V, p->n, p->d_m, d_theta, nc, d_num, d_den, p->rw, st));
     std::vector<double> num((size_t)nc), den((size_t)nc);
-    KF_HIP(hipMemcpyAsync(num.data(), d_num, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
-    KF_HIP(hipMemcpyAsync(den.data(), d_den, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+    Readback rr(p);
+    KF_TRY(rr.get(num.data(), d_num, sizeof(double) * nc));
+    KF_TRY(rr.get(den.data(), d_den, sizeof(double) * nc));
     KF_HIP(hipStreamSynchronize(st));
+    rr.land();
     for (int c = 0; c < nc; ++c) {
       const double th = sel[(size_t)c0 + c];
       double dn = std::sqrt(den[(size_t)c]);
@@ -721,7 +725,9 @@ int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector
 int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, bool want_vectors) {
   hipStream_t st = p->st;
   KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
-  KF_HIP(hipMemcpyAsync(&out.orth, p->small + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+  // lands after the eigensolver's own synchronisation
+  Readback ro(p);
+  KF_TRY(ro.get(&out.orth, p->small + 1024, sizeof(double)));
   // The pencil is (H, G) with G = I + E, E at the orthogonality level of the
   // basis: its eigenvalues are those of H - (E H + H E)/2 up to O(|E|^2).
   const double* Hm = p->H;
@@ -753,6 +759,8 @@ int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, boo
         return om >= lo && om <= hi;
       },
       sel));
+  KF_HIP(hipStreamSynchronize(st));
+  ro.land();
   if (E) KF_TRY(vectors_correct(k, (int)sel.size(), E, p->ew.Y, EH, st));
   return ritz_residuals(p, p->B, p->ldb, k, sel, tol, want_vectors, out);
 }
@@ -1503,8 +1511,10 @@ int solve_check_now(kf_problem* p, SolveState& s) {
       // columns never projected since they were formed: check them too
       int32_t lh = 0;
       KF_TRY(block_gate(s.cur, c0, nc, p->T + (int64_t)nc * s.cur, s.cur, kPendingTol, p->flags + 33, st));
-      KF_HIP(hipMemcpyAsync(&lh, p->flags + 33, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      Readback rl(p);
+      KF_TRY(rl.get(&lh, p->flags + 33, sizeof(int32_t)));
       KF_HIP(hipStreamSynchronize(st));
+      rl.land();
       if (lh) {
         KF_TRY(repair_block(p, c0, nc));
         s.proj_every = std::max(1, s.proj_every / 2);

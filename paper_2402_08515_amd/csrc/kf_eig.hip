@@ -29,7 +29,7 @@ namespace {
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // matrices of this order and larger are reduced by k_tri_step
-constexpr int kTriMultiFrom = 160;
+constexpr int kTriMultiFrom = 48;
 
 __device__ __forceinline__ double wave_sum_e(double v) {
 #pragma unroll

@@ -1,5 +1,5 @@
 """The projected-pencil eigensolver (kf_sym_eig: Householder
-tridiagonalisation on one workgroup below order 160 and one launch per
+tridiagonalisation on one workgroup below order 48 and one launch per
 reflector above, bisection, inverse iteration, back-transformation) on
 matrices whose spectrum is fixed by construction, A = Q diag(lam) Q^T."""
 
@@ -26,7 +26,7 @@ def _matrix(k, seed, clusters=True):
     return (Q * lam) @ Q.T, lam
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 17, 159, 160, 161, 457, 1100])
+@pytest.mark.parametrize("k", [1, 2, 3, 17, 47, 48, 49, 160, 457, 1100])
 def test_eigenvalues_and_vectors(k):
     kf = _kf()
     print(f"case sym_eig k={k}", flush=True)
