@@ -210,54 +210,85 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma(
   }
 }
 
-// V = Bk Y (n x k times k x nc) on the float64 matrix cores: a wavefront owns
-// 16 rows and up to 64 columns (four 16 x 16 tiles sharing the Bk operand, so
-// Bk is streamed once per 64 columns).  Lane l supplies A[r = l%16][j = l/16] =
-// Bk[r][j] (four 128-byte row runs per instruction) and B[j = l/16][c = l%16] =
-// Y[j][c], read from a 32 x 64 slice of Y staged in LDS with c contiguous; its
-// accumulator register v holds D[r = 4v + l/16][c = l%16].
-constexpr int kGemmJ = 32;
+// V = Bk Y (n x k times k x nc) on the float64 matrix cores.  A wavefront
+// owns 32 rows (two 16-row tiles) and the up to four 16-column tiles of its
+// 64-column group that lie below nc; each Y value read from LDS feeds both
+// row tiles.  Lane l supplies A[r = l%16][j = l/16] = Bk[r][j] (four 128-byte
+// row runs per instruction) and B[j = l/16][c = l%16] = Y[j][c], read from a
+// GJ x 64 slice of Y staged in LDS with c contiguous; its accumulator
+// register v holds D[r = 4v + l/16][c = l%16].  The basis operand of the next
+// slice is loaded while the current one is multiplied.
+constexpr int kGemmJ = 16;
+constexpr int kGemmRT = 2;
 __global__ __launch_bounds__(256) void k_gemm_nn_mfma(int32_t n, int k, const double* __restrict__ Bk, int64_t ldb,
                                                       const double* __restrict__ Y, int64_t ldy, double* __restrict__ V,
                                                       int64_t ldv, int nc) {
+  constexpr int S = kGemmJ / 4;
   __shared__ double ys[kGemmJ][64 + 2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t rt = ((int64_t)blockIdx.x * 4 + wave) * 16;  // first row of this wavefront
+  const int64_t rt = ((int64_t)blockIdx.x * 4 + wave) * 16 * kGemmRT;  // first row of this wavefront
   const bool live = rt < n;
   const int c0 = blockIdx.y * 64;
-  const int64_t ra = rt + (lane & 15);
-  const bool rok = ra < n;
-  const int kr = lane >> 4;
-  f64x4 acc[4];
+  const int ntile = std::min(4, (nc - c0 + 15) / 16);
+  const int q = lane >> 4, cl = lane & 15;
+  f64x4 acc[kGemmRT][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < kGemmRT; ++r)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[r][t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  double a[kGemmRT][S], an[kGemmRT][S];
+  auto load = [&](int jb, double (&dst)[kGemmRT][S]) {
+#pragma unroll
+    for (int r = 0; r < kGemmRT; ++r) {
+      const int64_t ra = rt + 16 * r + cl;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int j = jb + 4 * s + q;
+        dst[r][s] = (ra < n && j < k) ? Bk[ra + (int64_t)j * ldb] : 0.0;
+      }
+    }
+  };
+  if (live) load(0, a);
   for (int jb = 0; jb < k; jb += kGemmJ) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kGemmJ * 64; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kGemmJ * 16 * ntile; t += blockDim.x) {
       const int c = t / kGemmJ, j = t % kGemmJ;  // consecutive threads: consecutive j (coalesced)
       ys[j][c] = (jb + j < k && c0 + c < nc) ? Y[(jb + j) + (int64_t)(c0 + c) * ldy] : 0.0;
     }
     __syncthreads();
     if (!live) continue;
-    const int jn = min(kGemmJ, k - jb);
-    for (int j0 = 0; j0 < jn; j0 += 4) {
-      const int j = j0 + kr;
-      const double a = (rok && j < jn) ? Bk[ra + (int64_t)(jb + j) * ldb] : 0.0;
+    if (jb + kGemmJ < k) load(jb + kGemmJ, an);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ys[j][16 * t + (lane & 15)], acc[t], 0, 0, 0);
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < ntile) {
+          const double b = ys[4 * s + q][16 * t + cl];
+#pragma unroll
+          for (int r = 0; r < kGemmRT; ++r)
+            acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][s], b, acc[r][t], 0, 0, 0);
+        }
+      }
     }
+#pragma unroll
+    for (int r = 0; r < kGemmRT; ++r)
+#pragma unroll
+      for (int s = 0; s < S; ++s) a[r][s] = an[r][s];
   }
   if (!live) return;
+  // constant trip counts: the accumulators stay in registers
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int c = c0 + 16 * t + (lane & 15);
-    if (c >= nc) continue;
+  for (int r = 0; r < kGemmRT; ++r)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = rt + 4 * v + (lane >> 4);
-      if (r < n) V[r + (int64_t)c * ldv] = acc[t][v];
+    for (int t = 0; t < 4; ++t) {
+      const int c = c0 + 16 * t + cl;
+      if (t >= ntile || c >= nc) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = rt + 16 * r + 4 * v + q;
+        if (row < n) V[row + (int64_t)c * ldv] = acc[r][t][v];
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int nrhs,
@@ -637,7 +668,7 @@ int gemm_nn(int32_t n, int k, const double* Bk, int64_t ldb, const double* Y, in
     hipLaunchKernelGGL((k_gemv_n<8, false>), grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc, nullptr);
   } else {
     // a dense product: on the float64 matrix cores, Bk streamed once per 64 columns
-    const dim3 grid(ceil_div64(n, 64), ceil_div64(nc, 64));
+    const dim3 grid(ceil_div64(n, 64 * kGemmRT), ceil_div64(nc, 64));
     hipLaunchKernelGGL(k_gemm_nn_mfma, grid, dim3(256), 0, st, n, k, Bk, ldb, Y, ldy, V, ldv, nc);
   }
   KF_HIP(hipGetLastError());

@@ -395,6 +395,7 @@ __global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict_
 // arrays (LU factors and the iterate) are interleaved across lanes, element i
 // of lane c at [i * ldw + c], so that at every step the lanes of a wavefront
 // touch consecutive addresses.  Finished vectors go to Z (m x nsel).
+constexpr int kIvB = 8;  // rows loaded ahead of the running values
 __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ d, const double* __restrict__ e,
                                               const double* __restrict__ bounds, int ncl,
                                               const int32_t* __restrict__ cstart, const double* __restrict__ sel,
@@ -416,37 +417,51 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
     if (s > cstart[cl] && lam - prev_lam < 10.0 * tiny) lam = prev_lam + 10.0 * tiny;
     prev_lam = lam;
     // LU of T - lam I with partial pivoting; row i is (a, b, c) at columns
-    // (i, i+1, i+2) while it is being eliminated
+    // (i, i+1, i+2) while it is being eliminated.  The recurrences below load
+    // kIvB rows ahead of the running values (the loads do not depend on them).
     double a = d[0] - lam;
     double b = m > 1 ? e[0] : 0.0;
-    for (int i = 0; i + 1 < m; ++i) {
-      const int64_t o = (int64_t)i * ldw;
-      const double bi = e[i];
-      const double ai1 = d[i + 1] - lam;
-      const double ci1 = (i + 2 < m) ? e[i + 1] : 0.0;
-      double na, nb;
-      if (fabs(a) >= fabs(bi)) {
-        const double l = (a != 0.0) ? bi / a : 0.0;
-        pv[o] = 0.0;
-        lm[o] = l;
-        u2[o] = 0.0;
-        u1[o] = b;
-        if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-        rinv[o] = 1.0 / a;
-        na = ai1 - l * b;
-        nb = ci1;
-      } else {
-        const double l = a / bi;
-        pv[o] = 1.0;
-        lm[o] = l;
-        u1[o] = ai1;
-        u2[o] = ci1;
-        rinv[o] = 1.0 / bi;
-        na = b - l * ai1;
-        nb = -l * ci1;
+    for (int i0 = 0; i0 + 1 < m; i0 += kIvB) {
+      double eb[kIvB], dn[kIvB], en[kIvB];
+#pragma unroll
+      for (int u = 0; u < kIvB; ++u) {
+        const int i = i0 + u;
+        eb[u] = i + 1 < m ? e[i] : 0.0;
+        dn[u] = i + 1 < m ? d[i + 1] : 0.0;
+        en[u] = i + 2 < m ? e[i + 1] : 0.0;
       }
-      a = na;
-      b = nb;
+#pragma unroll
+      for (int u = 0; u < kIvB; ++u) {
+        const int i = i0 + u;
+        if (i + 1 >= m) break;
+        const int64_t o = (int64_t)i * ldw;
+        const double bi = eb[u];
+        const double ai1 = dn[u] - lam;
+        const double ci1 = en[u];
+        double na, nb;
+        if (fabs(a) >= fabs(bi)) {
+          const double l = (a != 0.0) ? bi / a : 0.0;
+          pv[o] = 0.0;
+          lm[o] = l;
+          u2[o] = 0.0;
+          u1[o] = b;
+          if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+          rinv[o] = 1.0 / a;
+          na = ai1 - l * b;
+          nb = ci1;
+        } else {
+          const double l = a / bi;
+          pv[o] = 1.0;
+          lm[o] = l;
+          u1[o] = ai1;
+          u2[o] = ci1;
+          rinv[o] = 1.0 / bi;
+          na = b - l * ai1;
+          nb = -l * ci1;
+        }
+        a = na;
+        b = nb;
+      }
     }
     const int64_t ol = (int64_t)(m - 1) * ldw;
     if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
@@ -458,27 +473,56 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
     for (int it = 0; it < 3; ++it) {
       // forward: row swaps and elimination, running value in a register
       double y = z[0];
-      for (int i = 0; i + 1 < m; ++i) {
-        const int64_t o = (int64_t)i * ldw;
-        double nx = z[o + ldw];
-        if (pv[o] != 0.0) {
-          const double t = y;
-          y = nx;
-          nx = t;
+      for (int i0 = 0; i0 + 1 < m; i0 += kIvB) {
+        double nxv[kIvB], pvv[kIvB], lmv[kIvB];
+#pragma unroll
+        for (int u = 0; u < kIvB; ++u) {
+          const int i = i0 + u;
+          const int64_t o = (int64_t)i * ldw;
+          const bool ok = i + 1 < m;
+          nxv[u] = ok ? z[o + ldw] : 0.0;
+          pvv[u] = ok ? pv[o] : 0.0;
+          lmv[u] = ok ? lm[o] : 0.0;
         }
-        z[o] = y;
-        y = nx - lm[o] * y;
+#pragma unroll
+        for (int u = 0; u < kIvB; ++u) {
+          const int i = i0 + u;
+          if (i + 1 >= m) break;
+          double nx = nxv[u];
+          if (pvv[u] != 0.0) {
+            const double t = y;
+            y = nx;
+            nx = t;
+          }
+          z[(int64_t)i * ldw] = y;
+          y = nx - lmv[u] * y;
+        }
       }
       z[ol] = y;
       // backward substitution with U (diagonal inverse, two superdiagonals)
       double x1 = 0.0, x2 = 0.0, mx = 0.0;
-      for (int i = m - 1; i >= 0; --i) {
-        const int64_t o = (int64_t)i * ldw;
-        const double x = (z[o] - u1[o] * x1 - u2[o] * x2) * rinv[o];
-        z[o] = x;
-        mx = fmax(mx, fabs(x));
-        x2 = x1;
-        x1 = x;
+      for (int i0 = m - 1; i0 >= 0; i0 -= kIvB) {
+        double zv[kIvB], u1v[kIvB], u2v[kIvB], rv[kIvB];
+#pragma unroll
+        for (int u = 0; u < kIvB; ++u) {
+          const int i = i0 - u;
+          const int64_t o = (int64_t)i * ldw;
+          const bool ok = i >= 0;
+          zv[u] = ok ? z[o] : 0.0;
+          u1v[u] = ok ? u1[o] : 0.0;
+          u2v[u] = ok ? u2[o] : 0.0;
+          rv[u] = ok ? rinv[o] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kIvB; ++u) {
+          const int i = i0 - u;
+          if (i < 0) break;
+          const double x = (zv[u] - u1v[u] * x1 - u2v[u] * x2) * rv[u];
+          z[(int64_t)i * ldw] = x;
+          mx = fmax(mx, fabs(x));
+          x2 = x1;
+          x1 = x;
+        }
       }
       const double r = mx > 0.0 ? 1.0 / mx : 0.0;
       for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] *= r;
