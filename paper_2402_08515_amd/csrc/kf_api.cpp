@@ -1521,7 +1521,10 @@ int solve_check_now(kf_problem* p, SolveState& s) {
       }
     }
   }
+  // the check formed the pending columns' projections and checked their
+  // orthogonality: the projection interval starts again from here
   s.pending = 0;
+  s.since_proj = 0;
   KF_TRY(rr_check(p, s.cur, s.tol_loop, s.chk, s.margin, false));
   KF_HIP(hipEventRecord(p->ev[4], st));
   s.rr_pending = true;
