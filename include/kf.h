@@ -106,7 +106,7 @@ typedef struct kf_options {
                             orthogonalisation coefficients) runs every
                             proj_every steps; in between a step is
                             orthogonalised against the last two columns only
-                            (three-term form).  Columns found more than 1e-8
+                            (three-term form).  Columns found more than 1e-7
                             off M-orthogonal at a projection are orthogonalised
                             again and proj_every is halved from then on.  The
                             Rayleigh-Ritz step corrects to first order for the

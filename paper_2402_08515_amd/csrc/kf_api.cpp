@@ -123,13 +123,14 @@ constexpr size_t kPinBytes = (size_t)64 << 10;  // pinned staging for per-step r
 constexpr int kSmall = 4096;
 // offsets of the device scalars in kf_problem::small used by the
 // orthogonalisation (the Rayleigh-Ritz check uses 1024.. and 2048..)
-constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kOne = 4095;
+constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kRec = 2560, kOne = 4095;
 // mixed mode: refinements tried before a solve with a target gives up
 constexpr int kMaxRefines = 4;
 // columns projected only every proj_every steps must be M-orthogonal to the
 // older basis to this level, else they are orthogonalised again and the
-// projection interval is halved
-constexpr double kPendingTol = 1e-8;
+// projection interval is halved; the Rayleigh-Ritz step's first-order
+// correction leaves an eigenvalue error of order |E|^2 <= 1e-14 relative
+constexpr double kPendingTol = 1e-7;
 
 int pow2ceil(int b) {
   int p = 1;
@@ -411,10 +412,15 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   // first projection: the window [loc0, kb) (none without the three-term
   // form) and the block itself; rows lw.. hold the block's Gram matrix
   const int ld1 = lw + nb;
-  const double* L1 = p->B + (int64_t)(kb - lw) * ldb;
-  KF_TRY(gemv_t(n, ld1, L1, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, T1, ld1, p->gw, st));
+  double* L1 = p->B + (int64_t)(kb - lw) * ldb;
   const double* Tref = T1 + lw;  // nb x nb, leading dimension ld1
-  if (lw > 0) KF_TRY(gemv_n_sub(n, lw, L1, ldb, T1, ld1, X, ldb, nb, st));
+  // one vector between projections: the window pass and the normalisation
+  // in two launches and one readback (norm by Pythagoras over the window)
+  const bool fused = kb > 0 && nb == 1 && !monitor && local && lw <= 2;
+  if (!fused) {
+    KF_TRY(gemv_t(n, ld1, L1, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, T1, ld1, p->gw, st));
+    if (lw > 0) KF_TRY(gemv_n_sub(n, lw, L1, ldb, T1, ld1, X, ldb, nb, st));
+  }
   // pass over the whole basis; the first one also forms the pending
   // projected-pencil columns [B^T S Q | B^T M Q] with Q = B[:, kb-pn:kb]; the
   // rows below kb give the block's Gram matrix before the pass
@@ -469,14 +475,32 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     // between projections: the window pass only; the coefficients against
     // the older basis are formed at the next projection (every proj_every
     // steps), which also checks how far this column is from orthogonal
-    KF_TRY(finish_cols(Tref, ld1));
     double g2h = 0.0;
-    KF_TRY(fetch(nrm2, 1, &g2h));
-    KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t)));
-    KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
-    if (done) KF_HIP(hipEventRecord(done, st));
-    KF_HIP(hipStreamSynchronize(st));
-    rb.land();
+    bool explicit_norm = !fused;
+    if (fused) {
+      double* rec = p->small + kRec;
+      KF_TRY(window_step(n, lw, L1, ldb, p->d_m, p->gw, T1, rec, st));
+      double rh[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      KF_TRY(fetch(rec, (size_t)lw + 3, rh));
+      if (done) KF_HIP(hipEventRecord(done, st));
+      KF_HIP(hipStreamSynchronize(st));
+      rb.land();
+      for (int j = 0; j <= lw; ++j) hv[(size_t)j] = rh[j];
+      g2h = rh[lw + 1];
+      fl[0] = 1;
+      // status 2: strong cancellation in the window pass, the norm by
+      // Pythagoras is not accurate; normalise against the explicit norm
+      explicit_norm = rh[lw + 2] != 1.0;
+    }
+    if (explicit_norm) {
+      KF_TRY(finish_cols(Tref, ld1));
+      KF_TRY(fetch(nrm2, 1, &g2h));
+      KF_TRY(rb.get(fl.data(), p->flags, sizeof(int32_t)));
+      KF_TRY(fetch(T1, (size_t)ld1, hv.data()));
+      if (done) KF_HIP(hipEventRecord(done, st));
+      KF_HIP(hipStreamSynchronize(st));
+      rb.land();
+    }
     have = true;
     if (fl[0] && g2h < 1e-4 * hv[(size_t)lw]) {
       have = false;

@@ -530,7 +530,135 @@ __global__ __launch_bounds__(256) void k_axpy(int64_t count, double a, const dou
   if (t < count) y[t] = fma(a, x[t], y[t]);
 }
 
+
+// Three-term Gram-Schmidt step of one column in two launches (the window
+// pass of Algorithm 2.5 in the M inner product).  k_window_dots writes the
+// per-chunk partial sums of the lw window columns' products with x (L's
+// column lw is x), x^T M x, and the window's own Gram matrix:
+//   D = [L_0^T M x, .., L_{lw-1}^T M x, x^T M x, L_0^T M L_0, L_0^T M L_1, L_1^T M L_1]
+// (the last two only for lw = 2).
+constexpr int kWinCH = 1024;
+constexpr int kWinGrid = 512;  // workgroups of k_window_scale (grid-stride)
+__host__ __device__ constexpr int window_dot_count(int lw) { return lw + 1 + lw * (lw + 1) / 2; }
+__global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const double* __restrict__ L, int64_t ldl,
+                                                     const double* __restrict__ m, double* __restrict__ partial) {
+  __shared__ double red[4][6];
+  const int chunk = blockIdx.x, nchunks = gridDim.x;
+  const int nd = window_dot_count(lw);
+  const int64_t r0 = (int64_t)chunk * kWinCH;
+  const int rows = (int)std::min<int64_t>(kWinCH, (int64_t)n - r0);
+  const double* __restrict__ x = L + (int64_t)lw * ldl;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    const int64_t i = r0 + r;
+    const double mi = m[i];
+    const double xm = x[i] * mi;
+    const double l0 = lw > 0 ? L[i] : 0.0;
+    const double l1 = lw > 1 ? L[i + ldl] : 0.0;
+    if (lw == 2) {
+      s[0] = fma(l0, xm, s[0]);
+      s[1] = fma(l1, xm, s[1]);
+      s[2] = fma(x[i], xm, s[2]);
+      const double l0m = l0 * mi;
+      s[3] = fma(l0, l0m, s[3]);
+      s[4] = fma(l1, l0m, s[4]);
+      s[5] = fma(l1, l1 * mi, s[5]);
+    } else if (lw == 1) {
+      s[0] = fma(l0, xm, s[0]);
+      s[1] = fma(x[i], xm, s[1]);
+      s[2] = fma(l0, l0 * mi, s[2]);
+    } else {
+      s[0] = fma(x[i], xm, s[0]);
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = 0; d < 6; ++d) {
+    const double v = wave_sum(s[d]);
+    if (lane == 0) red[wave][d] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nd) {
+    const int d = threadIdx.x;
+    partial[(int64_t)d * nchunks + chunk] = ((red[0][d] + red[1][d]) + red[2][d]) + red[3][d];
+  }
+}
+
+// Every workgroup sums the partials in chunk order (the same values bit for
+// bit in all of them), then x <- (x - sum_{j<lw} c_j L_j) / sqrt(g) with
+// c_j = L_j^T M x and g = x^T M x - 2 c^T c + c^T G c (G the window's Gram
+// matrix): the exact M-norm^2 after the pass, to rounding of order
+// eps * x^T M x.  When g < 1e-4 x^T M x that rounding is no longer small: x
+// is only subtracted and status 2 tells the caller to normalise it
+// explicitly.  Workgroup 0 writes T = [c, x^T M x] and
+// rec = {T[0..lw], g, status}.
+__global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double* __restrict__ L, int64_t ldl,
+                                                      const double* __restrict__ partial, int nchunks,
+                                                      double* __restrict__ T, double* __restrict__ rec) {
+  __shared__ double ds[6];
+  const int nd = window_dot_count(lw);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = wave; d < nd; d += 4) {
+    double v = 0.0;
+    for (int c = lane; c < nchunks; c += 64) v += partial[(int64_t)d * nchunks + c];
+    v = wave_sum(v);
+    if (lane == 0) ds[d] = v;
+  }
+  __syncthreads();
+  double* x = L + (int64_t)lw * ldl;
+  const double c0 = lw > 0 ? ds[0] : 0.0, c1 = lw > 1 ? ds[1] : 0.0;
+  const double txx = ds[lw];
+  double g = txx;
+  if (lw == 2) {
+    g += c0 * (c0 * ds[3] - 2.0 * c0) + c1 * (c1 * ds[5] - 2.0 * c1) + 2.0 * c0 * c1 * ds[4];
+  } else if (lw == 1) {
+    g += c0 * (c0 * ds[2] - 2.0 * c0);
+  }
+  const bool strong = !(g > 0.0 && g >= 1e-4 * txx);
+  const double sc = strong ? 1.0 : 1.0 / sqrt(g);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = x[i];
+    if (lw > 0) v = fma(-c0, L[i], v);
+    if (lw > 1) v = fma(-c1, L[i + ldl], v);
+    x[i] = v * sc;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j <= lw; ++j) {
+      T[j] = ds[j];
+      rec[j] = ds[j];
+    }
+    rec[lw + 1] = g;
+    rec[lw + 2] = strong ? 2.0 : 1.0;
+  }
+}
+
 }  // namespace
+
+int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, GemvTWork& wk, double* T, double* rec,
+                hipStream_t st) {
+  if (lw < 0 || lw > 2) {
+    set_error("window_step: the window holds at most two columns");
+    return KF_EINVAL;
+  }
+  const int nchunks = ceil_div64(n, kWinCH);
+  const size_t need = (size_t)window_dot_count(lw) * nchunks;
+  if (wk.cap < need) {
+    if (wk.partial) (void)hipFree(wk.partial);
+    wk.partial = nullptr;
+    wk.cap = 0;
+    const size_t cap = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&wk.partial, cap * sizeof(double)) != hipSuccess) {
+      set_error("window_step: cannot allocate the partial-sum buffer");
+      return KF_ENOMEM;
+    }
+    wk.cap = cap;
+  }
+  hipLaunchKernelGGL(k_window_dots, dim3(nchunks), dim3(256), 0, st, n, lw, L, ldl, m, wk.partial);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_window_scale, dim3(std::min(kWinGrid, ceil_div64(n, 256))), dim3(256), 0, st, n, lw, L, ldl,
+                     wk.partial, nchunks, T, rec);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
 
 int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, int n1, int64_t ldx1,
            const double* X2, int n2, int64_t ldx2, const double* m, double* H, int64_t ldh, GemvTWork& wk,

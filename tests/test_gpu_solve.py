@@ -59,10 +59,10 @@ def test_grid2d_fp64_matches_oracle_and_closed_form(grid2d, full_reorth, reorth_
     # unconverged Ritz values after many iterations follow rounding noise in
     # the late basis vectors and are not compared (only accepted pairs are)
     # with projections every few steps the basis is held M-orthonormal to
-    # 1e-8 (the Rayleigh-Ritz step corrects for that to second order); with
+    # 1e-7 (the Rayleigh-Ritz step corrects for that to second order); with
     # a projection at every step and a tight subtraction threshold, to 1e-12
     tight = full_reorth or (proj_every == 1 and reorth_tol is not None and reorth_tol <= 1e-14)
-    assert got.orth_error < (1e-12 if tight else 1e-8), got.orth_error
+    assert got.orth_error < (1e-12 if tight else 1e-7), got.orth_error
     assert got.leapfrog_vector_steps == 39 * (L - 1)
 
 
@@ -196,10 +196,11 @@ def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
     assert got.omega2.size == tgt == 110
     assert np.max(np.abs(got.omega2 - vals) / vals) <= 1e-10
     assert got.residual.max() <= 1e-6
-    # the projection onto the whole basis runs every 4 steps and subtracts
-    # only coefficients above 1e-10; the Rayleigh-Ritz step corrects for the
+    # the projection onto the whole basis runs every few steps and subtracts
+    # only coefficients above 1e-9 of the column norm; columns that drift past
+    # 1e-7 are orthogonalised again; the Rayleigh-Ritz step corrects for the
     # remaining non-orthogonality to first order
-    assert got.orth_error < 1e-8
+    assert got.orth_error < 1e-7
     print("orth_error", got.orth_error, "full passes", got.full_passes, "of", got.krylov_steps)
 
 
