@@ -18,6 +18,15 @@ namespace {
 
 inline int ceil_div64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; renumber
+// them so that each XCD receives one contiguous range of row slices and its
+// L2 keeps the neighbouring rows it gathers.
+__device__ __forceinline__ int xcd_map(int i, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = i & 7, t = i >> 3;
+  return (x < r) ? x * (q + 1) + t : r * (q + 1) + (x - r) * q + t;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(256) void k_spmv_cols(int32_t n, int32_t nslices, c
                                                    const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                                                    int64_t ldy, int ncols, const double* __restrict__ rscale) {
   constexpr bool relative = sizeof(IT) == 2;
-  const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int slice = xcd_map(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (slice >= nslices) return;
   const int row = slice * 64 + lane;
