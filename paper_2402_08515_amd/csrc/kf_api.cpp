@@ -289,12 +289,12 @@ int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, 
   KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
   KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, sb.Y1, st));
   void* Y[2] = {sb.Y0, sb.Y1};
+  auto wt = [&](int i) { return i < 0 ? 0.0 : w[(size_t)i]; };
   for (int l = 1; l < L; ++l) {
-    int mode = (l == 1) ? kFirst : kMid;
-    if (l == L - 1) mode |= kLast;
+    const StepPlan sp = step_plan(l, L);
     void* cur = Y[l & 1];
     void* nxt = Y[(l + 1) & 1];
-    KF_TRY(launch_leapfrog(A, bk, mode, cur, nxt, nxt, sb.R, dst, drs, dcs, bout, w[0], w[(size_t)l],
+    KF_TRY(launch_leapfrog(A, bk, sp.mode, cur, nxt, nxt, sb.R, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic), wt(sp.in),
                            p->opt.xcd_remap, st));
   }
   return KF_OK;
@@ -973,12 +973,14 @@ int time_variant(kf_problem* p, const SellOp& A, StepBufs& sb, int remap, int re
   KF_HIP(hipMemsetAsync(sb.Y1, 0, bytes, st));
   KF_HIP(hipMemsetAsync(sb.R, 0, bytes, st));
   for (int w = 0; w < 3; ++w)
-    KF_TRY(launch_leapfrog(A, bk, kMid, sb.Y1, sb.Y0, sb.Y0, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+    KF_TRY(launch_leapfrog(A, bk, kMid, sb.Y1, sb.Y0, sb.Y0, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, 0.0, remap, st));
   KF_HIP(hipEventRecord(p->ev[0], st));
+  // the mix of a filter application: the weighted sum is updated every third step
   for (int r = 0; r < reps; ++r) {
     void* a = (r & 1) ? sb.Y0 : sb.Y1;
     void* b = (r & 1) ? sb.Y1 : sb.Y0;
-    KF_TRY(launch_leapfrog(A, bk, kMid, a, b, b, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, remap, st));
+    KF_TRY(launch_leapfrog(A, bk, r % 3 == 2 ? kMidAcc : kMid, a, b, b, sb.R, nullptr, 0, 0, 0, 0.0, 0.0, 0.0, remap,
+                           st));
   }
   KF_HIP(hipEventRecord(p->ev[1], st));
   KF_HIP(hipEventSynchronize(p->ev[1]));

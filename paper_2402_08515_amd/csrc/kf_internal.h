@@ -63,18 +63,32 @@ int build_sell(int32_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d
                const double* d_row_scale, int val_bytes, int want_idx_bytes, hipStream_t st, SellOp& out);
 
 // ---- fused leapfrog step ----------------------------------------------------
-enum StepMode { kMid = 0, kFirst = 1, kLast = 2, kFirstLast = 3 };
+enum StepMode { kMid = 0, kFirst = 1, kLast = 2, kFirstLast = 3, kMidAcc = 4 };
 
 // One step of eq. 2stepmethod fused with the rectangle-rule accumulation:
 //   nxt = 2 cur - prev - A cur   (prev ignored in kFirst: prev = cur)
-//   kFirst:  acc = w0*cur + w*nxt ;  otherwise acc += w*nxt
-//   kLast:   the accumulated value of columns j < bout goes to
-//            rout[i*rs + j*cs] (float64) and nxt is not stored;
-//            otherwise nxt -> out (may alias prev)
+//   kFirst:   acc = wc*cur + wn*nxt
+//   kMid:     acc untouched
+//   kMidAcc:  acc += wp*prev + wc*cur + wn*nxt
+//   kLast:    the value acc + wp*prev + wc*cur + wn*nxt of columns j < bout
+//             goes to rout[i*rs + j*cs] (float64) and nxt is not stored
+//   kFirstLast: rout gets wc*cur + wn*nxt
+// (the step sees three consecutive time levels, so the weighted sum can be
+// accumulated once every three steps); otherwise nxt -> out (may alias prev).
 // Blocks are n x b row-major in the stepping precision.
 int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
-                    double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int xcd_remap,
+                    double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
                     hipStream_t st);
+
+// The accumulation schedule of one filter application (L - 1 steps): for
+// step l, the mode and the weights (wp, wc, wn) of prev, cur and nxt.  Every
+// y_j enters once: y_0 and y_1 at step 1, then three at a time at steps
+// 4, 7, ..., and whatever is pending at the last step.
+struct StepPlan {
+  int mode;
+  int ip, ic, in;  // indices of the weights of prev, cur, nxt (-1: weight 0)
+};
+StepPlan step_plan(int l, int L);
 
 // Per-problem tables of a batch (device memory, refreshed before every
 // batched filter application).  kMaxBatch bounds the number of problems.

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
                                                   const T* __restrict__ val, const IT* __restrict__ idx,
                                                   const T* __restrict__ cur, const T* prev, T* out,
                                                   T* __restrict__ acc, double* __restrict__ rout, int64_t rs,
-                                                  int64_t cs, int bout, T w0, T w, int remap) {
+                                                  int64_t cs, int bout, T wp, T wc, T wn, int remap) {
   constexpr bool relative = sizeof(IT) == 2;
   constexpr int BL = B / LPR;   // vector columns per lane
   constexpr int RW = 64 / LPR;  // rows per wavefront
@@ -151,14 +151,15 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
 #pragma unroll
   for (int j = 0; j < BL; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
   if (!(MODE & kLast)) *reinterpret_cast<Row<T, BL>*>(out + off) = nx;
+  if (MODE == kMid) return;  // the weighted sum is brought up to date every third step
   Row<T, BL> r;
   if (MODE & kFirst) {
 #pragma unroll
-    for (int j = 0; j < BL; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
+    for (int j = 0; j < BL; ++j) r.v[j] = fma(wn, nx.v[j], wc * yc.v[j]);
   } else {
     r = *reinterpret_cast<const Row<T, BL>*>(acc + off);
 #pragma unroll
-    for (int j = 0; j < BL; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
+    for (int j = 0; j < BL; ++j) r.v[j] = fma(wn, nx.v[j], fma(wc, yc.v[j], fma(wp, yp.v[j], r.v[j])));
   }
   if (MODE & kLast) {
 #pragma unroll
@@ -210,20 +211,26 @@ __global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const i
 #pragma unroll
     for (int j = 0; j < B; ++j) sum[j] = fma(a, x.v[j], sum[j]);
   }
-  const T w0 = wtab[(int64_t)p * lmax], w = wtab[(int64_t)p * lmax + ell];
   const Row<T, B> yc = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)row * B);
   Row<T, B> yp = first ? yc : *reinterpret_cast<const Row<T, B>*>(prev + (int64_t)row * B);
   Row<T, B> nx, r;
 #pragma unroll
   for (int j = 0; j < B; ++j) nx.v[j] = (T)2 * yc.v[j] - yp.v[j] - sum[j];
   if (!last) *reinterpret_cast<Row<T, B>*>(out + (int64_t)row * B) = nx;
+  // the same accumulation schedule as the single-problem steps (step_plan):
+  // y_0, y_1 at step 1, then three levels at steps 4, 7, ..., the rest at the
+  // problem's last step
+  const int u = ell >= 2 ? 1 + 3 * ((ell - 2) / 3) : 1;  // latest update before this step
+  if (!(first || last || ell - u == 3)) return;
+  const T* __restrict__ wq = wtab + (int64_t)p * lmax;
   if (first) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) r.v[j] = w0 * yc.v[j] + w * nx.v[j];
+    for (int j = 0; j < B; ++j) r.v[j] = fma(wq[1], nx.v[j], wq[0] * yc.v[j]);
   } else {
+    const T wp = ell - 2 > u ? wq[ell - 2] : (T)0, wc = ell - 1 > u ? wq[ell - 1] : (T)0, wn = wq[ell];
     r = *reinterpret_cast<const Row<T, B>*>(acc + (int64_t)row * B);
 #pragma unroll
-    for (int j = 0; j < B; ++j) r.v[j] = fma(w, nx.v[j], r.v[j]);
+    for (int j = 0; j < B; ++j) r.v[j] = fma(wn, nx.v[j], fma(wc, yc.v[j], fma(wp, yp.v[j], r.v[j])));
   }
   if (last) {
     double* __restrict__ dst = tb->dst[p];
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(256) void k_scale_copy(int32_t n, int b, int bsrc, 
 // ---- host-side dispatch helpers
 template <typename T, typename IT, int B, bool NT, int LPR>
 int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
-                 int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+                 int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   const int grid = ceil_div64((int64_t)A.nslices * LPR, 4);
   const T* v = static_cast<const T*>(A.val);
   const IT* ix = static_cast<const IT*>(A.idx);
@@ -291,19 +298,23 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   switch (mode) {
     case kMid:
       hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     case kFirst:
       hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      break;
+    case kMidAcc:
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMidAcc, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     case kLast:
       hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     default:
       hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)w0, (T)w, remap);
+                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
   }
   KF_HIP(hipGetLastError());
@@ -312,32 +323,32 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
 
 template <typename T, typename IT, int B, int LPR>
 int launch_lf_bl(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
-                 int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+                 int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   if (A.nt_loads)
-    return launch_lf_bn<T, IT, B, true, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-  return launch_lf_bn<T, IT, B, false, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    return launch_lf_bn<T, IT, B, true, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  return launch_lf_bn<T, IT, B, false, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
 }
 
 template <typename T, typename IT, int B>
 int launch_lf_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
-                int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+                int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   const int lpr = lanes_per_row(A, B);
   if (B >= 4 && lpr == 4)
-    return launch_lf_bl<T, IT, B, (B >= 4 ? 4 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    return launch_lf_bl<T, IT, B, (B >= 4 ? 4 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
   if (B >= 2 && lpr == 2)
-    return launch_lf_bl<T, IT, B, (B >= 2 ? 2 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-  return launch_lf_bl<T, IT, B, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    return launch_lf_bl<T, IT, B, (B >= 2 ? 2 : 1)>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  return launch_lf_bl<T, IT, B, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
 }
 
 template <typename T, typename IT>
 int launch_lf_t(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
-                double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int remap, hipStream_t st) {
+                double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   switch (b) {
-    case 1: return launch_lf_b<T, IT, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-    case 2: return launch_lf_b<T, IT, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-    case 4: return launch_lf_b<T, IT, 4>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-    case 8: return launch_lf_b<T, IT, 8>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
-    case 16: return launch_lf_b<T, IT, 16>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, remap, st);
+    case 1: return launch_lf_b<T, IT, 1>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 2: return launch_lf_b<T, IT, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 4: return launch_lf_b<T, IT, 4>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 8: return launch_lf_b<T, IT, 8>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 16: return launch_lf_b<T, IT, 16>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
     default: set_error("leapfrog: block width must be 1, 2, 4, 8 or 16"); return KF_EINVAL;
   }
 }
@@ -442,16 +453,26 @@ int lanes_per_row(const SellOp& A, int b) {
 }
 
 int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc,
-                    double* rout, int64_t rs, int64_t cs, int bout, double w0, double w, int xcd_remap,
+                    double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
                     hipStream_t st) {
   if (A.val_bytes == 8) {
     if (A.idx_bytes == 2)
-      return launch_lf_t<double, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
-    return launch_lf_t<double, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+      return launch_lf_t<double, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap,
+                                          st);
+    return launch_lf_t<double, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap,
+                                        st);
   }
   if (A.idx_bytes == 2)
-    return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
-  return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, w0, w, xcd_remap, st);
+    return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
+  return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
+}
+
+StepPlan step_plan(int l, int L) {
+  const bool last = l == L - 1;
+  if (l == 1) return StepPlan{last ? kFirstLast : kFirst, -1, 0, 1};
+  const int u = 1 + 3 * ((l - 2) / 3);  // the latest step that brought the sum up to date
+  if (!last && l - u < 3) return StepPlan{kMid, -1, -1, -1};
+  return StepPlan{last ? kLast : kMidAcc, l - 2 > u ? l - 2 : -1, l - 1 > u ? l - 1 : -1, l};
 }
 
 namespace {

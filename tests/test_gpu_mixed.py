@@ -47,7 +47,14 @@ def test_grid2d_mixed_without_refinement_stalls_at_the_float32_floor():
     V0 = start_block(P.n, 1, P.seed)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision="mixed", refine=False)
     loose = prob.solve(V0, m_max=40, tol=1e-3)
-    assert loose.omega2.size == 11
+    # every distinct eigenvalue is found; float32 round-off may also seed the
+    # second direction of a double eigenvalue (the grid's spectrum has them),
+    # which then converges to the loose tolerance as a second copy
+    tgt, vals, mult = distinct_target(grid_spectrum(2, 64), P.omega_min, P.omega_max, 1)
+    near = np.abs(loose.omega2[:, None] - vals[None, :]) / vals[None, :]
+    assert near.min(axis=1).max() <= 1e-5
+    assert len(set(near.argmin(axis=1))) == tgt == 11
+    assert loose.omega2.size <= int(np.minimum(mult, 2).sum())
     tight = prob.solve(V0, m_max=40, tol=1e-7)
     assert tight.omega2.size < 11  # float32 round-off: eps32 * lambda_max / omega^2 ~ 1e-5
 
