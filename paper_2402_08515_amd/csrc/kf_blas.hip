@@ -33,6 +33,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum of p[i * stride], i < count, by one wavefront in a fixed order: lane l
+// takes i = l, l + 64, ... into four interleaved sums (four independent loads
+// in flight instead of a chain of dependent ones), then the lanes combine.
+__device__ __forceinline__ double wave_strided_sum(const double* __restrict__ p, int count, int64_t stride, int lane) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = lane;
+  for (; i + 192 < count; i += 256) {
+    s0 += p[(int64_t)i * stride];
+    s1 += p[(int64_t)(i + 64) * stride];
+    s2 += p[(int64_t)(i + 128) * stride];
+    s3 += p[(int64_t)(i + 192) * stride];
+  }
+  for (; i < count; i += 64) s0 += p[(int64_t)i * stride];
+  return wave_sum((s0 + s1) + (s2 + s3));
+}
+
 // ------------------------------------------------------- tall-skinny float64
 // Stage 1 of H = Bk^T diag(w) X: one workgroup per (row chunk, group of 64
 // basis columns); the weighted X chunk sits in LDS.  Each wavefront streams
@@ -306,10 +322,7 @@ __global__ __launch_bounds__(256) void k_reduce_partial(int nchunks, int k, int 
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= k * nrhs) return;
-  const double* p = partial + (int64_t)t * nchunks;
-  double s = 0.0;
-  for (int ch = lane; ch < nchunks; ch += 64) s += p[ch];
-  s = wave_sum(s);
+  const double s = wave_strided_sum(partial + (int64_t)t * nchunks, nchunks, 1, lane);
   if (lane == 0) {
     const int j = t / nrhs, c = t - j * nrhs;
     H[j + (int64_t)c * ldh] = s;
@@ -440,17 +453,18 @@ __global__ __launch_bounds__(256) void k_resid_partial(int32_t n, const double* 
   }
 }
 
+// one wavefront per column: the sums over chunks of both quantities
 __global__ __launch_bounds__(256) void k_resid_reduce(int nchunks, int nc, const double* __restrict__ partial,
                                                       double* __restrict__ num, double* __restrict__ den) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (c >= nc) return;
-  double a = 0.0, b = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) {
-    a += partial[((int64_t)ch * nc + c) * 2 + 0];
-    b += partial[((int64_t)ch * nc + c) * 2 + 1];
+  const double a = wave_strided_sum(partial + (int64_t)c * 2, nchunks, (int64_t)nc * 2, lane);
+  const double b = wave_strided_sum(partial + (int64_t)c * 2 + 1, nchunks, (int64_t)nc * 2, lane);
+  if (lane == 0) {
+    num[c] = a;
+    den[c] = b;
   }
-  num[c] = a;
-  den[c] = b;
 }
 
 __global__ __launch_bounds__(256) void k_copy_cols(int32_t n, const double* __restrict__ src, int64_t lds,
@@ -547,7 +561,6 @@ __global__ __launch_bounds__(256) void k_axpy(int64_t count, double a, const dou
 //   D = [L_0^T M x, .., L_{lw-1}^T M x, x^T M x, L_0^T M L_0, L_0^T M L_1, L_1^T M L_1]
 // (the last two only for lw = 2).
 constexpr int kWinCH = 1024;
-constexpr int kWinGrid = 512;  // workgroups of k_window_scale (grid-stride)
 __host__ __device__ constexpr int window_dot_count(int lw) { return lw + 1 + lw * (lw + 1) / 2; }
 __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const double* __restrict__ L, int64_t ldl,
                                                      const double* __restrict__ m, double* __restrict__ partial) {
@@ -592,28 +605,24 @@ __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const do
   }
 }
 
-// Every workgroup sums the partials in chunk order (the same values bit for
-// bit in all of them), then x <- (x - sum_{j<lw} c_j L_j) / sqrt(g) with
-// c_j = L_j^T M x and g = x^T M x - 2 c^T c + c^T G c (G the window's Gram
-// matrix): the exact M-norm^2 after the pass, to rounding of order
-// eps * x^T M x.  When g < 1e-4 x^T M x that rounding is no longer small: x
-// is only subtracted and status 2 tells the caller to normalise it
-// explicitly.  Workgroup 0 writes T = [c, x^T M x] and
-// rec = {T[0..lw], g, status}.
-__global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double* __restrict__ L, int64_t ldl,
-                                                      const double* __restrict__ partial, int nchunks,
-                                                      double* __restrict__ T, double* __restrict__ rec) {
+// One workgroup sums the partials in chunk order and forms c_j = L_j^T M x
+// and g = x^T M x - 2 c^T c + c^T G c (G the window's Gram matrix): the exact
+// M-norm^2 after the pass, to rounding of order eps * x^T M x.  When
+// g < 1e-4 x^T M x that rounding is no longer small: status 2 tells the caller
+// to normalise explicitly (x is then only subtracted).  Writes T = [c, x^T M x],
+// coef = {c_0, c_1, scale} for k_window_scale and rec = {T[0..lw], g, status}.
+__global__ __launch_bounds__(256) void k_window_reduce(int lw, const double* __restrict__ partial, int nchunks,
+                                                       double* __restrict__ T, double* __restrict__ coef,
+                                                       double* __restrict__ rec) {
   __shared__ double ds[6];
   const int nd = window_dot_count(lw);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int d = wave; d < nd; d += 4) {
-    double v = 0.0;
-    for (int c = lane; c < nchunks; c += 64) v += partial[(int64_t)d * nchunks + c];
-    v = wave_sum(v);
+    const double v = wave_strided_sum(partial + (int64_t)d * nchunks, nchunks, 1, lane);
     if (lane == 0) ds[d] = v;
   }
   __syncthreads();
-  double* x = L + (int64_t)lw * ldl;
+  if (threadIdx.x != 0) return;
   const double c0 = lw > 0 ? ds[0] : 0.0, c1 = lw > 1 ? ds[1] : 0.0;
   const double txx = ds[lw];
   double g = txx;
@@ -623,21 +632,27 @@ __global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double*
     g += c0 * (c0 * ds[2] - 2.0 * c0);
   }
   const bool strong = !(g > 0.0 && g >= 1e-4 * txx);
-  const double sc = strong ? 1.0 : 1.0 / sqrt(g);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double v = x[i];
-    if (lw > 0) v = fma(-c0, L[i], v);
-    if (lw > 1) v = fma(-c1, L[i + ldl], v);
-    x[i] = v * sc;
+  coef[0] = c0;
+  coef[1] = c1;
+  coef[2] = strong ? 1.0 : 1.0 / sqrt(g);
+  for (int j = 0; j <= lw; ++j) {
+    T[j] = ds[j];
+    rec[j] = ds[j];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int j = 0; j <= lw; ++j) {
-      T[j] = ds[j];
-      rec[j] = ds[j];
-    }
-    rec[lw + 1] = g;
-    rec[lw + 2] = strong ? 2.0 : 1.0;
-  }
+  rec[lw + 1] = g;
+  rec[lw + 2] = strong ? 2.0 : 1.0;
+}
+
+// x <- (x - c_0 L_0 - c_1 L_1) * scale with the coefficients of k_window_reduce
+__global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double* __restrict__ L, int64_t ldl,
+                                                      const double* __restrict__ coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* x = L + (int64_t)lw * ldl;
+  double v = x[i];
+  if (lw > 0) v = fma(-coef[0], L[i], v);
+  if (lw > 1) v = fma(-coef[1], L[i + ldl], v);
+  x[i] = v * coef[2];
 }
 
 }  // namespace
@@ -663,8 +678,9 @@ int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, Gemv
   }
   hipLaunchKernelGGL(k_window_dots, dim3(nchunks), dim3(256), 0, st, n, lw, L, ldl, m, wk.partial);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_window_scale, dim3(std::min(kWinGrid, ceil_div64(n, 256))), dim3(256), 0, st, n, lw, L, ldl,
-                     wk.partial, nchunks, T, rec);
+  hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_window_scale, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, lw, L, ldl, rec + 8);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
@@ -876,7 +892,7 @@ int residual_norms(int32_t n, const double* SV, const double* V, int64_t ld, con
   hipLaunchKernelGGL(k_resid_partial, dim3(nchunks, nc), dim3(256), 0, st, n, SV, V, ld, m, theta, nc, CH,
                      wk.partial);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_resid_reduce, dim3(ceil_div64(nc, 256)), dim3(256), 0, st, nchunks, nc, wk.partial, num, den);
+  hipLaunchKernelGGL(k_resid_reduce, dim3(ceil_div64(nc, 4)), dim3(256), 0, st, nchunks, nc, wk.partial, num, den);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

@@ -135,11 +135,12 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
            hipStream_t st);
 
 // Three-term step of one column x = L[:, lw] (lw <= 2 window columns before
-// it, leading dimension ldl), two launches: c_j = L[:, j]^T M x (j < lw),
+// it, leading dimension ldl), three launches: c_j = L[:, j]^T M x (j < lw),
 // x <- (x - sum_j c_j L[:, j]) / sqrt(g) with g the M-norm^2 after the
 // subtraction (from x^T M x, c and the window's Gram matrix, no further pass);
-// T = [c, x^T M x]; rec = {T[0..lw], g, status} with status 1 (scaled) or 2
-// (g < 1e-4 x^T M x: only subtracted, the caller normalises explicitly).
+// T = [c, x^T M x]; rec (16 doubles of device memory) = {T[0..lw], g, status}
+// with status 1 (scaled) or 2 (g < 1e-4 x^T M x: only subtracted, the caller
+// normalises explicitly); rec[8..10] is work space.
 int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, GemvTWork& wk, double* T, double* rec,
                 hipStream_t st);
 
