@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <atomic>
@@ -84,7 +85,10 @@ struct kf_problem {
   GemvTWork rw;
   EigWork ew;
   int basis_cols = 0;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // 0, 1: filter start / end, 2: orthogonalisation end, 3, 4: check start /
+  // end; 5, 6: start / end of a filter application queued ahead (swapped
+  // with 0, 1 when it is kept)
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   double tuned_us = 0.0;
   // k x k work arrays of the pencil correction (E, E H, corrected H)
   double* rr_work = nullptr;
@@ -396,7 +400,8 @@ struct Readback {
 
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
                hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr,
-               bool monitor = true, bool* pending_loose = nullptr) {
+               bool monitor = true, bool* pending_loose = nullptr, const std::function<int()>* ahead = nullptr,
+               bool* ahead_kept = nullptr) {
   if (c0 != kb) return fail(KF_EINVAL, "orth_block: the block must follow the basis");
   hipStream_t st = p->st;
   const int32_t n = p->n;
@@ -482,8 +487,18 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       KF_TRY(window_step(n, lw, L1, ldb, p->d_m, p->gw, T1, rec, st));
       double rh[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       KF_TRY(fetch(rec, (size_t)lw + 3, rh));
-      if (done) KF_HIP(hipEventRecord(done, st));
-      KF_HIP(hipStreamSynchronize(st));
+      if (ahead && done) {
+        // queue the next filter application (on this column) before waiting
+        // for the readback: the host's turnaround overlaps the time steps;
+        // the caller drops it if this column is changed below
+        KF_HIP(hipEventRecord(done, st));
+        KF_TRY((*ahead)());
+        KF_HIP(hipEventSynchronize(done));
+        if (ahead_kept) *ahead_kept = true;
+      } else {
+        if (done) KF_HIP(hipEventRecord(done, st));
+        KF_HIP(hipStreamSynchronize(st));
+      }
       rb.land();
       for (int j = 0; j <= lw; ++j) hv[(size_t)j] = rh[j];
       g2h = rh[lw + 1];
@@ -491,6 +506,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       // status 2: strong cancellation in the window pass, the norm by
       // Pythagoras is not accurate; normalise against the explicit norm
       explicit_norm = rh[lw + 2] != 1.0;
+      if (explicit_norm && ahead_kept) *ahead_kept = false;
     }
     if (explicit_norm) {
       KF_TRY(finish_cols(Tref, ld1));
@@ -503,6 +519,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     }
     have = true;
     if (fl[0] && g2h < 1e-4 * hv[(size_t)lw]) {
+      if (ahead_kept) *ahead_kept = false;
       have = false;
       // the window pass removed all but 1 % of the norm: its rounding is no
       // longer negligible, so this column gets a pass against the whole basis
@@ -1395,6 +1412,9 @@ struct SolveState {
   int proj_every = 1, since_proj = 0;
   int pred_k = -1;  // basis size and unconverged candidates at the previous check
   std::vector<double> pred_theta, pred_res;
+  // kf_solve: the next filter application may be queued before the host
+  // has read this step's orthogonalisation (ahead_ok), and was (ahead_ready)
+  bool ahead_ok = false, ahead_ready = false;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -1571,8 +1591,25 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   const bool monitor = !three || s.proj_every <= 1 || s.since_proj + 1 >= s.proj_every ||
                        s.pending + s.bk > 15;
   bool loose = false;
+  // between projections and checks the step's column is final once the
+  // window pass is done (unless the pass cancels strongly): the next filter
+  // application can then be queued before the host reads it back
+  const int it1 = s.iters, cur1 = s.cur + s.bk;
+  const bool check_next = it1 % p->opt.check_every == 0 && cur1 >= s.next_check;
+  const bool go_on = !(p->opt.max_iters > 0 && it1 >= p->opt.max_iters) && cur1 < s.m_max;
+  const bool ahead_ok = s.ahead_ok && three && !monitor && !check_next && go_on;
+  const int64_t ldb = p->ldb;
+  const std::function<int()> ahead = [&]() -> int {
+    KF_HIP(hipEventRecord(p->ev[5], st));
+    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.cur * ldb, 1, ldb, s.bk, s.bk, p->B + (int64_t)cur1 * ldb, 1,
+                      ldb, s.bk, p->w));
+    KF_HIP(hipEventRecord(p->ev[6], st));
+    return KF_OK;
+  };
+  bool ahead_kept = false;
   KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], monitor ? s.pending : 0,
-                    p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose));  // synchronises the stream
+                    p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose, ahead_ok ? &ahead : nullptr,
+                    &ahead_kept));  // synchronises with the step's readback
   if (loose) s.proj_every = std::max(1, s.proj_every / 2);
   if (monitor) {
     s.pending = 0;
@@ -1587,6 +1624,13 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   if (s.timed_filter) {
     KF_TRY(elapsed_acc(p->ev[0], p->ev[1], s.t_lf));
     KF_TRY(elapsed_acc(p->ev[1], p->ev[2], s.t_gs));
+  }
+  // a filter queued ahead is kept when the column it read stayed as it was
+  // (it is recomputed otherwise); its events become the next step's
+  s.ahead_ready = ahead_kept && kept == s.bk;
+  if (s.ahead_ready) {
+    std::swap(p->ev[0], p->ev[5]);
+    std::swap(p->ev[1], p->ev[6]);
   }
   for (int j = 0; j < s.bk; ++j) {
     // a stable step keeps |C x|_M <= sum|w_l| max|q_l| for |x|_M = 1
@@ -1712,12 +1756,19 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   SolveState s;
   KF_TRY(solve_begin(p, start, b, m_max, tol, s));
   s.timed_filter = true;
+  s.ahead_ok = true;
   const int64_t ldb = p->ldb;
   while (solve_wants_filter(p, s)) {
-    KF_HIP(hipEventRecord(p->ev[0], p->st));
-    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.q0 * ldb, 1, ldb, s.qn, s.bk, p->B + (int64_t)s.cur * ldb, 1,
-                      ldb, s.bk, p->w));
-    KF_HIP(hipEventRecord(p->ev[1], p->st));
+    if (s.ahead_ready) {
+      // queued during the previous step's orthogonalisation (same input
+      // column q0, same output column cur)
+      s.ahead_ready = false;
+    } else {
+      KF_HIP(hipEventRecord(p->ev[0], p->st));
+      KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.q0 * ldb, 1, ldb, s.qn, s.bk, p->B + (int64_t)s.cur * ldb,
+                        1, ldb, s.bk, p->w));
+      KF_HIP(hipEventRecord(p->ev[1], p->st));
+    }
     KF_TRY(solve_after_filter(p, s));
   }
   return solve_finish(p, s, out);

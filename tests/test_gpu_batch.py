@@ -30,7 +30,10 @@ def _members(spec):
     return out
 
 
-SPEC = [(2, 20, 0.3, 0.5, 1), (2, 33, 0.2, 0.3, 2), (3, 9, 0.3, 0.6, 5), (2, 41, 0.1, 0.2, 0), (3, 12, 0.25, 0.4, 0)]
+# L = 1 and 2 (no step, one step), 4, 5 and 7 (last steps with two, three and
+# one pending levels of the weighted sum), and the time-step rule's L
+SPEC = [(2, 20, 0.3, 0.5, 1), (2, 33, 0.2, 0.3, 2), (3, 9, 0.3, 0.6, 5), (2, 41, 0.1, 0.2, 0), (3, 12, 0.25, 0.4, 0),
+        (2, 25, 0.3, 0.4, 4), (3, 8, 0.3, 0.5, 7)]
 
 
 @pytest.mark.parametrize("precision,b", [("fp64", 1), ("fp64", 3), ("mixed", 4)])

@@ -46,6 +46,12 @@ def _case(dim, n, omin_frac=0.3, omax_frac=0.5, L=None):
         (3, 13, 8, 9, 0, 1),
         (3, 9, 16, 5, 4, 1),
         (3, 11, 5, 6, 2, 0),
+        # the weighted sum is taken every third step: L - 1 = 2, 3, 6, 9
+        # cover last steps with one, two and three pending levels
+        (2, 37, 1, 3, 0, 1),
+        (2, 37, 1, 4, 0, 1),
+        (2, 37, 2, 7, 2, 1),
+        (3, 9, 4, 10, 0, 0),
     ],
 )
 def test_apply_filter_fp64_matches_oracle(dim, n, b, L, index_bytes, remap):
