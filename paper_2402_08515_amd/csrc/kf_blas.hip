@@ -703,7 +703,12 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   // of 32 along the grid's z, chunks of 2048 rows (the sums over rows stay
   // in the accumulators)
   const bool mfma = nrhs > 3;
-  const int CH = mfma ? 2048 : 1024;
+  // row chunks of 2048 (1024 on the vector path), halved down to 256 while
+  // the grid would leave the chip mostly idle (small problems, few columns)
+  const int cols_per_wg = mfma ? 16 * kMfmaWaves : 64;
+  const int zgroups = !mfma ? 1 : (nrhs <= 16 ? 1 : ceil_div64(nrhs, 32));
+  int CH = mfma ? 2048 : 1024;
+  while (CH > 256 && (int64_t)ceil_div64(n, CH) * ceil_div64(k, cols_per_wg) * zgroups < 1024) CH /= 2;
   const int nchunks = ceil_div64(n, CH);
   const size_t need = (size_t)nchunks * k * nrhs;
   if (wk.cap < need) {
