@@ -87,7 +87,9 @@ typedef struct kf_options {
                             orthogonal to the older ones in exact arithmetic)
                             then once against the whole basis, a second time
                             only when that pass removed over half the norm */
-  int32_t target;        /* stop once this many pairs are accepted (0: never) */
+  int32_t target;        /* stop once this many pairs are accepted (0: never);
+                            a basis of k columns holds at most k Ritz pairs,
+                            so no check runs before it has target columns */
   int32_t max_iters;     /* cap on filter applications (0: none) */
   double drop_tol;       /* a new column whose M-norm after orthogonalisation
                             is <= drop_tol times its M-norm before is dropped

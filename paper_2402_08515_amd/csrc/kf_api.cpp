@@ -1537,6 +1537,8 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   s.prev0 = 0;
   s.pending = kept;
   s.target = p->opt.target;
+  // k columns hold at most k Ritz pairs: no check can meet the target earlier
+  s.next_check = std::max(s.target, 0);
   for (double v : p->w) s.wsum += std::fabs(v);
   return KF_OK;
 }
@@ -1561,10 +1563,10 @@ int solve_check_now(kf_problem* p, SolveState& s) {
       KF_TRY(rl.get(&lh, p->flags + 33, sizeof(int32_t)));
       KF_HIP(hipStreamSynchronize(st));
       rl.land();
-      if (lh) {
-        KF_TRY(repair_block(p, c0, nc));
-        s.proj_every = std::max(1, s.proj_every / 2);
-      }
+      // drifted columns are orthogonalised again; the interval is left to
+      // the periodic projection's own check (halving here as well shortened
+      // it more than needed: slower solves on the 96- and 128-cell cubes)
+      if (lh) KF_TRY(repair_block(p, c0, nc));
     }
   }
   // the check formed the pending columns' projections and checked their
