@@ -599,10 +599,8 @@ __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const do
     if (lane == 0) red[wave][d] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nd) {
-    const int d = threadIdx.x;
-    partial[(int64_t)d * nchunks + chunk] = ((red[0][d] + red[1][d]) + red[2][d]) + red[3][d];
-  }
+  const int d = (int)threadIdx.x;
+  if (d < nd) partial[(int64_t)d * nchunks + chunk] = ((red[0][d] + red[1][d]) + red[2][d]) + red[3][d];
 }
 
 // One workgroup sums the partials in chunk order and forms c_j = L_j^T M x
