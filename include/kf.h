@@ -99,9 +99,10 @@ typedef struct kf_options {
                             coefficients against the whole basis are always
                             computed (they are needed for B^T S B), but
                             subtracted only when one exceeds reorth_tol times
-                            the column's M-norm, so the basis stays
-                            M-orthonormal to about that level (reported as
-                            kf_result.orth_error); 0 = always subtract */
+                            the column's M-norm; with the pending-column check
+                            of proj_every the basis stays M-orthonormal to
+                            about 1e-7 (reported as kf_result.orth_error);
+                            0 = always subtract */
   int32_t proj_every;    /* KF_FP64, single-vector blocks, full_reorth 0: the
                             projection onto the whole basis (which forms the
                             new columns of B^T S B and B^T M B and the
@@ -110,7 +111,8 @@ typedef struct kf_options {
                             orthogonalised against the last two columns only
                             (three-term form).  Columns found more than 1e-7
                             off M-orthogonal at a projection are orthogonalised
-                            again and proj_every is halved from then on.  The
+                            again and proj_every is halved from then on (a
+                            check repairs such columns without halving).  The
                             Rayleigh-Ritz step corrects to first order for the
                             remaining non-orthogonality (E = B^T M B - I: the
                             eigenvalues of H - (E H + H E)/2); 1 = every step */
