@@ -361,6 +361,16 @@ int ensure_misc(kf_problem* p) {
 // The block's own Gram matrix rides along as extra rows of the first
 // projection (the block sits right after its left operand in B: X is column
 // kb = c0), so the norms before each pass cost no launch of their own.
+//
+// carried != null (one vector, three-term form, pending columns): the
+// periodic projection also cleans the last pending column, column kb - 1,
+// against the rest of the basis, in the same subtraction as the new column.
+// The recurrence builds each new column from the last two, so their losses of
+// orthogonality both pass into the next column: cleaning only the new one
+// leaves the next columns near the level the last pending one had reached,
+// and the interval between projections shrinks.  Column kb - 1 changes after
+// its pencil entries were formed, so *carried = true asks the caller to keep
+// it pending (its entries are formed again at the next projection).
 int rr_update(kf_problem* p, int c0, int nc);
 int repair_block(kf_problem* p, int p0, int pn);
 
@@ -401,7 +411,7 @@ struct Readback {
 int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<double>& ref_out,
                hipEvent_t done = nullptr, int pn = 0, int loc0 = -1, int* full_passes = nullptr,
                bool monitor = true, bool* pending_loose = nullptr, const std::function<int()>* ahead = nullptr,
-               bool* ahead_kept = nullptr) {
+               bool* ahead_kept = nullptr, bool* carried = nullptr) {
   if (c0 != kb) return fail(KF_EINVAL, "orth_block: the block must follow the basis");
   hipStream_t st = p->st;
   const int32_t n = p->n;
@@ -411,7 +421,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   double* nrm2 = p->small + kNrm2;   // nb squared norms
   double* g2 = p->small + kG2;       // nb x nb Gram after the full pass (blocks)
   double* T1 = p->small + kT1;       // first projection [(w + nb) x nb]
-  double* coef = p->T;               // (kb + nb) x (2 pn + nb)
+  double* coef = p->T;               // (kb + nb) x (2 pn + nb), 2 more with carried
   const bool local = kb > 0 && loc0 >= 0;
   const int lw = local ? kb - loc0 : 0;
   // first projection: the window [loc0, kb) (none without the three-term
@@ -446,7 +456,17 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       KF_TRY(gemv_t(n, ldc, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, ldc, p->gw, st));
     }
     if (gated) KF_TRY(reorth_gate(kb, cx, cx + kb, p->opt.reorth_tol, gate, st));
-    KF_TRY(gemv_n_sub(n, kb, p->B, ldb, cx, ldc, X, ldb, nb, st, gated ? gate : nullptr));
+    if (carried && local && with_pending && pn > 0 && nb == 1) {
+      // columns kb - 1 and kb in one pass over the basis: the coefficients of
+      // column kb - 1 (without its own row) beside those of the new column
+      double* pc = coef + (int64_t)(2 * pn + 1) * ldc;
+      KF_TRY(pair_coef(kb, coef + (int64_t)(2 * pn - 1) * ldc, cx, pc, ldc, p->opt.reorth_tol, gated ? gate : nullptr,
+                       st));
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, pc, ldc, X - ldb, ldb, 2, st, gated ? gate : nullptr));
+      *carried = true;
+    } else {
+      KF_TRY(gemv_n_sub(n, kb, p->B, ldb, cx, ldc, X, ldb, nb, st, gated ? gate : nullptr));
+    }
     if (full_passes && !gated) ++*full_passes;
     return KF_OK;
   };
@@ -1587,8 +1607,9 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   s.lf_steps += (int64_t)s.qn * (p->L - 1);
   int kept = 0;
   // single vectors in the three-term form project onto the whole basis every
-  // proj_every steps; columns that drifted beyond kPendingTol are repaired
-  // and the interval halved
+  // proj_every steps (the new column and the last pending one are cleaned);
+  // columns that drifted beyond kPendingTol are repaired and the interval
+  // halved
   const bool three = !p->opt.full_reorth && s.bk == 1 && s.cur > 0;
   const bool monitor = !three || s.proj_every <= 1 || s.since_proj + 1 >= s.proj_every ||
                        s.pending + s.bk > 15;
@@ -1608,13 +1629,14 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
     KF_HIP(hipEventRecord(p->ev[6], st));
     return KF_OK;
   };
-  bool ahead_kept = false;
+  bool ahead_kept = false, carried = false;
   KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], monitor ? s.pending : 0,
                     p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose, ahead_ok ? &ahead : nullptr,
-                    &ahead_kept));  // synchronises with the step's readback
+                    &ahead_kept, &carried));  // synchronises with the step's readback
   if (loose) s.proj_every = std::max(1, s.proj_every / 2);
   if (monitor) {
-    s.pending = 0;
+    // the last pending column, cleaned with the new one, stays pending
+    s.pending = carried ? 1 : 0;
     s.since_proj = 0;
   } else {
     ++s.since_proj;

@@ -795,6 +795,36 @@ int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, 
   return KF_OK;
 }
 
+// Coefficients for one subtraction that cleans two columns: out[:, 0] = c_last
+// with its own row (kb - 1) zeroed, out[:, 1] = cx (rows < kb, leading
+// dimension ldo).  The gate is raised when an entry of c_last exceeds tol,
+// so the subtraction runs whenever either column needs it.
+__global__ __launch_bounds__(256) void k_pair_coef(int kb, const double* __restrict__ c_last,
+                                                   const double* __restrict__ cx, double* __restrict__ out,
+                                                   int64_t ldo, double tol, int32_t* __restrict__ gate) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < kb; j += blockDim.x) {
+    const double v = j == kb - 1 ? 0.0 : c_last[j];
+    out[j] = v;
+    out[ldo + j] = cx[j];
+    mx = fmax(mx, isfinite(v) ? fabs(v) : INFINITY);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0 && gate && fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) > tol) *gate = 1;
+}
+
+int pair_coef(int kb, const double* c_last, const double* cx, double* out, int64_t ldo, double tol, int32_t* gate,
+              hipStream_t st) {
+  if (kb <= 0) return KF_OK;
+  hipLaunchKernelGGL(k_pair_coef, dim3(1), dim3(256), 0, st, kb, c_last, cx, out, ldo, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st) {
   hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(256), 0, st, k, c, g, tol, gate);
   KF_HIP(hipGetLastError());

@@ -156,6 +156,12 @@ int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, 
 // *gate = 1 if max_j |c[j]| (j < k) > tol * sqrt(*g), else 0 (device values)
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st);
 
+// out[:, 0] = c_last with row kb-1 set to 0, out[:, 1] = cx (rows < kb,
+// leading dimension ldo); *gate = 1 if some |c_last[j]| (j < kb-1) > tol,
+// left as it is otherwise (gate may be null)
+int pair_coef(int kb, const double* c_last, const double* cx, double* out, int64_t ldo, double tol, int32_t* gate,
+              hipStream_t st);
+
 // Y[:, c] = S X[:, c] (c < ncols), optional row scaling Y[i,c] *= rscale[i]
 int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,
               const double* rscale, hipStream_t st);
