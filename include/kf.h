@@ -109,8 +109,11 @@ typedef struct kf_options {
                             orthogonalisation coefficients) runs every
                             proj_every steps; in between a step is
                             orthogonalised against the last two columns only
-                            (three-term form).  Columns found more than 1e-7
-                            off M-orthogonal at a projection are orthogonalised
+                            (three-term form).  A projection cleans the new
+                            column and the last column of the previous
+                            interval (both feed the next step).  Columns found
+                            more than 1e-7 off M-orthogonal at a projection
+                            are orthogonalised
                             again and proj_every is halved from then on (a
                             check repairs such columns without halving).  The
                             Rayleigh-Ritz step corrects to first order for the
