@@ -1632,10 +1632,11 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   bool ahead_kept = false, carried = false;
   KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], monitor ? s.pending : 0,
                     p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose, ahead_ok ? &ahead : nullptr,
-                    &ahead_kept, &carried));  // synchronises with the step's readback
+                    &ahead_kept, s.proj_every > 1 ? &carried : nullptr));  // synchronises with the step's readback
   if (loose) s.proj_every = std::max(1, s.proj_every / 2);
   if (monitor) {
-    // the last pending column, cleaned with the new one, stays pending
+    // the last pending column, cleaned with the new one, stays pending (with
+    // a projection at every step each column was cleaned at its own step)
     s.pending = carried ? 1 : 0;
     s.since_proj = 0;
   } else {
