@@ -215,10 +215,24 @@ def bench_horn(args):
     tau, L = kf.time_step_rule(lam, P.omega_min)
     print(f"[bench] horn: n={P.n} nnz={P.nnz} (built in {t_mesh:.1f}s) lambda_est={lam:.6g} tau={tau:.6g} L={L}",
           file=sys.stderr, flush=True)
+    V0 = start_block(P.n, P.block, P.seed)
+    if args.probe_traffic:
+        # counter calibration: one device-to-device copy of exactly 1 GiB read
+        # + 1 GiB written, then one filter application of the block (L-1 fused
+        # steps) in the variant the autotuner picks here (2 lanes per row)
+        prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision="mixed", autotune=False,
+                          lanes_per_row=2)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        b = torch.empty_like(a)
+        b.copy_(a)
+        x = torch.from_numpy(V0).cuda()
+        prob.apply_filter(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "copy_bytes": a.numel() * 8, "workload": "horn_4m", "L": L}))
+        return
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision="mixed", check_every=args.check_every,
                       check_growth=args.check_growth, max_iters=args.horn_iters, autotune=not args.no_autotune)
     tuning = prob.tuning()
-    V0 = start_block(P.n, P.block, P.seed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = prob.solve(V0, m_max=args.m_max, tol=args.tol)
@@ -228,6 +242,8 @@ def bench_horn(args):
     per_launch = r.t_leapfrog / max(launches, 1)
     bytes_step = algorithmic_bytes_per_step(P.n, P.nnz, P.block, 4, L)
     achieved = bytes_step / per_launch / 1e9
+    src = open(os.path.join(ROOT, "paper_2402_08515_amd", "csrc", "kf_step.hip"), "rb").read()
+    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(), "horn_4m")
     print(f"[bench] {r.krylov_steps} block iterations in {wall:.2f}s (stepping {r.t_leapfrog:.2f}s, "
           f"gs {r.t_gs:.2f}s, rr {r.t_rr:.2f}s), basis {r.basis_size}, pairs {r.omega2.size}",
           file=sys.stderr, flush=True)
@@ -252,7 +268,7 @@ def bench_horn(args):
         "leapfrog_only_dof_steps_per_s": P.n * r.leapfrog_vector_steps / r.t_leapfrog,
         "phase_seconds": {"leapfrog": r.t_leapfrog, "gram_schmidt": r.t_gs, "rayleigh_ritz": r.t_rr},
         "roofline": {"bound": "hbm", "kernel": "k_leapfrog (block 16, float32)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_step, "avg_launch_us": per_launch * 1e6, "variant": tuning},
     }
     print(json.dumps(out))
