@@ -291,14 +291,22 @@ int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, 
   hipStream_t st = p->st;
   if (L == 1) return launch_scale_copy(p->n, bout, std::min(bsrc, bout), src, srs, scs, w[0], dst, drs, dcs, st);
   KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
-  KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, sb.Y1, st));
+  // a single float64 vector stored contiguously already has the layout of a
+  // step buffer: the first two steps read it in place (no load launch);
+  // otherwise it is loaded (converted, interleaved) into Y1
+  const bool direct = A.val_bytes == 8 && bk == 1 && bsrc == 1 && srs == 1;
+  const void* y0 = direct ? static_cast<const void*>(src) : sb.Y1;
+  if (!direct) KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, sb.Y1, st));
   void* Y[2] = {sb.Y0, sb.Y1};
   auto wt = [&](int i) { return i < 0 ? 0.0 : w[(size_t)i]; };
   for (int l = 1; l < L; ++l) {
     const StepPlan sp = step_plan(l, L);
-    void* cur = Y[l & 1];
+    // step l reads y_l (cur) and y_{l-1} (prev) and writes y_{l+1} over
+    // y_{l-1}, except at l = 2 where y_1 is the source itself
+    const void* cur = l == 1 ? y0 : Y[l & 1];
     void* nxt = Y[(l + 1) & 1];
-    KF_TRY(launch_leapfrog(A, bk, sp.mode, cur, nxt, nxt, sb.R, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic), wt(sp.in),
+    const void* prv = l == 2 ? y0 : nxt;
+    KF_TRY(launch_leapfrog(A, bk, sp.mode, cur, prv, nxt, sb.R, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic), wt(sp.in),
                            p->opt.xcd_remap, st));
   }
   return KF_OK;
