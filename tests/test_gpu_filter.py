@@ -52,6 +52,9 @@ def _case(dim, n, omin_frac=0.3, omax_frac=0.5, L=None):
         (2, 37, 1, 4, 0, 1),
         (2, 37, 2, 7, 2, 1),
         (3, 9, 4, 10, 0, 0),
+        # a single float64 vector is read in place by the first two steps
+        (2, 20, 1, 2, 0, 1),  # L = 2: the in-place first step is also the last
+        (2, 5, 1, 9, 0, 1),  # 16 DOFs: less than one 64-row slice
     ],
 )
 def test_apply_filter_fp64_matches_oracle(dim, n, b, L, index_bytes, remap):

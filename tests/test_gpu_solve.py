@@ -138,6 +138,25 @@ def test_breakdown_on_exact_eigenvector():
     assert got.omega2.size == 1 and got.omega2[0] == pytest.approx(mu[1] + mu[2], rel=1e-12)
 
 
+def test_interval_without_eigenvalues_returns_no_pairs():
+    """An interval inside a gap of the spectrum: the solve ends at m_max with
+    no accepted pair and no error, as the oracle does."""
+    kf = _kf()
+    n = 20
+    S, m, h = grid_problem(2, n)
+    lam = np.unique(np.round(grid_spectrum(2, n), 9))
+    i = int(np.argmax(np.diff(lam[:40])))  # the widest gap among the low eigenvalues
+    lo, hi = lam[i] + 0.25 * (lam[i + 1] - lam[i]), lam[i + 1] - 0.25 * (lam[i + 1] - lam[i])
+    omin, omax = math.sqrt(lo), math.sqrt(hi)
+    tau, L, w = _params(S, m, omin, omax, 0)
+    V0 = start_block(S.shape[0], 1, 4)
+    print(f"case empty interval [{omin:.4f}, {omax:.4f}] grid2d_20", flush=True)
+    ref = oracle.krylov_solve(S, m, tau, w, V0, omin, omax, tol=1e-9, m_max=24)
+    got = kf.Problem(S, m, omin, omax, tau, L).solve(V0, m_max=24, tol=1e-9)
+    assert ref.omega2.size == 0
+    assert got.omega2.size == 0 and got.basis_size == 24 and not got.breakdown
+
+
 def test_near_eigenvector_start_matches_oracle(grid2d):
     """A start vector within 1e-5 of an eigenvector: each filtered column is
     almost parallel to the previous one, so the window pass of a step cancels
