@@ -438,7 +438,8 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
   double* L1 = p->B + (int64_t)(kb - lw) * ldb;
   const double* Tref = T1 + lw;  // nb x nb, leading dimension ld1
   // one vector between projections: the window pass and the normalisation
-  // in two launches and one readback (norm by Pythagoras over the window)
+  // in three launches and one readback (the norm from the window's Gram
+  // matrix and the new column's products with it)
   const bool fused = kb > 0 && nb == 1 && !monitor && local && lw <= 2;
   if (!fused) {
     KF_TRY(gemv_t(n, ld1, L1, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, T1, ld1, p->gw, st));

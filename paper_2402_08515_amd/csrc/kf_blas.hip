@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void k_axpy(int64_t count, double a, const dou
 }
 
 
-// Three-term Gram-Schmidt step of one column in two launches (the window
+// Three-term Gram-Schmidt step of one column in three launches (the window
 // pass of Algorithm 2.5 in the M inner product).  k_window_dots writes the
 // per-chunk partial sums of the lw window columns' products with x (L's
 // column lw is x), x^T M x, and the window's own Gram matrix:
