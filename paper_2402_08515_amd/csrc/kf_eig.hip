@@ -395,17 +395,24 @@ __global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict_
 // arrays (LU factors and the iterate) are interleaved across lanes, element i
 // of lane c at [i * ldw + c], so that at every step the lanes of a wavefront
 // touch consecutive addresses.  Finished vectors go to Z (m x nsel).
+// LDS: the work arrays of the wavefront's first ldw lanes live in LDS (the
+// recurrences are chains of dependent steps, and LDS answers in a fraction of
+// the time of the cache hierarchy); otherwise in `scratch` (global memory).
 constexpr int kIvB = 8;  // rows loaded ahead of the running values
+constexpr int kIvLdsBytes = 65536;  // LDS for the work arrays of one wavefront
+template <bool LDS>
 __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ d, const double* __restrict__ e,
                                               const double* __restrict__ bounds, int ncl,
                                               const int32_t* __restrict__ cstart, const double* __restrict__ sel,
                                               double* __restrict__ Z, double* __restrict__ scratch, int ldw) {
-  const int cl = blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double ivs[];
+  if (LDS && (int)threadIdx.x >= ldw) return;
+  const int cl = LDS ? blockIdx.x * ldw + threadIdx.x : blockIdx.x * blockDim.x + threadIdx.x;
   if (cl >= ncl) return;
   const double tn = fmax(fabs(bounds[0]), fabs(bounds[1]));
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
   const int64_t blk = (int64_t)m * ldw;
-  double* __restrict__ rinv = scratch + cl;
+  double* __restrict__ rinv = LDS ? ivs + threadIdx.x : scratch + cl;
   double* __restrict__ u1 = rinv + blk;
   double* __restrict__ u2 = u1 + blk;
   double* __restrict__ lm = u2 + blk;
@@ -666,9 +673,18 @@ int eig_vectors(EigWork& w, int k, const double* theta_sel, const int32_t* clust
   KF_TRY(eig_reserve(w, k, nsel));
   KF_HIP(hipMemcpyAsync(w.sel, theta_sel, sizeof(double) * nsel, hipMemcpyHostToDevice, st));
   KF_HIP(hipMemcpyAsync(w.cl, cluster_start, sizeof(int32_t) * (nclusters + 1), hipMemcpyHostToDevice, st));
-  const int ldw = cdiv(nclusters, 64) * 64;  // <= nsel + 63
-  hipLaunchKernelGGL(k_invit, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters, w.cl,
-                     w.sel, w.Z, w.scratch, ldw);
+  // six work arrays of k doubles per lane: as many lanes per wavefront as fit
+  // in kIvLdsBytes of LDS, else all 64 lanes with the arrays in global memory
+  const int lds_lanes = std::min(64, kIvLdsBytes / (6 * 8 * k));
+  if (lds_lanes >= 1) {
+    const size_t lds = sizeof(double) * 6 * (size_t)k * lds_lanes;
+    hipLaunchKernelGGL(k_invit<true>, dim3(cdiv(nclusters, lds_lanes)), dim3(64), lds, st, k, w.d, w.e, w.bounds,
+                       nclusters, w.cl, w.sel, w.Z, w.scratch, lds_lanes);
+  } else {
+    const int ldw = cdiv(nclusters, 64) * 64;  // <= nsel + 63
+    hipLaunchKernelGGL(k_invit<false>, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters,
+                       w.cl, w.sel, w.Z, w.scratch, ldw);
+  }
   KF_HIP(hipGetLastError());
   const int grid = cdiv(nsel, 4);
   const int mt = cdiv(k, 64);
