@@ -482,6 +482,8 @@ def main():
     ap.add_argument("--check-growth", type=float, default=0.3)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gather-unroll", type=int, default=0,
+                    help="single vectors: unroll factor of the fused step's loop over a slice (0 = autotuned)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-step variant instead of timing all of them at set-up")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -533,7 +535,8 @@ def main():
     tau, L = kf.time_step_rule(lam, P.omega_min)
     print(f"[bench] lambda_est={lam:.6g} tau={tau:.6g} L={L}", file=sys.stderr, flush=True)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
-                      check_every=args.check_every, check_growth=args.check_growth, autotune=not args.no_autotune)
+                      check_every=args.check_every, check_growth=args.check_growth, autotune=not args.no_autotune,
+                      gather_unroll=args.gather_unroll)
     tuning = prob.tuning()
     print(f"[bench] fused-step variant {tuning}", file=sys.stderr, flush=True)
     V0 = start_block(P.n, P.block, P.seed)

@@ -1096,6 +1096,22 @@ int autotune(kf_problem* p, DevCsr& dc, const double* d_scale) {
   p->A.nt_loads = best_nt;
   p->A64.nt_loads = best_nt;
   p->opt.xcd_remap = best_remap;
+  // then the unroll factor of the single-vector step's loop over a slice's
+  // entries (unless the caller fixed it); the float64 copy of the operator
+  // used by the refinement has the same slices and takes the same factor
+  if (p->opt.gather_unroll == 0) {
+    int best_u = 4;
+    for (int u = 2; u <= 4; ++u) {
+      p->A.unroll = u;
+      double us = 0;
+      KF_TRY(time_variant(p, p->A, p->sb, best_remap, 20, &us));
+      if (us < best) {
+        best = us;
+        best_u = u;
+      }
+    }
+    p->A.unroll = p->A64.unroll = best_u;
+  }
   p->tuned_us = best;
   return KF_OK;
 }
@@ -1147,6 +1163,7 @@ void kf_default_options(kf_options* o) {
   o->nt_loads = 0;
   o->autotune = 0;
   o->lanes_per_row = 0;
+  o->gather_unroll = 0;
   o->batch_workers = 0;
   o->stream = nullptr;
 }
@@ -1190,6 +1207,8 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.proj_every < 1) o.proj_every = 1;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 1 && o.lanes_per_row != 2 && o.lanes_per_row != 4)
     return fail(KF_EINVAL, "kf_create: lanes_per_row must be 0, 1, 2 or 4");
+  if (o.gather_unroll != 0 && (o.gather_unroll < 2 || o.gather_unroll > 4))
+    return fail(KF_EINVAL, "kf_create: gather_unroll must be 0, 2, 3 or 4");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 
@@ -1236,6 +1255,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     }
     p->A.nt_loads = o.nt_loads ? 1 : 0;
     p->A64.nt_loads = p->A.nt_loads;
+    p->A.unroll = p->A64.unroll = o.gather_unroll;
     for (hipEvent_t& e : p->ev)
       if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
     if (!rc && o.autotune) rc = autotune(p, dc, d_scale);
@@ -1286,11 +1306,12 @@ int kf_sym_eig(int32_t k, const double* A, double lo, double hi, double* theta, 
 }
 
 int kf_get_tuning(const kf_problem* p, int32_t* xcd_remap, int32_t* nt_loads, int32_t* index_bytes,
-                  double* us_per_step) {
+                  int32_t* gather_unroll, double* us_per_step) {
   if (!p) return fail(KF_EINVAL, "kf_get_tuning: NULL handle");
   if (xcd_remap) *xcd_remap = p->opt.xcd_remap;
   if (nt_loads) *nt_loads = p->A.nt_loads;
   if (index_bytes) *index_bytes = p->A.idx_bytes;
+  if (gather_unroll) *gather_unroll = p->A.unroll ? p->A.unroll : 4;
   if (us_per_step) *us_per_step = p->tuned_us;
   return KF_OK;
 }

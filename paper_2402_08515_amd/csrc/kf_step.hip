@@ -103,8 +103,9 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, int32_t nslices, c
 // One step for a block of B vectors.  LPR lanes share a row, each owning B/LPR
 // consecutive vector columns, so a wavefront covers 64/LPR rows of a slice and
 // the gather of a neighbour's block row is LPR adjacent 16-byte pieces (LPR = 1:
-// one lane per row with the whole block row in registers).
-template <typename T, typename IT, int B, int MODE, bool NT, int LPR>
+// one lane per row with the whole block row in registers).  U: unroll factor
+// of the loop over the slice's stored entries.
+template <typename T, typename IT, int B, int MODE, bool NT, int LPR, int U>
 __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
                                                   const T* __restrict__ val, const IT* __restrict__ idx,
                                                   const T* __restrict__ cur, const T* prev, T* out,
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
     yc = *reinterpret_cast<const Row<T, BL>*>(cur + off);
     if (!(MODE & kFirst)) yp = *reinterpret_cast<const Row<T, BL>*>(prev + off);
   }
-#pragma unroll 4
+#pragma unroll U
   for (int q = 0; q < width; ++q) {
     const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
     const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void k_scale_copy(int32_t n, int b, int bsrc, 
 }
 
 // ---- host-side dispatch helpers
-template <typename T, typename IT, int B, bool NT, int LPR>
+template <typename T, typename IT, int B, bool NT, int LPR, int U>
 int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   const int grid = ceil_div64((int64_t)A.nslices * LPR, 4);
@@ -306,23 +307,23 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   T* a = static_cast<T*>(acc);
   switch (mode) {
     case kMid:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     case kFirst:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     case kMidAcc:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMidAcc, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMidAcc, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     case kLast:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
     default:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
                          A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
       break;
   }
@@ -330,12 +331,27 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   return KF_OK;
 }
 
+template <typename T, typename IT, int B, int LPR, int U>
+int launch_lf_bu(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                 int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
+  if (A.nt_loads)
+    return launch_lf_bn<T, IT, B, true, LPR, U>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap,
+                                                st);
+  return launch_lf_bn<T, IT, B, false, LPR, U>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+}
+
+// The loop over a slice's entries is unrolled four times for blocks; for
+// single vectors the factor (2, 3 or 4) is a tuning choice: the best one
+// depends on the slice widths (on the 3D grids, 15 entries per row, three
+// times is 3 % faster than four).
 template <typename T, typename IT, int B, int LPR>
 int launch_lf_bl(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
-  if (A.nt_loads)
-    return launch_lf_bn<T, IT, B, true, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
-  return launch_lf_bn<T, IT, B, false, LPR>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  if (B == 1 && A.unroll == 2)
+    return launch_lf_bu<T, IT, B, LPR, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  if (B == 1 && A.unroll == 3)
+    return launch_lf_bu<T, IT, B, LPR, 3>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  return launch_lf_bu<T, IT, B, LPR, 4>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
 }
 
 template <typename T, typename IT, int B>

@@ -61,6 +61,7 @@ class OptionsT(C.Structure):
         ("autotune", C.c_int32),
         ("batch_workers", C.c_int32),
         ("lanes_per_row", C.c_int32),
+        ("gather_unroll", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -127,7 +128,7 @@ _SIGNATURES = {
     "kf_sym_eig": (C.c_int, [C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int32),
                              C.c_void_p, C.c_void_p]),
     "kf_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                C.POINTER(C.c_double)]),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "kf_create_batch": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(OptionsT), C.POINTER(C.c_void_p)]),
     "kf_destroy_batch": (C.c_int, [C.c_void_p]),
     "kf_batch_set_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
@@ -282,7 +283,7 @@ def _take_result(res, n: int) -> SolveResult:
 
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=2, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
-             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None):
+             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -303,6 +304,7 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
     opt.nt_loads = int(nt_loads)
     opt.autotune = int(autotune)
     opt.lanes_per_row = int(lanes_per_row)
+    opt.gather_unroll = int(gather_unroll)
     opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt
@@ -394,10 +396,11 @@ class Problem:
             pass
 
     def tuning(self) -> dict:
-        r, nt, ib = C.c_int32(), C.c_int32(), C.c_int32()
+        r, nt, ib, u = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         us = C.c_double()
-        _check(lib().kf_get_tuning(self._h, C.byref(r), C.byref(nt), C.byref(ib), C.byref(us)))
-        return {"xcd_remap": r.value, "nt_loads": nt.value, "index_bytes": ib.value, "us_per_step": us.value}
+        _check(lib().kf_get_tuning(self._h, C.byref(r), C.byref(nt), C.byref(ib), C.byref(u), C.byref(us)))
+        return {"xcd_remap": r.value, "nt_loads": nt.value, "index_bytes": ib.value, "gather_unroll": u.value,
+                "us_per_step": us.value}
 
     def weights(self) -> np.ndarray:
         w = np.empty(self.L)

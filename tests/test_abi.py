@@ -89,6 +89,25 @@ def test_create_rejects_bad_parameters(small):
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, index_bytes=3))
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, reorth_tol=-1.0))
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, reorth_tol=float("inf")))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, lanes_per_row=3))
+    assert "gather_unroll" in _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, gather_unroll=1))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, gather_unroll=5))
+
+
+def test_default_options_fill_the_bindings_structure():
+    """kf_default_options writes through the binding's copy of kf_options:
+    every default lands in its own field, so the two layouts agree."""
+    import ctypes
+
+    kf = _kf()
+    o = kf.OptionsT()
+    kf.lib().kf_default_options(ctypes.byref(o))
+    got = {f: getattr(o, f) for f, _ in kf.OptionsT._fields_}
+    want = {"precision": 0, "check_every": 1, "check_growth": 0.3, "full_reorth": 0, "target": 0, "max_iters": 0,
+            "drop_tol": 1e-10, "reorth_tol": 1e-9, "proj_every": 12, "refine": 2, "want_vectors": 0,
+            "index_bytes": 0, "xcd_remap": 1, "nt_loads": 0, "autotune": 0, "batch_workers": 0, "lanes_per_row": 0,
+            "gather_unroll": 0, "stream": None}
+    assert got == want
 
 
 def test_last_error_is_a_string():

@@ -159,6 +159,7 @@ def test_autotuned_and_cached_load_variants_match_oracle(precision):
     P = kf.Problem(S, m, omin, omax, tau, L, precision=precision, autotune=True)
     t = P.tuning()
     assert t["us_per_step"] > 0 and t["index_bytes"] in (2, 4) and t["nt_loads"] in (0, 1)
+    assert t["gather_unroll"] in (2, 3, 4)
     y = P.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
     assert np.abs(y - ref).max() / np.abs(ref).max() <= tol
     for ib in (2, 4):
@@ -168,6 +169,29 @@ def test_autotuned_and_cached_load_variants_match_oracle(precision):
             assert Q.tuning()["nt_loads"] == 0 and Q.tuning()["us_per_step"] == 0
             y = Q.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
             assert np.abs(y - ref).max() / np.abs(ref).max() <= tol, (ib, remap)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim,n", [(2, 37), (3, 13)])
+@pytest.mark.parametrize("unroll", [2, 3, 4])
+def test_gather_unroll_variants_match_oracle(precision, dim, n, unroll):
+    """Each unroll factor of the single-vector step's loop over a slice's
+    entries (2D rows hold up to 7 entries, 3D rows up to 15; both grids end in
+    a ragged slice) computes the same operator C."""
+    import torch
+
+    kf = _kf()
+    S, m, tau, _, omin, omax = _case(dim, n)
+    L = 8
+    w = oracle.discrete_weights(omin, omax, tau, L)
+    X = start_block(S.shape[0], 1, 23)
+    ref = oracle.apply_filter(S, m, tau, w, X)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    print(f"case gather_unroll={unroll} precision={precision} dim={dim} n={n}", flush=True)
+    P = kf.Problem(S, m, omin, omax, tau, L, precision=precision, gather_unroll=unroll)
+    assert P.tuning()["gather_unroll"] == unroll
+    y = P.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.abs(y - ref).max() / np.abs(ref).max() <= tol
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
