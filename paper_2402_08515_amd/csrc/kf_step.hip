@@ -347,10 +347,12 @@ int launch_lf_bu(const SellOp& A, int mode, const void* cur, const void* prev, v
 template <typename T, typename IT, int B, int LPR>
 int launch_lf_bl(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
-  if (B == 1 && A.unroll == 2)
-    return launch_lf_bu<T, IT, B, LPR, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
-  if (B == 1 && A.unroll == 3)
-    return launch_lf_bu<T, IT, B, LPR, 3>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  if constexpr (B == 1) {
+    if (A.unroll == 2)
+      return launch_lf_bu<T, IT, B, LPR, 2>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    if (A.unroll == 3)
+      return launch_lf_bu<T, IT, B, LPR, 3>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  }
   return launch_lf_bu<T, IT, B, LPR, 4>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
 }
 
