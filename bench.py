@@ -483,7 +483,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gather-unroll", type=int, default=0,
-                    help="single vectors: unroll factor of the fused step's loop over a slice (0 = autotuned)")
+                    help="single vectors: unroll factor (2, 3, 4 or 6) of the fused step's loop over a slice "
+                         "(0 = autotuned)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-step variant instead of timing all of them at set-up")
     ap.add_argument("--batch-count", type=int, default=64)

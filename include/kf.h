@@ -134,8 +134,8 @@ typedef struct kf_options {
   int32_t autotune;      /* 1: kf_create times the fused step with every
                             combination of xcd_remap, nt_loads and (when both
                             fit) 2- and 4-byte column indices and keeps the
-                            fastest, then gather_unroll 2, 3 and 4 when it is
-                            0 (kf_get_tuning reports the choice); blocks of
+                            fastest, then gather_unroll 2, 3, 4 and 6 when it
+                            is 0 (kf_get_tuning reports the choice); blocks of
                             b > 1 vectors also get lanes_per_row timed on
                             first use */
   int32_t batch_workers; /* batches: host threads that drive the members'
@@ -146,10 +146,10 @@ typedef struct kf_options {
   int32_t lanes_per_row; /* lanes of a wavefront sharing one row in the fused
                             step for b > 1 (1, 2 or 4, capped at b); 0 =
                             16 bytes of the block row per lane */
-  int32_t gather_unroll; /* single vectors: unroll factor (2, 3 or 4) of the
-                            fused step's loop over the stored entries of a
-                            row slice; 0 = timed by the autotuner (4 without
-                            it).  Other values: KF_EINVAL */
+  int32_t gather_unroll; /* single vectors: unroll factor (2, 3, 4 or 6) of
+                            the fused step's loop over the stored entries of
+                            a row slice; 0 = timed by the autotuner (4
+                            without it).  Other values: KF_EINVAL */
   void* stream;          /* hipStream_t */
 } kf_options;
 

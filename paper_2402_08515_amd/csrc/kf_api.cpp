@@ -1101,7 +1101,7 @@ int autotune(kf_problem* p, DevCsr& dc, const double* d_scale) {
   // used by the refinement has the same slices and takes the same factor
   if (p->opt.gather_unroll == 0) {
     int best_u = 4;
-    for (int u = 2; u <= 4; ++u) {
+    for (int u : {2, 3, 4, 6}) {
       p->A.unroll = u;
       double us = 0;
       KF_TRY(time_variant(p, p->A, p->sb, best_remap, 20, &us));
@@ -1207,8 +1207,9 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.proj_every < 1) o.proj_every = 1;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 1 && o.lanes_per_row != 2 && o.lanes_per_row != 4)
     return fail(KF_EINVAL, "kf_create: lanes_per_row must be 0, 1, 2 or 4");
-  if (o.gather_unroll != 0 && (o.gather_unroll < 2 || o.gather_unroll > 4))
-    return fail(KF_EINVAL, "kf_create: gather_unroll must be 0, 2, 3 or 4");
+  if (o.gather_unroll != 0 && o.gather_unroll != 2 && o.gather_unroll != 3 && o.gather_unroll != 4 &&
+      o.gather_unroll != 6)
+    return fail(KF_EINVAL, "kf_create: gather_unroll must be 0, 2, 3, 4 or 6");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 

@@ -48,7 +48,7 @@ struct SellOp {
   int nt_loads = 0;  // 1: stream the matrix with non-temporal loads in the fused step
   int lpr[5] = {0, 0, 0, 0, 0};  // lanes per row of the fused step for blocks 1..16 (0: default)
   int lpr_tuned = 0;             // bit l: lpr[l] was chosen by timing
-  int unroll = 0;                // single vectors: unroll of the loop over a slice's entries (2, 3, 4; 0: 4)
+  int unroll = 0;                // single vectors: unroll of the loop over a slice's entries (2, 3, 4, 6; 0: 4)
 };
 
 // Lanes that share one row in the fused step for block width b.

@@ -92,6 +92,7 @@ def test_create_rejects_bad_parameters(small):
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, lanes_per_row=3))
     assert "gather_unroll" in _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, gather_unroll=1))
     _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, gather_unroll=5))
+    _expect_einval(lambda: kf.Problem(S, m, 1.0, 2.0, 0.01, 10, gather_unroll=8))
 
 
 def test_default_options_fill_the_bindings_structure():
