@@ -136,8 +136,8 @@ typedef struct kf_options {
                             fit) 2- and 4-byte column indices and keeps the
                             fastest, then gather_unroll 2, 3, 4 and 6 when it
                             is 0 (kf_get_tuning reports the choice); blocks of
-                            b > 1 vectors also get lanes_per_row timed on
-                            first use */
+                            b > 1 vectors also get lanes_per_row and
+                            block_band timed on first use */
   int32_t batch_workers; /* batches: host threads that drive the members'
                             Gram-Schmidt and Rayleigh-Ritz between two batched
                             filter launches, each member on a stream of its
@@ -150,6 +150,14 @@ typedef struct kf_options {
                             the fused step's loop over the stored entries of
                             a row slice; 0 = timed by the autotuner (4
                             without it).  Other values: KF_EINVAL */
+  int32_t block_band;    /* blocks (b > 1): 1 = each workgroup of the fused
+                            step first copies its rows of the current block,
+                            and the rows within the operator's largest
+                            |col - row| of them, into LDS and gathers from
+                            there, whenever that copy fits in 64 KB; -1 =
+                            gathers from the caches; 0 = timed with
+                            lanes_per_row when autotune is on (else from the
+                            caches).  Other values: KF_EINVAL */
   void* stream;          /* hipStream_t */
 } kf_options;
 

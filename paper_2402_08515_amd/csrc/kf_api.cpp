@@ -1045,17 +1045,26 @@ int tune_block(kf_problem* p, SellOp& A, StepBufs& sb, int bk) {
   while ((1 << lb) < bk && lb < 4) ++lb;
   if (A.lpr_tuned & (1 << lb)) return KF_OK;
   double best = 1e300;
-  int best_l = 1;
+  int best_l = 1, best_b = 0;
+  // lanes per row, each with the gathers from the caches and (unless the
+  // caller fixed it, and where the band copy fits) from LDS
+  const bool try_band = p->opt.block_band == 0;
   for (int l = 1; l <= std::min(bk, 4); l *= 2) {
-    A.lpr[lb] = l;
-    double us = 0.0;
-    KF_TRY(time_variant(p, A, sb, p->opt.xcd_remap, 10, &us, bk));
-    if (us < best) {
-      best = us;
-      best_l = l;
+    for (int band = 0; band <= 1; ++band) {
+      if (band && (!try_band || band_lds_bytes(A, bk, l) > kBandLdsBytes)) continue;
+      A.lpr[lb] = l;
+      A.band[lb] = try_band ? band : A.band[lb];
+      double us = 0.0;
+      KF_TRY(time_variant(p, A, sb, p->opt.xcd_remap, 10, &us, bk));
+      if (us < best) {
+        best = us;
+        best_l = l;
+        best_b = A.band[lb];
+      }
     }
   }
   A.lpr[lb] = best_l;
+  A.band[lb] = best_b;
   A.lpr_tuned |= 1 << lb;
   return KF_OK;
 }
@@ -1164,6 +1173,7 @@ void kf_default_options(kf_options* o) {
   o->autotune = 0;
   o->lanes_per_row = 0;
   o->gather_unroll = 0;
+  o->block_band = 0;
   o->batch_workers = 0;
   o->stream = nullptr;
 }
@@ -1210,6 +1220,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.gather_unroll != 0 && o.gather_unroll != 2 && o.gather_unroll != 3 && o.gather_unroll != 4 &&
       o.gather_unroll != 6)
     return fail(KF_EINVAL, "kf_create: gather_unroll must be 0, 2, 3, 4 or 6");
+  if (o.block_band < -1 || o.block_band > 1) return fail(KF_EINVAL, "kf_create: block_band must be -1, 0 or 1");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 
@@ -1257,6 +1268,7 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     p->A.nt_loads = o.nt_loads ? 1 : 0;
     p->A64.nt_loads = p->A.nt_loads;
     p->A.unroll = p->A64.unroll = o.gather_unroll;
+    for (int l = 0; l < 5; ++l) p->A.band[l] = p->A64.band[l] = o.block_band == 1 ? 1 : 0;
     for (hipEvent_t& e : p->ev)
       if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
     if (!rc && o.autotune) rc = autotune(p, dc, d_scale);

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include <string>
@@ -49,7 +51,26 @@ struct SellOp {
   int lpr[5] = {0, 0, 0, 0, 0};  // lanes per row of the fused step for blocks 1..16 (0: default)
   int lpr_tuned = 0;             // bit l: lpr[l] was chosen by timing
   int unroll = 0;                // single vectors: unroll of the loop over a slice's entries (2, 3, 4, 6; 0: 4)
+  int32_t max_off = 0;           // largest |col - row| of a stored entry
+  int band[5] = {0, 0, 0, 0, 0}; // blocks 2..16: 1 = gather from an LDS copy of the workgroup's band of rows
 };
+
+// LDS available to the band copy of one workgroup of the fused step.
+constexpr size_t kBandLdsBytes = 65536;
+
+// Bytes of the band copy for block width b with lpr lanes per row: the
+// workgroup's 4 * 64 / lpr rows and max_off rows on either side.
+inline size_t band_lds_bytes(const SellOp& A, int b, int lpr) {
+  const int64_t rows = std::min<int64_t>((int64_t)A.n, 4 * (64 / lpr) + 2 * (int64_t)A.max_off);
+  return (size_t)rows * b * A.val_bytes;
+}
+
+// Whether the fused step for block width b gathers from the LDS band copy.
+inline bool use_band(const SellOp& A, int b, int lpr) {
+  int lb = 0;
+  while ((1 << lb) < b && lb < 4) ++lb;
+  return b > 1 && A.band[lb] == 1 && band_lds_bytes(A, b, lpr) <= kBandLdsBytes;
+}
 
 // Lanes that share one row in the fused step for block width b.
 int lanes_per_row(const SellOp& A, int b);

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -105,18 +107,39 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, int32_t nslices, c
 // the gather of a neighbour's block row is LPR adjacent 16-byte pieces (LPR = 1:
 // one lane per row with the whole block row in registers).  U: unroll factor
 // of the loop over the slice's stored entries.
-template <typename T, typename IT, int B, int MODE, bool NT, int LPR, int U>
+// BAND (blocks): every column a row gathers lies within moff rows of it, so
+// the workgroup first copies the rows [r0 - moff, r0 + 4 RW + moff) of `cur`
+// (its own 4 RW rows and their neighbours; one contiguous, coalesced stretch)
+// into LDS and gathers from there; the caller checks that the stretch fits.
+template <typename T, typename IT, int B, int MODE, bool NT, int LPR, int U, bool BAND>
 __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
                                                   const T* __restrict__ val, const IT* __restrict__ idx,
                                                   const T* __restrict__ cur, const T* prev, T* out,
                                                   T* __restrict__ acc, double* __restrict__ rout, int64_t rs,
-                                                  int64_t cs, int bout, T wp, T wc, T wn, int remap) {
+                                                  int64_t cs, int bout, T wp, T wc, T wn, int remap, int moff) {
   constexpr bool relative = sizeof(IT) == 2;
   constexpr int BL = B / LPR;   // vector columns per lane
   constexpr int RW = 64 / LPR;  // rows per wavefront
   const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int gw = wg * 4 + (threadIdx.x >> 6);  // global wavefront
   const int lane = threadIdx.x & 63;
+  extern __shared__ __align__(16) unsigned char band_raw[];
+  T* __restrict__ band = reinterpret_cast<T*>(band_raw);
+  int clo = 0;
+  if constexpr (BAND) {
+    // every thread takes part in the copy and the barrier before any returns
+    const int rlo = wg * 4 * RW;
+    clo = max(0, rlo - moff);
+    const int chi = min(n, rlo + 4 * RW + moff);
+    constexpr int VB = (B * sizeof(T)) % 16 == 0 ? 16 : ((B * sizeof(T)) % 8 == 0 ? 8 : 4);
+    using V = typename std::conditional<VB == 16, int4, typename std::conditional<VB == 8, int2, int>::type>::type;
+    const int64_t nv = (int64_t)(chi - clo) * B * sizeof(T) / VB;
+    const V* __restrict__ src = reinterpret_cast<const V*>(cur + (int64_t)clo * B);
+    V* dst = reinterpret_cast<V*>(band_raw);
+    for (int64_t t = threadIdx.x; t < nv; t += blockDim.x) dst[t] = src[t];
+    __syncthreads();
+  }
+  const T* __restrict__ xsrc = BAND ? band : cur;  // gathered rows, indexed from row clo
   const int slice = (gw * RW) >> 6;
   if (slice >= nslices) return;
   const int rin = ((gw * RW) & 63) + lane / LPR;  // row within the slice
@@ -148,12 +171,12 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
     const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
     const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
     const int c = relative ? row + (int)ci : (int)ci;
-    const Row<T, BL> x = *reinterpret_cast<const Row<T, BL>*>(cur + (int64_t)c * B + col0);
+    const Row<T, BL> x = *reinterpret_cast<const Row<T, BL>*>(xsrc + (int64_t)(c - clo) * B + col0);
 #pragma unroll
     for (int j = 0; j < BL; ++j) sum[j] = fma(a, x.v[j], sum[j]);
   }
   if (!early) {
-    yc = *reinterpret_cast<const Row<T, BL>*>(cur + off);
+    yc = *reinterpret_cast<const Row<T, BL>*>(xsrc + (int64_t)(row - clo) * B + col0);
     if (!(MODE & kFirst)) yp = *reinterpret_cast<const Row<T, BL>*>(prev + off);
   }
   if (MODE & kFirst) yp = yc;
@@ -295,10 +318,11 @@ __global__ __launch_bounds__(256) void k_scale_copy(int32_t n, int b, int bsrc, 
 }
 
 // ---- host-side dispatch helpers
-template <typename T, typename IT, int B, bool NT, int LPR, int U>
+template <typename T, typename IT, int B, bool NT, int LPR, int U, bool BAND>
 int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
   const int grid = ceil_div64((int64_t)A.nslices * LPR, 4);
+  const size_t lds = BAND ? band_lds_bytes(A, B, LPR) : 0;
   const T* v = static_cast<const T*>(A.val);
   const IT* ix = static_cast<const IT*>(A.idx);
   const T* c = static_cast<const T*>(cur);
@@ -307,37 +331,57 @@ int launch_lf_bn(const SellOp& A, int mode, const void* cur, const void* prev, v
   T* a = static_cast<T*>(acc);
   switch (mode) {
     case kMid:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMid, NT, LPR, U, BAND>), dim3(grid), dim3(256), lds, st, A.n,
+                         A.nslices, A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap,
+                         A.max_off);
       break;
     case kFirst:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirst, NT, LPR, U, BAND>), dim3(grid), dim3(256), lds, st, A.n,
+                         A.nslices, A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap,
+                         A.max_off);
       break;
     case kMidAcc:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMidAcc, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kMidAcc, NT, LPR, U, BAND>), dim3(grid), dim3(256), lds, st, A.n,
+                         A.nslices, A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap,
+                         A.max_off);
       break;
     case kLast:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kLast, NT, LPR, U, BAND>), dim3(grid), dim3(256), lds, st, A.n,
+                         A.nslices, A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap,
+                         A.max_off);
       break;
     default:
-      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR, U>), dim3(grid), dim3(256), 0, st, A.n, A.nslices,
-                         A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap);
+      hipLaunchKernelGGL((k_leapfrog<T, IT, B, kFirstLast, NT, LPR, U, BAND>), dim3(grid), dim3(256), lds, st, A.n,
+                         A.nslices, A.slice_ptr, v, ix, c, p, o, a, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap,
+                         A.max_off);
       break;
   }
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
 
+template <typename T, typename IT, int B, int LPR, int U, bool BAND>
+int launch_lf_bs(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
+                 int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
+  if (A.nt_loads)
+    return launch_lf_bn<T, IT, B, true, LPR, U, BAND>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn,
+                                                      remap, st);
+  return launch_lf_bn<T, IT, B, false, LPR, U, BAND>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn,
+                                                     remap, st);
+}
+
+// Blocks gather from an LDS copy of the workgroup's band of rows when the
+// operator chose it for this block width and the band fits.
 template <typename T, typename IT, int B, int LPR, int U>
 int launch_lf_bu(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, double* rout,
                  int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap, hipStream_t st) {
-  if (A.nt_loads)
-    return launch_lf_bn<T, IT, B, true, LPR, U>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap,
-                                                st);
-  return launch_lf_bn<T, IT, B, false, LPR, U>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap, st);
+  if constexpr (B > 1) {
+    if (use_band(A, B, LPR))
+      return launch_lf_bs<T, IT, B, LPR, U, true>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap,
+                                                  st);
+  }
+  return launch_lf_bs<T, IT, B, LPR, U, false>(A, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, remap,
+                                               st);
 }
 
 // The loop over a slice's entries is unrolled four times for blocks; for
@@ -444,6 +488,7 @@ int build_sell(int32_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d
   out.idx_bytes = ib;
   out.val_bytes = val_bytes;
   out.max_width = maxw;
+  out.max_off = maxoff;
   if (hipMalloc(&out.slice_ptr, sizeof(int64_t) * (ns + 1)) != hipSuccess ||
       hipMalloc(&out.val, (size_t)tot * val_bytes) != hipSuccess ||
       hipMalloc(&out.idx, (size_t)tot * ib) != hipSuccess) {

@@ -62,6 +62,7 @@ class OptionsT(C.Structure):
         ("batch_workers", C.c_int32),
         ("lanes_per_row", C.c_int32),
         ("gather_unroll", C.c_int32),
+        ("block_band", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -283,7 +284,8 @@ def _take_result(res, n: int) -> SolveResult:
 
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=2, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
-             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0):
+             autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0,
+             block_band=0):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -305,6 +307,7 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
     opt.autotune = int(autotune)
     opt.lanes_per_row = int(lanes_per_row)
     opt.gather_unroll = int(gather_unroll)
+    opt.block_band = int(block_band)
     opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt

@@ -195,6 +195,31 @@ def test_gather_unroll_variants_match_oracle(precision, dim, n, unroll):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim,n", [(2, 37), (3, 13)])
+@pytest.mark.parametrize("b", [2, 4, 16])
+@pytest.mark.parametrize("lpr", [1, 2, 4])
+def test_lds_band_variants_match_oracle(precision, dim, n, b, lpr):
+    """Blocks gathering from the LDS copy of each workgroup's band of rows
+    (block_band = 1) compute the same operator C.  On the square every copy
+    fits in 64 KB; on the cube (offsets up to 144 rows) the float64 block of
+    16 with one lane per row does not, and those launches gather from the
+    caches instead."""
+    import torch
+
+    kf = _kf()
+    S, m, tau, _, omin, omax = _case(dim, n)
+    L = 8
+    w = oracle.discrete_weights(omin, omax, tau, L)
+    X = start_block(S.shape[0], b, 29)
+    ref = oracle.apply_filter(S, m, tau, w, X)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    print(f"case block_band precision={precision} dim={dim} n={n} b={b} lpr={lpr}", flush=True)
+    P = kf.Problem(S, m, omin, omax, tau, L, precision=precision, block_band=1, lanes_per_row=lpr)
+    y = P.apply_filter(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.abs(y - ref).max() / np.abs(ref).max() <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("b", [2, 4, 8, 16])
 @pytest.mark.parametrize("lpr", [1, 2, 4])
 def test_lanes_per_row_variants_match_oracle(precision, b, lpr):
