@@ -261,11 +261,11 @@ int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, doub
  * stream: returns after enqueueing. */
 int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b);
 
-/* Run the eigensolver from the host start block start[n x b] (row-major,
- * 1 <= b <= 16) until opt.target pairs are accepted (residual <= tol), the
- * basis reaches m_max columns, opt.max_iters filter applications, or
- * breakdown.  *out receives a library-owned result released with
- * kf_result_free.  Synchronous. */
+/* Run the eigensolver from the start block start[n x b] (row-major, in host
+ * or device memory, 1 <= b <= 16) until opt.target pairs are accepted
+ * (residual <= tol), the basis reaches m_max columns, opt.max_iters filter
+ * applications, or breakdown.  *out receives a library-owned result released
+ * with kf_result_free.  Synchronous. */
 int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol,
              kf_result** out);
 

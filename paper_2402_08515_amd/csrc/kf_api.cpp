@@ -1563,8 +1563,6 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   if (m_max < b) return fail(KF_EINVAL, "kf_solve: m_max must be >= b");
   if (m_max > 2048) return fail(KF_EINVAL, "kf_solve: m_max must be <= 2048");
   if (!(tol > 0)) return fail(KF_EINVAL, "kf_solve: tol must be positive");
-  for (int64_t i = 0; i < (int64_t)p->n * b; ++i)
-    if (!std::isfinite(start[i])) return fail(KF_EINVAL, "kf_solve: non-finite start block");
   s.b = b;
   s.bk = pow2ceil(b);
   s.m_max = m_max;
@@ -1577,8 +1575,21 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   KF_TRY(ensure_basis(p, m_max + s.bk));
   KF_TRY(ensure_misc(p));
   const int32_t n = p->n;
-  // start block: host row-major -> V (scratch) -> B[:, 0:b] column-major
-  KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyHostToDevice, st));
+  // start block: row-major in host or device memory (the runtime tells them
+  // apart) -> V (scratch), checked there for non-finite entries (on the
+  // device, so a device block is never read by the host) -> B[:, 0:b]
+  KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyDefault, st));
+  {
+    int32_t* fin = p->flags + 48;
+    int32_t hf = 0;
+    KF_HIP(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+    KF_TRY(nonfinite_flag((int64_t)n * b, p->V, fin, st));
+    Readback rb(p);
+    KF_TRY(rb.get(&hf, fin, sizeof(int32_t)));
+    KF_HIP(hipStreamSynchronize(st));
+    rb.land();
+    if (hf) return fail(KF_EINVAL, "kf_solve: non-finite start block");
+  }
   KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, p->ldb, st));
   int kept = 0;
   KF_HIP(hipEventRecord(p->ev[1], st));

@@ -753,6 +753,15 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   return KF_OK;
 }
 
+// *flag = 1 when some x[i] (i < cnt) is not finite (the caller clears it).
+__global__ __launch_bounds__(256) void k_nonfinite_flag(int64_t cnt, const double* __restrict__ x,
+                                                        int32_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) *flag = 1;
+}
+
 // The gate of the selective full subtraction: one workgroup, max |c_j|.
 __global__ __launch_bounds__(256) void k_reorth_gate(int k, const double* __restrict__ c, const double* __restrict__ g,
                                                      double tol, int32_t* __restrict__ gate) {
@@ -821,6 +830,14 @@ int pair_coef(int kb, const double* c_last, const double* cx, double* out, int64
               hipStream_t st) {
   if (kb <= 0) return KF_OK;
   hipLaunchKernelGGL(k_pair_coef, dim3(1), dim3(256), 0, st, kb, c_last, cx, out, ldo, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int nonfinite_flag(int64_t cnt, const double* x, int32_t* flag, hipStream_t st) {
+  if (cnt <= 0) return KF_OK;
+  const int grid = (int)std::min<int64_t>(1024, ceil_div64(cnt, 256));
+  hipLaunchKernelGGL(k_nonfinite_flag, dim3(grid), dim3(256), 0, st, cnt, x, flag);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

@@ -175,6 +175,10 @@ int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H,
 // entry of basis column p0 + c by more than tol (device values)
 int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, int32_t* flag, hipStream_t st);
 
+// *flag = 1 if some x[i] (i < cnt, device) is not finite; the caller clears
+// *flag beforehand
+int nonfinite_flag(int64_t cnt, const double* x, int32_t* flag, hipStream_t st);
+
 // *gate = 1 if max_j |c[j]| (j < k) > tol * sqrt(*g), else 0 (device values)
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st);
 

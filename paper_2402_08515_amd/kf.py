@@ -15,7 +15,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-import torch  # noqa: F401  (load torch's HIP runtime before libkf.so)
+import torch  # loads torch's HIP runtime before libkf.so; device start blocks
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkf.so")
@@ -431,11 +431,19 @@ class Problem:
         return y
 
     def solve(self, start, m_max: int, tol: float) -> SolveResult:
-        V0 = np.ascontiguousarray(start, dtype=np.float64)
-        if V0.ndim == 1:
-            V0 = V0[:, None]
+        """start: n x b float64 block, a host array or a contiguous CUDA tensor."""
+        if isinstance(start, torch.Tensor) and start.is_cuda:
+            V0 = start if start.dim() == 2 else start[:, None]
+            if V0.dtype != torch.float64 or not V0.is_contiguous() or V0.shape[0] != self.n:
+                raise ValueError("start must be a contiguous float64 tensor with n rows")
+            ptr, b = V0.data_ptr(), int(V0.shape[1])
+        else:
+            V0 = np.ascontiguousarray(start, dtype=np.float64)
+            if V0.ndim == 1:
+                V0 = V0[:, None]
+            ptr, b = _ptr(V0), int(V0.shape[1])
         res = C.POINTER(ResultT)()
-        _check(lib().kf_solve(self._h, _ptr(V0), int(V0.shape[1]), int(m_max), float(tol), C.byref(res)))
+        _check(lib().kf_solve(self._h, ptr, b, int(m_max), float(tol), C.byref(res)))
         return _take_result(res, self.n)
 
     def basis(self, max_cols: int) -> np.ndarray:

@@ -138,6 +138,26 @@ def test_breakdown_on_exact_eigenvector():
     assert got.omega2.size == 1 and got.omega2[0] == pytest.approx(mu[1] + mu[2], rel=1e-12)
 
 
+def test_device_start_block_equals_host_start_block(grid2d):
+    """The start block may live in device memory: same result as from host
+    memory, bit for bit; non-finite entries are rejected from either."""
+    import torch
+
+    kf = _kf()
+    P, tau, L, w, V0, ref = grid2d
+    print("case device start block grid2d_64", flush=True)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L)
+    a = prob.solve(V0, m_max=40, tol=1e-9)
+    d = prob.solve(torch.from_numpy(V0).cuda(), m_max=40, tol=1e-9)
+    assert np.array_equal(a.omega2, d.omega2) and np.array_equal(a.residual, d.residual)
+    bad = V0.copy()
+    bad[5, 0] = np.nan
+    for start in (bad, torch.from_numpy(bad).cuda()):
+        with pytest.raises(kf.KfError) as ei:
+            prob.solve(start, m_max=40, tol=1e-9)
+        assert ei.value.code == kf.KF_EINVAL and "non-finite" in str(ei.value)
+
+
 def test_interval_without_eigenvalues_returns_no_pairs():
     """An interval inside a gap of the spectrum: the solve ends at m_max with
     no accepted pair and no error, as the oracle does."""
