@@ -234,6 +234,9 @@ def bench_horn(args):
                       check_growth=args.check_growth, max_iters=args.horn_iters, autotune=not args.no_autotune)
     tuning = prob.tuning()
     V0d = torch.from_numpy(V0).cuda()  # inputs resident in HBM before the timed region
+    # set-up outside the timed region: the block width's step variant (lanes
+    # per row, LDS band copy) is timed on its first use
+    prob.apply_filter(V0d)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = prob.solve(V0d, m_max=args.m_max, tol=args.tol)
