@@ -127,7 +127,11 @@ constexpr size_t kPinBytes = (size_t)64 << 10;  // pinned staging for per-step r
 constexpr int kSmall = 4096;
 // offsets of the device scalars in kf_problem::small used by the
 // orthogonalisation (the Rayleigh-Ritz check uses 1024.. and 2048..)
-constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kRec = 2560, kOne = 4095;
+constexpr int kPost = 256, kNrm2 = 512, kG2 = 768, kT1 = 1100, kRec = 2560, kRinv = 3072, kOne = 4095;
+// a block is orthonormalised by Cholesky QR (twice) when every pivot keeps at
+// least this fraction of its column's squared M-norm; otherwise column by
+// column (classical Gram-Schmidt twice, with the drop test)
+constexpr double kCholPivot = 1e-8;
 // mixed mode: refinements tried before a solve with a target gives up
 constexpr int kMaxRefines = 4;
 // columns projected only every proj_every steps must be M-orthogonal to the
@@ -613,7 +617,35 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     for (int j = 0; j < nb; ++j)
       if (hg2[(size_t)j * nb + j] < 0.25 * hg1[(size_t)kb + j + (size_t)j * ldc]) again = true;
     if (again) KF_TRY(full_pass(false));
-    KF_TRY(finish_cols(Tref, ld1));
+    // within the block: Cholesky QR twice (four launches per pass, and no
+    // column can be dropped: the full pass kept >= 1/4 of every norm and each
+    // pivot keeps >= kCholPivot of its column) when the Gram matrix after the
+    // full pass is well conditioned, else column by column; the pivots are
+    // checked on the copy of G read back for the second-pass test above
+    bool chol = !again;
+    std::vector<double> R((size_t)nb * nb, 0.0);  // upper triangle, column-major
+    for (int j = 0; chol && j < nb; ++j) {
+      double d = hg2[(size_t)j + (size_t)j * nb];
+      for (int i = 0; i < j; ++i) {
+        double t = hg2[(size_t)i + (size_t)j * nb];
+        for (int q = 0; q < i; ++q) t -= R[(size_t)q + (size_t)i * nb] * R[(size_t)q + (size_t)j * nb];
+        t /= R[(size_t)i + (size_t)i * nb];
+        R[(size_t)i + (size_t)j * nb] = t;
+        d -= t * t;
+      }
+      if (!std::isfinite(d) || !(d >= kCholPivot * hg2[(size_t)j + (size_t)j * nb]))
+        chol = false;
+      else
+        R[(size_t)j + (size_t)j * nb] = std::sqrt(d);
+    }
+    if (chol) {
+      double* Rinv = p->small + kRinv;
+      KF_TRY(chol_orthonormalise(n, nb, X, ldb, g2, Rinv, p->flags, post, st));
+      KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+      KF_TRY(chol_orthonormalise(n, nb, X, ldb, g2, Rinv, p->flags, post, st));
+    } else {
+      KF_TRY(finish_cols(Tref, ld1));
+    }
     if (done) KF_HIP(hipEventRecord(done, st));
   } else {
     KF_TRY(finish_cols(Tref, ld1));

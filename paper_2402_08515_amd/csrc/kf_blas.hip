@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -753,6 +755,61 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   return KF_OK;
 }
 
+// Cholesky factor R of a block's Gram matrix G = X^T M X (nb x nb, nb <= 16,
+// leading dimension nb, upper triangle used) and Rinv = R^{-1} (column-major,
+// upper triangular), so that X Rinv is M-orthonormal; flags[j] = 1 and
+// post[j] = R_jj.  One thread: order at most 16.
+__global__ __launch_bounds__(64) void k_chol_inv(int nb, const double* __restrict__ G, double* __restrict__ Rinv,
+                                                 int32_t* __restrict__ flags, double* __restrict__ post) {
+  __shared__ double R[16][16], Ri[16][16];
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j < nb; ++j) {
+    double s = G[j + j * nb];
+    for (int i = 0; i < j; ++i) s -= R[i][j] * R[i][j];
+    const double rjj = sqrt(fmax(s, DBL_MIN));
+    R[j][j] = rjj;
+    for (int k = j + 1; k < nb; ++k) {
+      double t = G[j + k * nb];
+      for (int i = 0; i < j; ++i) t -= R[i][j] * R[i][k];
+      R[j][k] = t / rjj;
+    }
+    flags[j] = 1;
+    post[j] = rjj;
+  }
+  for (int k = 0; k < nb; ++k) {
+    Ri[k][k] = 1.0 / R[k][k];
+    for (int j = k - 1; j >= 0; --j) {
+      double t = 0.0;
+      for (int i = j + 1; i <= k; ++i) t += R[j][i] * Ri[i][k];
+      Ri[j][k] = -t / R[j][j];
+    }
+  }
+  for (int k = 0; k < nb; ++k)
+    for (int j = 0; j < nb; ++j) Rinv[j + k * nb] = j <= k ? Ri[j][k] : 0.0;
+}
+
+// X <- X Rinv in place (Rinv nb x nb upper triangular, nb <= 16): each thread
+// reads its row of the block, then writes the transformed row.
+__global__ __launch_bounds__(256) void k_apply_upper(int32_t n, int nb, double* __restrict__ X, int64_t ldx,
+                                                     const double* __restrict__ Rinv) {
+  __shared__ double ri[256];
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) ri[t] = Rinv[t];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = c < nb ? X[i + c * ldx] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k >= nb) break;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c <= k; ++c) s = fma(x[c], ri[c + k * nb], s);
+    X[i + k * ldx] = s;
+  }
+}
+
 // *flag = 1 when some x[i] (i < cnt) is not finite (the caller clears it).
 __global__ __launch_bounds__(256) void k_nonfinite_flag(int64_t cnt, const double* __restrict__ x,
                                                         int32_t* __restrict__ flag) {
@@ -830,6 +887,19 @@ int pair_coef(int kb, const double* c_last, const double* cx, double* out, int64
               hipStream_t st) {
   if (kb <= 0) return KF_OK;
   hipLaunchKernelGGL(k_pair_coef, dim3(1), dim3(256), 0, st, kb, c_last, cx, out, ldo, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int chol_orthonormalise(int32_t n, int nb, double* X, int64_t ldx, const double* G, double* Rinv, int32_t* flags,
+                        double* post, hipStream_t st) {
+  if (nb < 1 || nb > 16) {
+    set_error("chol_orthonormalise: block width must lie in [1, 16]");
+    return KF_EINVAL;
+  }
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, st, nb, G, Rinv, flags, post);
+  KF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_apply_upper, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, nb, X, ldx, Rinv);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

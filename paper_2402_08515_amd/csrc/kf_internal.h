@@ -175,6 +175,13 @@ int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H,
 // entry of basis column p0 + c by more than tol (device values)
 int block_gate(int k, int p0, int np, const double* G, int64_t ldg, double tol, int32_t* flag, hipStream_t st);
 
+// X <- X R^{-1} with R the Cholesky factor of G = X^T M X (device, nb x nb,
+// nb <= 16, leading dimension nb): one pass of Cholesky QR in the M inner
+// product; Rinv (nb x nb, device) receives R^{-1}, flags[0..nb) = 1 and
+// post[j] = R_jj.  The caller makes sure G is well conditioned.
+int chol_orthonormalise(int32_t n, int nb, double* X, int64_t ldx, const double* G, double* Rinv, int32_t* flags,
+                        double* post, hipStream_t st);
+
 // *flag = 1 if some x[i] (i < cnt, device) is not finite; the caller clears
 // *flag beforehand
 int nonfinite_flag(int64_t cnt, const double* x, int32_t* flag, hipStream_t st);
