@@ -633,7 +633,9 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
         R[(size_t)i + (size_t)j * nb] = t;
         d -= t * t;
       }
-      if (!std::isfinite(d) || !(d >= kCholPivot * hg2[(size_t)j + (size_t)j * nb]))
+      // (a zero column, e.g. the padding of a block of b < bk filtered
+      // columns, has d = 0 and must be dropped: the column path does that)
+      if (!std::isfinite(d) || !(d > 0.0) || !(d >= kCholPivot * hg2[(size_t)j + (size_t)j * nb]))
         chol = false;
       else
         R[(size_t)j + (size_t)j * nb] = std::sqrt(d);

@@ -112,6 +112,11 @@ def test_block_start_recovers_multiplicities(b):
     assert got.omega2.size == tgt == ref.omega2.size
     np.testing.assert_allclose(got.omega2, expect, rtol=1e-10)
     np.testing.assert_allclose(got.omega2, ref.omega2, rtol=1e-10)
+    # b = 3 runs in blocks of 4 whose fourth column is zero: it must be dropped
+    # (the basis stays M-orthonormal and grows by at most b per step after the
+    # start block)
+    assert got.orth_error < 1e-8
+    assert got.basis_size <= b * (got.krylov_steps + 1)
 
 
 def test_unstructured_neumann_matches_oracle():
