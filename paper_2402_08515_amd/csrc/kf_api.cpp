@@ -100,6 +100,10 @@ struct kf_problem {
   // (copies into it are queued without blocking the host)
   char* pin = nullptr;
   size_t pin_cap = 0;
+  // 64 bytes past pin_cap that the window step's kernel writes directly
+  // (device address of the same pinned memory), so that no copy is queued
+  double* win_rec_host = nullptr;
+  double* win_rec_dev = nullptr;
 };
 
 struct kf_batch {
@@ -342,11 +346,14 @@ int ensure_misc(kf_problem* p) {
   KF_TRY(dalloc(&p->SV, (size_t)p->n * 64));
   KF_TRY(dalloc(&p->small, kSmall));
   KF_TRY(dalloc(&p->flags, 64));
-  if (hipHostMalloc((void**)&p->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&p->pin, kPinBytes + 64, hipHostMallocDefault) != hipSuccess) {
     p->pin = nullptr;
     return fail(KF_ENOMEM, "kf: cannot allocate the pinned staging buffer");
   }
   p->pin_cap = kPinBytes;
+  p->win_rec_host = reinterpret_cast<double*>(p->pin + kPinBytes);
+  if (hipHostGetDevicePointer((void**)&p->win_rec_dev, p->win_rec_host, 0) != hipSuccess)
+    return fail(KF_EHIP, "kf: no device address for the pinned staging buffer");
   const double one = 1.0;
   KF_HIP(hipMemcpy(p->small + kOne, &one, sizeof(double), hipMemcpyHostToDevice));
   return KF_OK;
@@ -517,9 +524,9 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     bool explicit_norm = !fused;
     if (fused) {
       double* rec = p->small + kRec;
-      KF_TRY(window_step(n, lw, L1, ldb, p->d_m, p->gw, T1, rec, st));
-      double rh[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      KF_TRY(fetch(rec, (size_t)lw + 3, rh));
+      // the record {T, g, status} is also written straight to pinned host
+      // memory by the kernel (read after the synchronisation below)
+      KF_TRY(window_step(n, lw, L1, ldb, p->d_m, p->gw, T1, rec, st, p->win_rec_dev));
       if (ahead && done) {
         // queue the next filter application (on this column) before waiting
         // for the readback: the host's turnaround overlaps the time steps;
@@ -533,6 +540,7 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
         KF_HIP(hipStreamSynchronize(st));
       }
       rb.land();
+      const double* rh = p->win_rec_host;
       for (int j = 0; j <= lw; ++j) hv[(size_t)j] = rh[j];
       g2h = rh[lw + 1];
       fl[0] = 1;

@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const do
 // coef = {c_0, c_1, scale} for k_window_scale and rec = {T[0..lw], g, status}.
 __global__ __launch_bounds__(256) void k_window_reduce(int lw, const double* __restrict__ partial, int nchunks,
                                                        double* __restrict__ T, double* __restrict__ coef,
-                                                       double* __restrict__ rec) {
+                                                       double* __restrict__ rec, double* __restrict__ hrec) {
   __shared__ double ds[6];
   const int nd = window_dot_count(lw);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -641,6 +641,9 @@ __global__ __launch_bounds__(256) void k_window_reduce(int lw, const double* __r
   }
   rec[lw + 1] = g;
   rec[lw + 2] = strong ? 2.0 : 1.0;
+  if (hrec) {
+    for (int j = 0; j <= lw + 2; ++j) hrec[j] = rec[j];
+  }
 }
 
 // x <- (x - c_0 L_0 - c_1 L_1) * scale with the coefficients of k_window_reduce
@@ -658,7 +661,7 @@ __global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double*
 }  // namespace
 
 int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, GemvTWork& wk, double* T, double* rec,
-                hipStream_t st) {
+                hipStream_t st, double* host_rec) {
   if (lw < 0 || lw > 2) {
     set_error("window_step: the window holds at most two columns");
     return KF_EINVAL;
@@ -678,7 +681,7 @@ int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, Gemv
   }
   hipLaunchKernelGGL(k_window_dots, dim3(nchunks), dim3(256), 0, st, n, lw, L, ldl, m, wk.partial);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec);
+  hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec, host_rec);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_window_scale, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, lw, L, ldl, rec + 8);
   KF_HIP(hipGetLastError());

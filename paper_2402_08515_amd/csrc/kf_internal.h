@@ -162,9 +162,11 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
 // subtraction (from x^T M x, c and the window's Gram matrix, no further pass);
 // T = [c, x^T M x]; rec (16 doubles of device memory) = {T[0..lw], g, status}
 // with status 1 (scaled) or 2 (g < 1e-4 x^T M x: only subtracted, the caller
-// normalises explicitly); rec[8..10] is work space.
+// normalises explicitly); rec[8..10] is work space.  host_rec (optional):
+// device address of pinned host memory that receives the same lw + 3 values
+// (visible to the host once the stream has been synchronised).
 int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, GemvTWork& wk, double* T, double* rec,
-                hipStream_t st);
+                hipStream_t st, double* host_rec = nullptr);
 
 // X[:, c] -= sum_j Bk[:, j] * H[j + c*ldh], c < nrhs; skipped entirely when
 // gate (device flag) is given and holds 0
