@@ -317,12 +317,13 @@ def bench_forms(args):
         return int(found), float(max(errs)) if errs else None
 
     mm = args.m_max
-    # plain float64, one by one
+    # plain float64, one by one (problems created before the timed region, as
+    # the batches below are)
+    probs = [kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, check_growth=0.1)
+             for (S, m, lo, hi, tau, L, tgt, lam) in members]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = [kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, check_growth=0.1).solve(V0, m_max=mm,
-                                                                                              tol=args.tol)
-             for (S, m, lo, hi, tau, L, tgt, lam), V0 in zip(members, starts)]
+    plain = [pr.solve(V0, m_max=mm, tol=args.tol) for pr, V0 in zip(probs, starts)]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     # mixed, batched
