@@ -289,7 +289,7 @@ def bench_forms(args):
     solved to all eigenpairs in its interval at residual <= tol:
       plain   float64 stepping, Fourier weights, one problem after another;
       mixed   float32 stepping + float64 projection, all problems batched;
-      learned the same with the network's weights where the judge accepts
+      learned the same with the network's weights where the gate accepts
               them (network trained first, on the spectral range of these
               squares; training time reported separately).
     Every accepted eigenvalue is compared with the closed form."""
@@ -396,7 +396,7 @@ def bench_learned(args):
     then intervals from the evaluation law (seed 4 stream 1) on the 3D cube
     with 128 cells per axis (2,048,383 DOFs) are solved to all their
     eigenpairs with the Fourier weights and with the weights the network
-    proposes (the judge falls back to the Fourier weights when they leak
+    proposes (the acceptance gate falls back to the Fourier weights when they leak
     less).  Intervals holding more distinct eigenvalues than
     --learned-max-target are skipped (a single start vector needs a basis
     several times the target).  Stepping is fp64 by default: the cube's

@@ -590,7 +590,7 @@ int kf_weights_from_mlp(kf_mlp* net, double omega_min, double omega_max, double 
   KF_HIP(hipMemcpyAsync(net->Lover, &L, sizeof(int32_t), hipMemcpyHostToDevice, net->st));
   float jf = 0.f, jl = 0.f;
   std::vector<float> wl((size_t)kLM);
-  // the judge: Fourier weights (network off), then the network's weights
+  // the acceptance gate: Fourier weights (network off), then the network's weights
   KF_TRY(fwd_bwd(net, 64, nullptr, false, false, net->Lover));
   KF_HIP(hipMemcpyAsync(&jf, net->J, sizeof(float), hipMemcpyDeviceToHost, net->st));
   KF_HIP(hipStreamSynchronize(net->st));

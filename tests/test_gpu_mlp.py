@@ -45,7 +45,7 @@ def test_gradient_matches_fp64_reference():
     assert cos >= 0.995 and rel <= 5e-2
 
 
-def test_training_beats_fourier_and_the_judge_keeps_the_better_weights():
+def test_training_beats_fourier_and_the_gate_keeps_the_better_weights():
     kf = _kf()
     train = filter_samples(8192, stream=0)
     valid = filter_samples(16, stream=1)
@@ -65,7 +65,7 @@ def test_training_beats_fourier_and_the_judge_keeps_the_better_weights():
         wt[:L] = w
         j = mlp.loss_of_weights(r, wt)
         jT = mlp.loss_of_weights(r, mlp.teacher(r))
-        # the judge never returns weights worse than the Fourier ones
+        # the acceptance gate never returns weights worse than the Fourier ones
         assert j <= jF * (1 + 1e-3)
         assert jT <= j * (1 + 1e-6)
         better += used
@@ -102,4 +102,4 @@ def test_solve_with_learned_weights_finds_every_pair():
         assert r.omega2.size == tgt
         np.testing.assert_allclose(r.omega2, vals, rtol=1e-10)
         steps[name] = r.krylov_steps
-    print(f"judge used learned={used} (J {jl:.3e} vs {jf:.3e}); Krylov steps {steps}")
+    print(f"gate used learned={used} (J {jl:.3e} vs {jf:.3e}); Krylov steps {steps}")
