@@ -163,6 +163,11 @@ typedef struct kf_options {
 
 typedef struct kf_problem kf_problem; /* opaque */
 
+/* Result of a solve.  The accepted pairs are the Ritz pairs of the projected
+ * pencil (Section 2.1, eq. projevp) whose omega lies in [omega_min,
+ * omega_max] and whose residual (Section 2.4, eq. res, taken relative to
+ * ||S v||_2) is at most tol; the stopping rule after eq. res.  Library-owned
+ * until kf_result_free; every array is host memory. */
 typedef struct kf_result {
   int64_t n;              /* DOFs */
   int32_t n_pairs;        /* accepted eigenpairs */
@@ -239,10 +244,15 @@ int kf_set_weights(kf_problem* p, const double* w, int32_t L);
 /* Copy the current L filter coefficients to the host array w_out[L]. */
 int kf_get_weights(const kf_problem* p, double* w_out);
 
-/* Largest eigenvalue estimate of M^{-1} S by `iters` power iterations from the
+/* Section 3.1.2 and Section 3.2: the stable time step comes from a power
+ * iteration and the CFL condition of eq. 2stepmethod.
+ * Largest eigenvalue estimate of M^{-1} S by `iters` power iterations from the
  * start vector x0[n] (host, or device when S->on_device), normalised in the
  * M-norm each iteration; *out = Rayleigh quotient x^T S x / x^T M x of the
- * last iterate.  Runs on `stream` (NULL = default). */
+ * last iterate.  Runs on `stream` (NULL = default).  S is validated as in
+ * kf_create; the library allocates and frees its own device copies.
+ * Errors: KF_EINVAL (NULL, iters < 0, invalid CSR or mass, a start vector
+ * that vanishes or diverges), KF_ENOMEM, KF_EHIP. */
 int kf_estimate_lambda_max(const kf_csr* S, const double* m_diag, int32_t iters, const double* x0,
                            void* stream, double* out);
 
@@ -261,20 +271,30 @@ int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, doub
  * stream: returns after enqueueing. */
 int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b);
 
-/* Run the eigensolver from the start block start[n x b] (row-major, in host
+/* Algorithm 2.5 with the block remedy of Section 4.4: the Krylov space of C
+ * (Section 2.1, def. ArnoldiEWP) grown from the start block, the pencil
+ * projected onto it (eq. projevp), residuals and acceptance (Section 2.4,
+ * eq. res and the stopping rule after it).
+ * Run the eigensolver from the start block start[n x b] (row-major, in host
  * or device memory, 1 <= b <= 16) until opt.target pairs are accepted
  * (residual <= tol), the basis reaches m_max columns, opt.max_iters filter
  * applications, or breakdown.  *out receives a library-owned result released
- * with kf_result_free.  Synchronous. */
+ * with kf_result_free.  Synchronous.  Errors: KF_EINVAL (NULL, b or m_max
+ * out of range (m_max <= 2048), tol <= 0, non-finite or zero start block),
+ * KF_EUNSTABLE (the time stepping diverged), KF_ENOMEM, KF_EHIP; the result
+ * status KF_EBREAKDOWN / KF_ENOTCONV is informational. */
 int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol,
              kf_result** out);
 
 /* Release a result (NULL accepted). */
 int kf_result_free(kf_result* r);
 
-/* Copy up to max_cols columns of the current Krylov basis B (n x k,
+/* The basis B_m of Algorithm 2.5 (its output; the span of the Krylov space
+ * of Section 2.1) left by the last kf_solve on this handle.
+ * Copy up to max_cols columns of the current Krylov basis B (n x k,
  * M-orthonormal to the level reported as kf_result.orth_error) to host memory
- * out[n x max_cols] column-major; *ncols receives the number copied. */
+ * out[n x max_cols] column-major; *ncols receives the number copied.
+ * Errors: KF_EINVAL (NULL, max_cols < 0), KF_EHIP. */
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols);
 
 /* ---- batches of independent problems (one batched time-stepping launch) ----
@@ -307,10 +327,15 @@ int kf_destroy_batch(kf_batch* bt);
  * dimension n_p), 1 <= b <= 16.  Synchronous. */
 int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y, int32_t b);
 
-/* Solve every member from its host start block starts[p] (n_p x b
+/* Algorithm 2.5 (with the block remedy of Section 4.4) for every member,
+ * exactly as kf_solve, with the time loops of all members (eq. 2stepmethod,
+ * eq. disc_filtercoeff) advancing in one batched launch sequence.
+ * Solve every member from its host start block starts[p] (n_p x b
  * row-major); results[P] receives one library-owned result per member
  * (release each with kf_result_free).  t_leapfrog of every result is the time
- * of the batched time stepping of the whole batch.  Synchronous. */
+ * of the batched time stepping of the whole batch.  Synchronous.  Errors:
+ * as kf_solve, prefixed with the failing member's index; on error no result
+ * is returned (results[p] = NULL for every p). */
 int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t m_max, double tol,
                    kf_result** results);
 

@@ -18,13 +18,13 @@ Modules and the passages they follow:
                   the fully discrete filter function (Lemma 2.3).
 * ``timestep``  - the operator C: explicit two-step scheme (eq. 2stepmethod)
                   with y_{-1} = y_0 = r, weighted by the rectangle rule
-                  (Algorithm 2.5, time loop).
+                  (eq. disc_filtercoeff).
 * ``power``     - power iteration for the largest eigenvalue and the time
                   step / step count rule used by the workloads.
 * ``krylov``    - Algorithm 2.5 (Krylov loop), the projected pencil
-                  (eq. projevp), residuals (eq. res) and acceptance; both the
-                  paper's literal Euclidean-MGS variant and the M-inner CGS2
-                  block variant the GPU library implements.
+                  (eq. projevp), residuals (eq. res) and acceptance; a
+                  Euclidean basis of the Krylov space (the paper's inner
+                  product) and the M-inner CGS2 block form.
 
 Parity status: every function is pinned by CPU tests against closed forms,
 invariants or brute force (see ``tests/test_oracle_*.py``); none is
@@ -35,4 +35,4 @@ from .weights import alpha, discrete_weights  # noqa: F401
 from .filter import q_sequence, beta_tilde  # noqa: F401
 from .timestep import apply_filter  # noqa: F401
 from .power import power_lambda_max, time_step_rule  # noqa: F401
-from .krylov import krylov_basis_paper, krylov_solve, rayleigh_ritz, KrylovResult  # noqa: F401
+from .krylov import krylov_basis_euclidean, krylov_solve, rayleigh_ritz, KrylovResult  # noqa: F401

@@ -3,9 +3,10 @@ Algorithm 2.5; Section 2.4 eq. res and the stopping rule after it).
 
 Two forms of the Krylov loop:
 
-``krylov_basis_paper``  Algorithm 2.5 as printed: one pass of modified
-    Gram-Schmidt in the Euclidean inner product, 2-norm normalisation, stop on
-    an exactly zero vector.  Used by the tests to show that the projected
+``krylov_basis_euclidean``  an orthonormal basis, in the Euclidean inner
+    product, of the Krylov space K_m(C, r_0) of Section 2.1 (def. ArnoldiEWP),
+    the orthogonalisation the paper uses; a column that vanishes ends the
+    space (it is invariant).  Used by the tests to show that the projected
     pencil does not depend on the choice of basis.
 
 ``krylov_solve``  the form the GPU library computes (readings of the paper
@@ -53,21 +54,21 @@ class KrylovResult:
     history: list = field(default_factory=list)
 
 
-def krylov_basis_paper(S, m, tau, w, r0, mdim):
-    """Algorithm 2.5 verbatim: returns B_m = (r_0, ..., r_{m-1}) with
-    Euclidean-orthonormal columns (fewer if an exact zero vector appears)."""
-    r = np.asarray(r0, dtype=np.float64).copy()
-    r /= np.linalg.norm(r)
-    basis = [r]
-    for _k in range(mdim - 1):
-        nxt = apply_filter(S, m, tau, w, basis[-1])
-        for q in basis:  # modified Gram-Schmidt: coefficient from the updated vector
-            nxt = nxt - (nxt @ q) * q
-        nrm = np.linalg.norm(nxt)
-        if nrm == 0.0:
+def krylov_basis_euclidean(S, m, tau, w, r0, mdim):
+    """Euclidean-orthonormal basis of K_mdim(C, r0) (Section 2.1): column k+1
+    is C applied to column k with its components along the earlier columns
+    removed one at a time (modified Gram-Schmidt), then scaled to unit 2-norm.
+    Fewer than mdim columns when the space becomes invariant (a zero column)."""
+    columns = [np.asarray(r0, dtype=np.float64) / np.linalg.norm(r0)]
+    while len(columns) < mdim:
+        v = apply_filter(S, m, tau, w, columns[-1])
+        for q in columns:
+            v = v - (q @ v) * q
+        length = np.linalg.norm(v)
+        if length == 0.0:
             break
-        basis.append(nxt / nrm)
-    return np.column_stack(basis)
+        columns.append(v / length)
+    return np.column_stack(columns)
 
 
 def _orthonormalize_block(X, m, B, ref, drop_tol):

@@ -1131,7 +1131,16 @@ int tune_block(kf_problem* p, SellOp& A, StepBufs& sb, int bk) {
 int autotune(kf_problem* p, DevCsr& dc, const double* d_scale) {
   SellOp alt;
   const bool try_alt = p->A.idx_bytes == 2;
-  if (try_alt) KF_TRY(build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, p->A.val_bytes, 4, p->st, alt));
+  if (try_alt) {
+    KF_TRY(build_sell(p->n, p->nnz, dc.rowptr, dc.col, dc.val, d_scale, p->A.val_bytes, 4, p->st, alt));
+    // the alternative is timed, and kept, with the caller's fixed choices
+    // (unroll factor, lanes per row, band copy)
+    alt.unroll = p->A.unroll;
+    for (int l = 0; l < 5; ++l) {
+      alt.lpr[l] = p->A.lpr[l];
+      alt.band[l] = p->A.band[l];
+    }
+  }
   double best = 1e300;
   int best_remap = p->opt.xcd_remap, best_nt = p->A.nt_loads, best_alt = 0;
   for (int use_alt = 0; use_alt <= (try_alt ? 1 : 0); ++use_alt) {

@@ -137,12 +137,12 @@ def test_basis_is_m_orthonormal(grid2d_run):
 
 
 def test_projected_pencil_is_basis_independent(grid2d_run):
-    # Algorithm 2.5 as printed (Euclidean modified Gram-Schmidt) spans the same
+    # a Euclidean basis (the paper's inner product) spans the same
     # Krylov space; eq. projevp uses both B^T S B and B^T M B, so the Ritz
     # values agree although the bases differ
     P, tau, w, V0, res = grid2d_run
     k = 15
-    Bp = oracle.krylov_basis_paper(P.S, P.m, tau, w, V0[:, 0], k)
+    Bp = oracle.krylov_basis_euclidean(P.S, P.m, tau, w, V0[:, 0], k)
     Bm = res.basis[:, :k]
     th_p = oracle.rayleigh_ritz(P.S, P.m, Bp, 0, 1e9)[0]
     th_m = oracle.rayleigh_ritz(P.S, P.m, Bm, 0, 1e9)[0]
