@@ -271,6 +271,23 @@ int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, doub
  * stream: returns after enqueueing. */
 int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = C x as kf_apply_filter, with its three n x pow2(b) time-stepping blocks
+ * taken from a fixed array of 64 MiB that the library holds on every GPU it
+ * runs on until the process ends, instead of memory it allocates.  Calls no
+ * hipMalloc, hipFree or other allocating routine and does not time block
+ * variants (it uses the one kf_create or earlier calls chose).
+ * Limit: 3 * n * pow2(b) * value bytes (8 for KF_FP64, 4 for KF_MIXED) must
+ * not exceed 64 MiB, else KF_EINVAL (float64, b = 1: n <= 2,796,202).
+ * The current device must be the one kf_create ran on (else KF_EINVAL).
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other threads) race.  Every value the kernels read from
+ * the array is written first in the same call, so nothing needs clearing.
+ * x, y: DEVICE pointers to n x b row-major float64 blocks, 1 <= b <= 16.
+ * Asynchronous on the problem's stream. */
+int kf_apply_filter_noalloc(kf_problem* p, const double* x, double* y, int32_t b);
+
 /* Algorithm 2.5 with the block remedy of Section 4.4: the Krylov space of C
  * (Section 2.1, def. ArnoldiEWP) grown from the start block, the pencil
  * projected onto it (eq. projevp), residuals and acceptance (Section 2.4,

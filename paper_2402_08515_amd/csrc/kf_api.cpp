@@ -19,6 +19,7 @@
 #include <new>
 #include <string>
 #include <atomic>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -96,6 +97,7 @@ struct kf_problem {
   // batch members with their own stream (concurrent projection work)
   bool own_stream = false;
   hipEvent_t sync_ev = nullptr;
+  int device = 0;  // the GPU the problem's memory lives on
   // pinned host staging for the values read back at every Krylov step
   // (copies into it are queued without blocking the host)
   char* pin = nullptr;
@@ -283,6 +285,50 @@ int ensure_step_buffers(kf_problem* p, StepBufs& sb, int bk, int vb) {
   return KF_OK;
 }
 
+// Fixed device memory for kf_apply_filter_noalloc: one copy per GPU (the
+// runtime places the array on every device the library runs on), held until
+// the process ends.  Host code never passes the array's name to a kernel:
+// that is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  KF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(KF_EINVAL, "kf: device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(KF_EHIP, std::string("kf: no device address for the scratch array: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return KF_OK;
+}
+
+// The three n x bk time-stepping blocks carved out of the scratch array.
+int scratch_step_buffers(int32_t n, int bk, int vb, StepBufs& sb) {
+  const size_t one = ((size_t)n * bk * vb + 255) / 256 * 256;
+  if (3 * one > kScratchBytes)
+    return fail(KF_EINVAL, "kf_apply_filter_noalloc: 3 x n x " + std::to_string(bk) + " x " + std::to_string(vb) +
+                               " bytes exceed the fixed " + std::to_string(kScratchBytes >> 20) + " MiB");
+  void* base = nullptr;
+  KF_TRY(scratch_address(&base));
+  char* c = static_cast<char*>(base);
+  sb.Y0 = c;
+  sb.Y1 = c + one;
+  sb.R = c + 2 * one;
+  sb.cap = bk;
+  sb.vb = vb;
+  return KF_OK;
+}
+
 void free_step_buffers(StepBufs& sb) {
   dfree(sb.Y0);
   dfree(sb.Y1);
@@ -294,11 +340,16 @@ void free_step_buffers(StepBufs& sb) {
 // columns; float64) with kernel block width bk; the first bout columns of the
 // result go to dst (strides drs, dcs).  Asynchronous.
 int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, int64_t srs, int64_t scs, int bsrc,
-               int bk, double* dst, int64_t drs, int64_t dcs, int bout, const std::vector<double>& w) {
+               int bk, double* dst, int64_t drs, int64_t dcs, int bout, const std::vector<double>& w,
+               bool may_alloc = true) {
   const int L = (int)w.size();
   hipStream_t st = p->st;
   if (L == 1) return launch_scale_copy(p->n, bout, std::min(bsrc, bout), src, srs, scs, w[0], dst, drs, dcs, st);
-  KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
+  if (may_alloc) {
+    KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
+  } else if (sb.cap < bk || sb.vb != A.val_bytes || !sb.Y0 || !sb.Y1 || !sb.R) {
+    return fail(KF_EINVAL, "kf: time-stepping buffers too small");
+  }
   // a single float64 vector stored contiguously already has the layout of a
   // step buffer: the first two steps read it in place (no load launch);
   // otherwise it is loaded (converted, interleaved) into Y1
@@ -1299,6 +1350,10 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   p->L = L;
   p->opt = o;
   p->st = (hipStream_t)o.stream;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(KF_EHIP, "kf_create: no current device");
+  }
   p->w = fourier_weights(omega_min, omega_max, tau, L);
   int rc = KF_OK;
   do {
@@ -1503,6 +1558,20 @@ int kf_apply_filter(kf_problem* p, const double* x, double* y, int32_t b) {
   const int bk = pow2ceil(b);
   KF_TRY(tune_block(p, p->A, p->sb, bk));
   return run_filter(p, p->A, p->sb, x, b, 1, b, bk, y, b, 1, b, p->w);
+}
+
+int kf_apply_filter_noalloc(kf_problem* p, const double* x, double* y, int32_t b) {
+  if (!p || !x || !y) return fail(KF_EINVAL, "kf_apply_filter_noalloc: NULL argument");
+  if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_apply_filter_noalloc: b must lie in [1, 16]");
+  int dev = -1;
+  KF_HIP(hipGetDevice(&dev));
+  if (dev != p->device)
+    return fail(KF_EINVAL, "kf_apply_filter_noalloc: the problem lives on device " + std::to_string(p->device) +
+                               ", the current device is " + std::to_string(dev));
+  const int bk = pow2ceil(b);
+  StepBufs sb;
+  KF_TRY(scratch_step_buffers(p->n, bk, p->A.val_bytes, sb));
+  return run_filter(p, p->A, sb, x, b, 1, b, bk, y, b, 1, b, p->w, false);
 }
 
 int kf_result_free(kf_result* r) {

@@ -123,6 +123,7 @@ _SIGNATURES = {
     "kf_time_step_rule": (C.c_int, [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "kf_filter_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "kf_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "kf_apply_filter_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
@@ -429,6 +430,18 @@ class Problem:
         y = torch.empty_like(x)
         _check(lib().kf_apply_filter(self._h, x.data_ptr(), y.data_ptr(), int(x.shape[1])))
         return y
+
+    def apply_filter_noalloc(self, x: torch.Tensor, y: torch.Tensor) -> None:
+        """y = C x into the caller's device block y (both n x b float64,
+        contiguous), with no device allocation in the library."""
+        if x.dim() == 1:
+            x, y = x[:, None], y[:, None]
+        for t in (x, y):
+            if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous() or t.shape[0] != self.n:
+                raise ValueError("x and y must be contiguous float64 CUDA tensors with n rows")
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same shape")
+        _check(lib().kf_apply_filter_noalloc(self._h, x.data_ptr(), y.data_ptr(), int(x.shape[1])))
 
     def solve(self, start, m_max: int, tol: float) -> SolveResult:
         """start: n x b float64 block, a host array or a contiguous CUDA tensor."""
