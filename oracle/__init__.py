@@ -25,6 +25,8 @@ Modules and the passages they follow:
                   (eq. projevp), residuals (eq. res) and acceptance; a
                   Euclidean basis of the Krylov space (the paper's inner
                   product) and the M-inner CGS2 block form.
+* ``subspace``  - the fixed-dimension (FEAST-type) filtered subspace
+                  iteration of Section 4.4.
 
 Parity status: every function is pinned by CPU tests against closed forms,
 invariants or brute force (see ``tests/test_oracle_*.py``); none is
@@ -36,3 +38,4 @@ from .filter import q_sequence, beta_tilde  # noqa: F401
 from .timestep import apply_filter  # noqa: F401
 from .power import power_lambda_max, time_step_rule  # noqa: F401
 from .krylov import krylov_basis_euclidean, krylov_solve, rayleigh_ritz, KrylovResult  # noqa: F401
+from .subspace import subspace_solve, SubspaceResult  # noqa: F401
