@@ -13,10 +13,18 @@ through products with tau:
   a = tau*omega_min, c = tau*omega_max, for l < L.
 
 Network: features f = [a/pi, c/pi, x_max, L/512] (x_max = tau*sqrt(lambda_max)/2),
-three GELU layers of width 128 and a linear output of 512 values (features
-padded with zeros to 64 inputs);
+three GELU layers of width 128 and a linear output of 512 values;
 w = w_Fourier + s * out (masked to l < L), s = 0.01, so the untrained
-network (output layer at zero) reproduces the Fourier weights.
+network (output layer at zero) reproduces the Fourier weights.  The parameter
+vector stores the first layer in a 64 x 128 slot of which the rows of the four
+features are used (the rest multiplies nothing and gets a zero gradient).
+
+Precision: by default every product is float64.  With ``bf16=True`` the
+operands of the network's matrix products (the four layers forward, and the
+weight-gradient and back-propagation products) are first rounded to bfloat16
+(round to nearest, ties to even), the stated training precision of the
+learned filter (bfloat16 operands, wider accumulation); everything else
+stays float64.
 
 Loss per sample on the fixed grid x_g = 0.95 g / (G-1), g < G:
 J = mean over the band [x_lo, x_hi] of (beta~ - 1)^2
@@ -77,9 +85,22 @@ def sample_params(omega_min, omega_max, tau, lambda_max):
 
 def features(omega_min, omega_max, tau, lambda_max) -> np.ndarray:
     a, c, L, xm = sample_params(omega_min, omega_max, tau, lambda_max)
-    f = np.zeros(64)
-    f[:NFEAT] = [a / math.pi, c / math.pi, xm, L / LMAX]
-    return f
+    return np.array([a / math.pi, c / math.pi, xm, L / LMAX])
+
+
+def bf16_round(x) -> np.ndarray:
+    """Nearest bfloat16 value (8 significant bits, ties to even) of each
+    entry, as float64; the entries are first taken to float32."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _mm(A, B, bf16):
+    """Matrix product of the network, with bfloat16 operands when asked."""
+    return (bf16_round(A) @ bf16_round(B)) if bf16 else A @ B
 
 
 def fourier_weights_normalised(a: float, c: float, L: int) -> np.ndarray:
@@ -107,19 +128,19 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def forward(theta, samples):
+def forward(theta, samples, bf16=False):
     """samples: (B, 4) rows (omega_min, omega_max, tau, lambda_max).
     Returns (weights (B, LMAX), loss per sample (B,), cache)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta)
     X = np.stack([features(*s) for s in samples])
     prm = [sample_params(*s) for s in samples]
-    z1 = X @ W1 + b1
+    z1 = _mm(X, W1[:NFEAT], bf16) + b1
     h1 = gelu(z1)
-    z2 = h1 @ W2 + b2
+    z2 = _mm(h1, W2, bf16) + b2
     h2 = gelu(z2)
-    z3 = h2 @ W3 + b3
+    z3 = _mm(h2, W3, bf16) + b3
     h3 = gelu(z3)
-    out = h3 @ W4 + b4
+    out = _mm(h3, W4, bf16) + b4
     lmask = np.stack([(np.arange(LMAX) < L).astype(float) for (_a, _c, L, _x) in prm])
     wF = np.stack([fourier_weights_normalised(a, c, L) for (a, c, L, _x) in prm])
     w = (wF + OUT_SCALE * out) * lmask
@@ -135,24 +156,25 @@ def forward(theta, samples):
     return w, J, cache
 
 
-def loss_and_grad(theta, samples):
+def loss_and_grad(theta, samples, bf16=False):
     """Mean loss over the batch and its gradient (backpropagation)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta)
-    w, J, c = forward(theta, samples)
+    w, J, c = forward(theta, samples, bf16)
     B = len(samples)
     dbeta = (2.0 * c["mi"] * (c["beta"] - 1.0) / c["ni"][:, None] + 2.0 * GAMMA * c["mo"] * c["beta"] / c["no"][:, None]) / B
     dw = (dbeta @ c["Q"].T) * c["lmask"]
     dout = OUT_SCALE * dw
-    gW4 = c["h3"].T @ dout
+    gW4 = _mm(c["h3"].T, dout, bf16)
     gb4 = dout.sum(0)
-    dz3 = (dout @ W4.T) * gelu_grad(c["z3"])
-    gW3 = c["h2"].T @ dz3
+    dz3 = _mm(dout, W4.T, bf16) * gelu_grad(c["z3"])
+    gW3 = _mm(c["h2"].T, dz3, bf16)
     gb3 = dz3.sum(0)
-    dz2 = (dz3 @ W3.T) * gelu_grad(c["z2"])
-    gW2 = c["h1"].T @ dz2
+    dz2 = _mm(dz3, W3.T, bf16) * gelu_grad(c["z2"])
+    gW2 = _mm(c["h1"].T, dz2, bf16)
     gb2 = dz2.sum(0)
-    dz1 = (dz2 @ W2.T) * gelu_grad(c["z1"])
-    gW1 = c["X"].T @ dz1
+    dz1 = _mm(dz2, W2.T, bf16) * gelu_grad(c["z1"])
+    gW1 = np.zeros_like(W1)
+    gW1[:NFEAT] = _mm(c["X"].T, dz1, bf16)
     gb1 = dz1.sum(0)
     grad = np.concatenate([g.ravel() for g in (gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4)])
     return float(J.mean()), grad

@@ -71,3 +71,41 @@ def test_loss_in_frequency_terms():
         stop = (om <= np.sqrt(lam)) & ((om < omin - gap) | (om > omax + gap))
         expect = np.mean((beta[band] - 1.0) ** 2) + np.mean(beta[stop] ** 2)
         assert mlp.loss_of_weights(s, w) == pytest.approx(expect, rel=1e-9)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    import torch
+
+    one = 1.0
+    ulp = 2.0**-7  # spacing of bfloat16 just above 1
+    assert mlp.bf16_round(one + ulp / 2)[()] == one  # tie -> even (1.0)
+    assert mlp.bf16_round(one + 1.5 * ulp)[()] == one + 2 * ulp  # tie -> even mantissa
+    assert mlp.bf16_round(one + 0.49 * ulp)[()] == one
+    assert mlp.bf16_round(-3.0)[()] == -3.0
+    x = np.random.default_rng(3).standard_normal(10000) * 10.0 ** np.random.default_rng(4).uniform(-6, 6, 10000)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.bf16_round(x), ref)
+    assert np.max(np.abs(mlp.bf16_round(x) - x) / np.abs(x)) <= 2.0**-8 * (1 + 1e-6)
+
+
+def test_bf16_gradient_is_the_float64_gradient_to_bfloat16_accuracy():
+    # the float64 gradient is pinned by finite differences above; rounding
+    # the products' operands to 8 significant bits moves each layer's
+    # gradient by a few bfloat16 units relative to the layer's scale
+    s = filter_samples(64, stream=0)
+    rng = np.random.default_rng(3)
+    theta = mlp.init_params(1)
+    theta[-(128 * 512 + 512):] = 0.3 * rng.standard_normal(128 * 512 + 512)
+    f64, g64 = mlp.loss_and_grad(theta, s)
+    f16, g16 = mlp.loss_and_grad(theta, s, bf16=True)
+    assert f16 == pytest.approx(f64, rel=2e-2)
+    off = 0
+    for shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        a, b = g16[off:off + k], g64[off:off + k]
+        scale = np.abs(b).max()
+        if scale > 0:
+            assert np.abs(a - b).max() <= 0.02 * scale, shape
+        off += k
+    # rows of the first layer's slot that no feature feeds get no gradient
+    assert np.all(g16[4 * 128:64 * 128] == 0.0)
