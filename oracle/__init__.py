@@ -27,6 +27,10 @@ Modules and the passages they follow:
                   product) and the M-inner CGS2 block form.
 * ``subspace``  - the fixed-dimension (FEAST-type) filtered subspace
                   iteration of Section 4.4.
+* ``windows``   - the alternative weight functions of Section 4.3.
+* ``inertia``   - eigenvalue counts by Sylvester's law of inertia (a banded
+                  LDL^T in plain C, ``inertia.c``) for meshes without a closed
+                  form spectrum.
 
 Parity status: every function is pinned by CPU tests against closed forms,
 invariants or brute force (see ``tests/test_oracle_*.py``); none is
