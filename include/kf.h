@@ -119,11 +119,22 @@ typedef struct kf_options {
                             Rayleigh-Ritz step corrects to first order for the
                             remaining non-orthogonality (E = B^T M B - I: the
                             eigenvalues of H - (E H + H E)/2); 1 = every step */
-  int32_t refine;        /* KF_MIXED only: passes of float64 refinement
-                            (0 = none): each applies the filter in float64 to
-                            the near-interval Ritz block of the previous one
-                            and solves the pencil on its span; a second pass
-                            runs only while pairs of the target are missing */
+  int32_t refine;        /* KF_MIXED only: at most this many iterations of
+                            the float64 refinement (0 = none, and no float64
+                            operator is kept): the filtered subspace
+                            iteration (Section 4.4) in float64 started from
+                            the Ritz vectors of the float32 Krylov space near
+                            the interval; it stops once the target is met */
+  int32_t escalate;      /* KF_MIXED, solves with a target: when the float64
+                            refinement misses the target although the float32
+                            loop reached it (float32 round-off seeds, at every
+                            step, directions of eigenspaces of multiplicity
+                            above b that pollute the Ritz vectors of other
+                            eigenvalues where the filter cannot tell them
+                            apart), 1 = the Krylov loop starts again from the
+                            start block with float64 stepping
+                            (kf_result.escalated), so the target is still
+                            met; 0 = up to 4 further refinements instead */
   int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
   int32_t index_bytes;   /* column-index width of the device operator:
                             0 = automatic (2 when every |col - row| < 32768),
@@ -191,11 +202,17 @@ typedef struct kf_result {
   double t_refine;        /* seconds in the mixed-mode refinement */
   double orth_error;      /* max |B^T M B - I| over the columns checked */
   int32_t full_passes;    /* Gram-Schmidt passes over the whole basis */
+  int64_t refine_vector_steps; /* vector time steps of the float64 refinement
+                                  (KF_MIXED), not in leapfrog_vector_steps for
+                                  kf_solve; included in it for
+                                  kf_subspace_solve */
+  int32_t escalated;      /* 1 when the solve restarted with float64
+                             stepping (kf_options.escalate) */
 } kf_result;
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0.3, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, reorth_tol 1e-9, proj_every 12, refine 2, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-9, proj_every 12, refine 8, escalate 1, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);
@@ -261,6 +278,35 @@ int kf_estimate_lambda_max(const kf_csr* S, const double* m_diag, int32_t iters,
  * i.e. T covers one period of the lowest sought frequency.  Host arithmetic. */
 int kf_time_step_rule(double lambda_est, double omega_min, double safety, double* tau, int32_t* L);
 
+/* ---- alternative weight functions (Section 4.3) --------------------------
+ * Section 2.2 builds the weight as the inverse cosine transform of a target
+ * function g on the frequency axis, alpha(t) = (2/pi) int_0^inf g(omega)
+ * cos(omega t) d omega (eq. filterf, the indicator of the interval), truncated
+ * at T = L tau (eq. weightf); Section 4.3 names smoother or more localised
+ * targets and weights adapted to the spectrum.  With c = (omega_min +
+ * omega_max)/2 and d = (omega_max - omega_min)/2:
+ *   KF_WINDOW_INDICATOR: eq. weightf (width unused);
+ *   KF_WINDOW_TRIANGLE:  g = max(0, 1 - |omega - c|/h) + the same at -c,
+ *                        h = width*d (width 2: g = 1/2 at the interval ends);
+ *   KF_WINDOW_GAUSSIAN:  g = exp(-(omega - c)^2/(2 sigma^2)) + the same at -c,
+ *                        sigma = width*d/sqrt(2 ln 2) (width 1: g = 1/2 at the
+ *                        ends).
+ * The mirrored term makes the transform exact in closed form; it only
+ * matters when the peak reaches omega = 0.  w_out[l] = tau*alpha(l tau),
+ * l < L (eq. disc_filtercoeff), host memory; pass them to kf_set_weights. */
+enum kf_window { KF_WINDOW_INDICATOR = 0, KF_WINDOW_TRIANGLE = 1, KF_WINDOW_GAUSSIAN = 2 };
+int kf_window_weights(int32_t kind, double omega_min, double omega_max, double tau, int32_t L, double width,
+                      double* w_out);
+
+/* Spectrum-adapted weights (Section 4.3: make |beta~| small where unwanted
+ * eigenvalues of high multiplicity, or an essential spectrum, are expected):
+ * the weights nearest to w[L] in the 2-norm whose discrete filter of
+ * Lemma 2.3 vanishes at the k frequencies omega[k] (0 <= k <= min(64, L)),
+ * beta~(omega_j) = sum_l w_out[l] q_l(omega_j) = 0.  Host arrays; w_out may
+ * equal w.  KF_EINVAL for (nearly) dependent constraints (repeated
+ * frequencies). */
+int kf_notch_weights(const double* w, int32_t L, double tau, const double* omega, int32_t k, double* w_out);
+
 /* Discrete filter function of Lemma 2.3, beta~(omega) = sum_l w_l q_l(omega),
  * at n points omega[n] (host) into beta_out[n] (host). */
 int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, double* beta_out);
@@ -302,6 +348,29 @@ int kf_apply_filter_noalloc(kf_problem* p, const double* x, double* y, int32_t b
  * status KF_EBREAKDOWN / KF_ENOTCONV is informational. */
 int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol,
              kf_result** out);
+
+/* Section 4.4: the fixed-dimension variant of the method, a FEAST-type
+ * filtered subspace iteration.  The block X of ncols columns (start: n x ncols
+ * row-major, host or device memory, 1 <= ncols <= 2048) is replaced, at each
+ * iteration, by an M-orthonormal basis of span(C X) (Section 2.3 operator;
+ * directions of relative size below 1e-6 dropped); the pencil is projected
+ * onto it (eq. projevp) and the Ritz pairs with omega in [omega_min,
+ * omega_max] get residuals (eq. res, relative to ||S v||_2); those <= tol are
+ * accepted.  Stops after max_iters iterations, when opt.target pairs are
+ * accepted (every copy of a multiple eigenvalue counts: the space holds
+ * them all), or (target 0) when every Ritz value inside the interval is
+ * accepted and their number did not change since the previous iteration.
+ * ncols should exceed the number of eigenvalues in the interval (with
+ * multiplicity); the convergence factor of a pair is |beta~| of the first
+ * eigenvalue left out of the space over its own |beta~| (Lemma 2.3).
+ * KF_MIXED: float32 stepping until the pairs reach the float32 floor, then
+ * float64 stepping (when the problem keeps a float64 operator, refine != 0).
+ * krylov_steps counts iterations, basis_size the final dimension; status
+ * KF_ENOTCONV when the stop test was not met.  Synchronous.
+ * Errors: KF_EINVAL (NULL, sizes, tol <= 0, non-finite start), KF_ENOMEM,
+ * KF_EUNSTABLE, KF_EHIP. */
+int kf_subspace_solve(kf_problem* p, const double* start, int32_t ncols, int32_t max_iters, double tol,
+                      kf_result** out);
 
 /* Release a result (NULL accepted). */
 int kf_result_free(kf_result* r);
@@ -395,6 +464,14 @@ int kf_mlp_loss_grad(kf_mlp* net, const double* samples, int32_t n, double* loss
  * the mean training loss of each epoch. */
 int kf_mlp_train(kf_mlp* net, const double* samples, int32_t n, const int32_t* order, int32_t epochs,
                  int32_t batch, double lr, double* epoch_loss);
+
+/* The network's filter coefficients for n samples (host, n x 4 rows
+ * omega_min, omega_max, tau, lambda_max; each needs L = ceil(2 pi /
+ * (tau omega_min)) <= 512) without the acceptance gate: w_out (host,
+ * n x 512 row-major) receives w_Fourier + 0.01 * network output, zero from
+ * l = L on (Section 2.2: any weight function; Lemma 2.3 gives its filter).
+ * Errors: KF_EINVAL (NULL, n < 1, invalid sample), KF_ENOMEM, KF_EHIP. */
+int kf_mlp_weights(kf_mlp* net, const double* samples, int32_t n, double* w_out);
 
 /* Filter coefficients for one problem: the network's weights when their loss
  * is below that of the Fourier weights (*used_learned = 1), else the Fourier

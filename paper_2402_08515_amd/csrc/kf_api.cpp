@@ -90,6 +90,9 @@ struct kf_problem {
   // end; 5, 6: start / end of a filter application queued ahead (swapped
   // with 0, 1 when it is kept)
   hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // phases of the filtered subspace iteration (filter, orthonormalisation,
+  // projection and residuals)
+  hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
   double tuned_us = 0.0;
   // k x k work arrays of the pencil correction (E, E H, corrected H)
   double* rr_work = nullptr;
@@ -998,90 +1001,164 @@ int eig_orthonormalise(kf_problem* p, double* Z, int nz, double* out, int* r_out
 
 int distinct_count(const std::vector<double>& acc, int b);
 
-// passes: up to opt.refine; a further pass runs only while fewer than
-// `target` pairs (counted as distinct_count with block width b) are accepted
-int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out, int target = 0,
-                 int b = 1) {
+// Two n x cap blocks (Vx, Yy, leading dimension ldb), a cap x cap Gram and a
+// kc x cap block of small vectors for the subspace iteration.
+int ensure_refine(kf_problem* p, int nc, int k) {
+  if (nc <= p->rcap && k <= p->rkcap) return KF_OK;
+  dfree(p->Vx);
+  dfree(p->Yy);
+  dfree(p->Ysel);
+  dfree(p->Gm);
+  const int cap = std::max({nc, 64, p->rcap});
+  const int kc = std::max({k, cap, p->rkcap});
+  p->Vx = p->Yy = p->Ysel = p->Gm = nullptr;
+  p->rcap = p->rkcap = 0;
+  KF_TRY(dalloc(&p->Vx, (size_t)p->ldb * cap));
+  KF_TRY(dalloc(&p->Yy, (size_t)p->ldb * cap));
+  KF_TRY(dalloc(&p->Ysel, (size_t)kc * cap));
+  KF_TRY(dalloc(&p->Gm, (size_t)cap * cap));
+  p->rcap = cap;
+  p->rkcap = kc;
+  return KF_OK;
+}
+
+struct SubspaceStats {
+  int iters = 0;
+  int dim = 0;
+  int64_t lf_steps = 0;  // vector time steps
+  double t_lf = 0, t_orth = 0, t_rr = 0;
+};
+
+// Fixed-dimension filtered subspace iteration (Section 4.4: a space of fixed
+// dimension instead of a growing Krylov space, i.e. a FEAST-type method with
+// the time-domain filter).  X holds nc columns (device, column-major,
+// leading dimension ldb; X and Q are p->Vx and p->Yy in either order, the
+// other one is work space).  One iteration:
+//   Q = C X with the operator A (float64 or float32 stepping), 16 columns at a
+//   time; Q M-orthonormalised twice through the eigen-decomposition of
+//   Q^T M Q (directions below 1e-12 of the largest dropped); H = Q^T S Q;
+//   the Ritz values with omega in the interval widened by `margin` get Ritz
+//   vectors, Rayleigh quotients and residuals (eq. projevp, eq. res);
+//   X <- Q for the next iteration (the Ritz vectors span the same space).
+// Stops after max_iters iterations, when `target` pairs (counted as
+// distinct_count with cnt_b) are accepted, or (target 0) when every Ritz
+// value inside the interval is accepted and their number did not change.
+// On return X points at the last M-orthonormal block, st.dim its columns.
+int subspace_iterate(kf_problem* p, const SellOp& A, StepBufs& sb, double*& X, double*& Q, int nc, int max_iters,
+                     double tol, int target, int cnt_b, double margin, bool want_vectors, CheckOut& out,
+                     SubspaceStats& stats) {
   hipStream_t st = p->st;
   const int n = p->n;
   const int64_t ld = p->ldb;
-  std::vector<int> pick;
-  for (size_t s = 0; s < in.cand_res.size(); ++s)
-    if (in.cand_res[s] <= 0.1) pick.push_back((int)s);
-  const int nc = (int)pick.size();
-  out = in;
-  if (nc == 0 || !p->A64.val) return KF_OK;
-  if (nc > 2048) return fail(KF_EINVAL, "kf_solve: refinement block larger than 2048 columns");
-  if (nc > p->rcap || k > p->rkcap) {
-    dfree(p->Vx);
-    dfree(p->Yy);
-    dfree(p->Ysel);
-    dfree(p->Gm);
-    p->Vx = p->Yy = p->Ysel = p->Gm = nullptr;
-    p->rcap = p->rkcap = 0;
-    const int cap = std::max(nc, 64);
-    const int kc = std::max(k, cap);
-    KF_TRY(dalloc(&p->Vx, (size_t)ld * cap));
-    KF_TRY(dalloc(&p->Yy, (size_t)ld * cap));
-    KF_TRY(dalloc(&p->Ysel, (size_t)kc * cap));
-    KF_TRY(dalloc(&p->Gm, (size_t)cap * cap));
-    p->rcap = cap;
-    p->rkcap = kc;
-  }
-  // X = B * (selected eigenvectors of the last check), into Vx
-  for (int i = 0; i < nc; ++i)
-    KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)i * k, p->ew.Y + (int64_t)pick[(size_t)i] * k, sizeof(double) * k,
-                          hipMemcpyDeviceToDevice, st));
-  KF_TRY(gemm_nn(n, k, p->B, p->ldb, p->Ysel, k, p->Vx, ld, nc, st));
-  const int passes = std::max(1, p->opt.refine);
-  int ncur = nc;
-  for (int pass = 0; pass < passes; ++pass) {
-    // Yy = C X in float64
-    for (int c0 = 0; c0 < ncur; c0 += 16) {
-      const int nb = std::min(16, ncur - c0);
-      KF_TRY(run_filter(p, p->A64, p->sb64, p->Vx + (int64_t)c0 * ld, 1, ld, nb, pow2ceil(nb),
-                        p->Yy + (int64_t)c0 * ld, 1, ld, nb, p->w));
+  const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+  const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
+  int prev_inside = -1;
+  int cur = nc;
+  auto lap = [&](hipEvent_t a, hipEvent_t b, double& acc) -> int {
+    KF_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    KF_HIP(hipEventElapsedTime(&ms, a, b));
+    acc += 1e-3 * ms;
+    return KF_OK;
+  };
+  for (int it = 0; it < max_iters && cur > 0; ++it) {
+    KF_HIP(hipEventRecord(p->sev[0], st));
+    for (int c0 = 0; c0 < cur; c0 += 16) {
+      const int nb = std::min(16, cur - c0);
+      KF_TRY(run_filter(p, A, sb, X + (int64_t)c0 * ld, 1, ld, nb, pow2ceil(nb), Q + (int64_t)c0 * ld, 1, ld, nb,
+                        p->w));
     }
+    {
+      // a time step beyond the CFL bound (or non-finite input) shows as
+      // non-finite filtered columns
+      int32_t* bad = p->flags + 49;
+      int32_t hb = 0;
+      KF_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+      for (int c = 0; c < cur; ++c) KF_TRY(nonfinite_flag(n, Q + (int64_t)c * ld, bad, st));
+      KF_HIP(hipEventRecord(p->sev[1], st));
+      KF_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KF_HIP(hipStreamSynchronize(st));
+      if (hb) return fail(KF_EUNSTABLE, "kf: filtered subspace not finite (tau too large for the spectrum?)");
+    }
+    stats.lf_steps += (int64_t)cur * ((int64_t)p->w.size() - 1);
+    KF_TRY(lap(p->sev[0], p->sev[1], stats.t_lf));
+    ++stats.iters;
     int r = 0, r2 = 0;
-    KF_TRY(eig_orthonormalise(p, p->Yy, ncur, p->Vx, &r));
-    if (r == 0) return KF_OK;
-    KF_TRY(eig_orthonormalise(p, p->Vx, r, p->Yy, &r2));
-    if (r2 == 0) return KF_OK;
-    // projected pencil Z^T S Z with Z = Yy[:, :r2]; S Z into Vx
-    for (int c0 = 0; c0 < r2; c0 += 16) {
-      const int nb = std::min(16, r2 - c0);
-      KF_TRY(spmv_cols(p->S, p->Yy + (int64_t)c0 * ld, ld, p->Vx + (int64_t)c0 * ld, ld, nb, nullptr, st));
+    KF_TRY(eig_orthonormalise(p, Q, cur, X, &r));
+    if (r > 0) KF_TRY(eig_orthonormalise(p, X, r, Q, &r2));
+    KF_HIP(hipEventRecord(p->sev[2], st));
+    KF_TRY(lap(p->sev[1], p->sev[2], stats.t_orth));
+    if (r2 == 0) {
+      cur = 0;
+      break;
     }
-    for (int c0 = 0; c0 < r2; c0 += 32) {
-      const int nb = std::min(32, r2 - c0);
-      KF_TRY(gemv_t(n, r2, p->Yy, ld, p->Vx + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr,
-                    p->Gm + (int64_t)c0 * r2, r2, p->gw, st));
+    std::swap(X, Q);  // X: the M-orthonormal block; Q: work space
+    cur = r2;
+    // projected pencil X^T S X, S X into Q
+    for (int c0 = 0; c0 < cur; c0 += 16) {
+      const int nb = std::min(16, cur - c0);
+      KF_TRY(spmv_cols(p->S, X + (int64_t)c0 * ld, ld, Q + (int64_t)c0 * ld, ld, nb, nullptr, st));
     }
-    KF_TRY(symmetrize(r2, p->Gm, r2, st));
-    const double margin = 0.05 * (p->omega_max - p->omega_min);
-    const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+    for (int c0 = 0; c0 < cur; c0 += 32) {
+      const int nb = std::min(32, cur - c0);
+      KF_TRY(gemv_t(n, cur, X, ld, Q + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr, p->Gm + (int64_t)c0 * cur,
+                    cur, p->gw, st));
+    }
+    KF_TRY(symmetrize(cur, p->Gm, cur, st));
     std::vector<double> th, sel;
     KF_TRY(small_eigen(
-        p, r2, p->Gm, r2, th,
+        p, cur, p->Gm, cur, th,
         [&](double t) {
           const double om = std::sqrt(std::max(t, 0.0));
           return om >= lo && om <= hi;
         },
         sel));
-    KF_TRY(ritz_residuals(p, p->Yy, ld, r2, sel, tol, want_vectors, out, true));
-    if (pass + 1 == passes || (target > 0 && distinct_count(out.acc_theta, b) >= target)) break;
-    // next pass: the filter again on the Ritz vectors of this one that are
-    // still near (residual <= 0.1)
-    std::vector<int> pk;
-    for (size_t q = 0; q < out.cand_res.size(); ++q)
-      if (out.cand_res[q] <= 0.1) pk.push_back((int)q);
-    if (pk.empty()) break;
-    for (size_t i = 0; i < pk.size(); ++i)
-      KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)i * r2, p->ew.Y + (int64_t)pk[i] * r2, sizeof(double) * r2,
-                            hipMemcpyDeviceToDevice, st));
-    ncur = (int)pk.size();
-    KF_TRY(gemm_nn(n, r2, p->Yy, ld, p->Ysel, r2, p->Vx, ld, ncur, st));
+    KF_TRY(ritz_residuals(p, X, ld, cur, sel, tol, want_vectors, out, true));
+    out.ritz = th;
+    KF_HIP(hipEventRecord(p->sev[3], st));
+    KF_TRY(lap(p->sev[2], p->sev[3], stats.t_rr));
+    int inside = 0;
+    bool all = true;
+    for (size_t q = 0; q < out.cand_theta.size(); ++q) {
+      const double t = out.cand_theta[q];
+      if (t >= lo2 && t <= hi2) {
+        ++inside;
+        if (!(out.cand_res[q] <= tol)) all = false;
+      }
+    }
+    if (target > 0 && distinct_count(out.acc_theta, cnt_b) >= target) break;
+    if (target <= 0 && inside > 0 && all && inside == prev_inside) break;
+    prev_inside = inside;
   }
+  stats.dim = cur;
+  return KF_OK;
+}
+
+// Mixed-precision refinement: the float64 filtered subspace iteration started
+// from the Ritz vectors of the float32 Krylov space whose omega lies in the
+// interval widened by the margin (all of them: a half-converged copy of a
+// multiple eigenvalue, seeded by float32 round-off, must stay in the space
+// until it has converged, or it keeps contaminating its neighbours).  At most
+// opt.refine iterations; it stops once `target` pairs (distinct_count with
+// block width b) are accepted.
+int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out,
+                 int64_t* lf_steps, int target = 0, int b = 1, double margin = 0.0) {
+  hipStream_t st = p->st;
+  const int n = p->n;
+  const int64_t ld = p->ldb;
+  const int nc = (int)in.cand_theta.size();
+  out = in;
+  if (nc == 0 || !p->A64.val) return KF_OK;
+  if (nc > 2048) return fail(KF_EINVAL, "kf_solve: refinement block larger than 2048 columns");
+  KF_TRY(ensure_refine(p, nc, k));
+  // X = B * (eigenvectors of the last check's candidates, ew.Y), into Vx
+  KF_TRY(gemm_nn(n, k, p->B, p->ldb, p->ew.Y, k, p->Vx, ld, nc, st));
+  double* X = p->Vx;
+  double* Q = p->Yy;
+  SubspaceStats stats;
+  KF_TRY(subspace_iterate(p, p->A64, p->sb64, X, Q, nc, std::max(1, p->opt.refine), tol, target, b, margin,
+                          want_vectors, out, stats));
+  *lf_steps += stats.lf_steps;
   out.ritz = in.ritz;
   out.orth = in.orth;
   return KF_OK;
@@ -1256,6 +1333,8 @@ void free_problem(kf_problem* p) {
   free_eig(p->ew);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->sev)
+    if (e) (void)hipEventDestroy(e);
   if (p->sync_ev) (void)hipEventDestroy(p->sync_ev);
   if (p->own_stream && p->st) {
     (void)hipStreamSynchronize(p->st);
@@ -1281,7 +1360,8 @@ void kf_default_options(kf_options* o) {
   o->drop_tol = 1e-10;
   o->reorth_tol = 1e-9;
   o->proj_every = 12;
-  o->refine = 2;
+  o->refine = 8;
+  o->escalate = 1;
   o->want_vectors = 0;
   o->index_bytes = 0;
   o->xcd_remap = 1;
@@ -1391,6 +1471,8 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
     for (int l = 0; l < 5; ++l) p->A.band[l] = p->A64.band[l] = o.block_band == 1 ? 1 : 0;
     for (hipEvent_t& e : p->ev)
       if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
+    for (hipEvent_t& e : p->sev)
+      if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(KF_EHIP, "kf_create: event creation failed");
     if (!rc && o.autotune) rc = autotune(p, dc, d_scale);
     for (int l = 0; l < 5; ++l) p->A.lpr[l] = p->A64.lpr[l] = o.lanes_per_row;
     dfree(d_scale);
@@ -1468,6 +1550,111 @@ int kf_set_weights(kf_problem* p, const double* w, int32_t L) {
 int kf_get_weights(const kf_problem* p, double* w_out) {
   if (!p || !w_out) return fail(KF_EINVAL, "kf_get_weights: NULL argument");
   std::memcpy(w_out, p->w.data(), sizeof(double) * p->w.size());
+  return KF_OK;
+}
+
+int kf_window_weights(int32_t kind, double omega_min, double omega_max, double tau, int32_t L, double width,
+                      double* w_out) {
+  if (!w_out) return fail(KF_EINVAL, "kf_window_weights: NULL output");
+  if (!(omega_min >= 0) || !(omega_max > omega_min) || !std::isfinite(omega_max))
+    return fail(KF_EINVAL, "kf_window_weights: need 0 <= omega_min < omega_max (finite)");
+  if (!(tau > 0) || !std::isfinite(tau) || L < 1) return fail(KF_EINVAL, "kf_window_weights: need tau > 0, L >= 1");
+  if (kind != KF_WINDOW_INDICATOR && !(width > 0 && std::isfinite(width)))
+    return fail(KF_EINVAL, "kf_window_weights: width must be positive");
+  const double pi = 3.14159265358979323846;
+  const double c = 0.5 * (omega_min + omega_max), d = 0.5 * (omega_max - omega_min);
+  for (int32_t l = 0; l < L; ++l) {
+    const double t = l * tau;
+    double a = 0.0;
+    switch (kind) {
+      case KF_WINDOW_INDICATOR:
+        // eq. weightf
+        a = l == 0 ? 2.0 * (omega_max - omega_min) / pi
+                   : 4.0 / (pi * t) * std::sin(0.5 * t * (omega_max - omega_min)) * std::cos(0.5 * t * (omega_max + omega_min));
+        break;
+      case KF_WINDOW_TRIANGLE: {
+        // transform of max(0, 1 - |omega - c| / h) (+ its mirror image)
+        const double h = width * d;
+        const double x = 0.5 * h * t;
+        const double sn = x == 0.0 ? 1.0 : std::sin(x) / x;
+        a = 2.0 / pi * h * std::cos(c * t) * sn * sn;
+        break;
+      }
+      case KF_WINDOW_GAUSSIAN: {
+        // transform of exp(-(omega - c)^2 / (2 sigma^2)) (+ its mirror image)
+        const double sigma = width * d / std::sqrt(2.0 * std::log(2.0));
+        a = 2.0 / pi * sigma * std::sqrt(2.0 * pi) * std::exp(-0.5 * sigma * sigma * t * t) * std::cos(c * t);
+        break;
+      }
+      default:
+        return fail(KF_EINVAL, "kf_window_weights: unknown kind");
+    }
+    w_out[l] = tau * a;
+  }
+  return KF_OK;
+}
+
+int kf_notch_weights(const double* w, int32_t L, double tau, const double* omega, int32_t k, double* w_out) {
+  if (!w || !w_out || (k > 0 && !omega)) return fail(KF_EINVAL, "kf_notch_weights: NULL argument");
+  if (L < 1 || k < 0 || k > 64 || k > L) return fail(KF_EINVAL, "kf_notch_weights: need L >= 1 and 0 <= k <= min(64, L)");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(KF_EINVAL, "kf_notch_weights: tau must be positive");
+  for (int32_t l = 0; l < L; ++l)
+    if (!std::isfinite(w[l])) return fail(KF_EINVAL, "kf_notch_weights: non-finite weight");
+  // Q[j][l] = q_l(omega_j) by the scalar recurrence (Section 2.3), so that
+  // beta~(omega_j) = (Q w)_j (Lemma 2.3)
+  std::vector<double> Q((size_t)k * L);
+  for (int32_t j = 0; j < k; ++j) {
+    if (!std::isfinite(omega[j])) return fail(KF_EINVAL, "kf_notch_weights: non-finite frequency");
+    const double f = 2.0 - tau * tau * omega[j] * omega[j];
+    double qm = 1.0, q = 1.0;
+    for (int32_t l = 0; l < L; ++l) {
+      Q[(size_t)j * L + l] = q;
+      const double qn = f * q - qm;
+      qm = q;
+      q = qn;
+    }
+  }
+  // w_out = w - Q^T (Q Q^T)^{-1} Q w: the nearest weights (2-norm) with
+  // beta~(omega_j) = 0; Q Q^T solved by Cholesky
+  std::vector<double> G((size_t)k * k), r((size_t)k);
+  for (int32_t i = 0; i < k; ++i) {
+    double acc = 0.0;
+    for (int32_t l = 0; l < L; ++l) acc += Q[(size_t)i * L + l] * w[l];
+    r[(size_t)i] = acc;
+    for (int32_t j = 0; j <= i; ++j) {
+      double g = 0.0;
+      for (int32_t l = 0; l < L; ++l) g += Q[(size_t)i * L + l] * Q[(size_t)j * L + l];
+      G[(size_t)i * k + j] = G[(size_t)j * k + i] = g;
+    }
+  }
+  for (int32_t j = 0; j < k; ++j) {
+    double dj = G[(size_t)j * k + j];
+    for (int32_t q = 0; q < j; ++q) dj -= G[(size_t)j * k + q] * G[(size_t)j * k + q];
+    if (!(dj > 1e-13 * G[(size_t)j * k + j]))
+      return fail(KF_EINVAL, "kf_notch_weights: the notch constraints are (nearly) dependent");
+    dj = std::sqrt(dj);
+    G[(size_t)j * k + j] = dj;
+    for (int32_t i = j + 1; i < k; ++i) {
+      double v = G[(size_t)i * k + j];
+      for (int32_t q = 0; q < j; ++q) v -= G[(size_t)i * k + q] * G[(size_t)j * k + q];
+      G[(size_t)i * k + j] = v / dj;
+    }
+  }
+  for (int32_t i = 0; i < k; ++i) {  // forward: L y = r
+    double v = r[(size_t)i];
+    for (int32_t q = 0; q < i; ++q) v -= G[(size_t)i * k + q] * r[(size_t)q];
+    r[(size_t)i] = v / G[(size_t)i * k + i];
+  }
+  for (int32_t i = k - 1; i >= 0; --i) {  // backward: L^T c = y
+    double v = r[(size_t)i];
+    for (int32_t q = i + 1; q < k; ++q) v -= G[(size_t)q * k + i] * r[(size_t)q];
+    r[(size_t)i] = v / G[(size_t)i * k + i];
+  }
+  for (int32_t l = 0; l < L; ++l) {
+    double v = w[l];
+    for (int32_t j = 0; j < k; ++j) v -= Q[(size_t)j * L + l] * r[(size_t)j];
+    w_out[l] = v;
+  }
   return KF_OK;
 }
 
@@ -1599,6 +1786,7 @@ struct SolveState {
   int cur = 0, q0 = 0, qn = 0, prev0 = 0, pending = 0;
   int iters = 0, full_passes = 0, checked_at = -1, next_check = 0, target = 0;
   int64_t lf_steps = 0;
+  int64_t ref_lf_steps = 0;  // vector time steps of the mixed-mode refinement
   bool breakdown = false, done = false, rr_pending = false, timed_filter = false;
   double wsum = 0, t0 = 0, t_lf = 0, t_gs = 0, t_rr = 0, t_ref = 0;
   CheckOut chk;
@@ -1612,6 +1800,15 @@ struct SolveState {
   // kf_solve: the next filter application may be queued before the host
   // has read this step's orthogonalisation (ahead_ok), and was (ahead_ready)
   bool ahead_ok = false, ahead_ready = false;
+  // operator and step buffers of the Krylov loop's filter (the stepping
+  // precision; float64 after an escalation)
+  const SellOp* Aop = nullptr;
+  StepBufs* sbop = nullptr;
+  const double* start = nullptr;  // the caller's start block (valid for the call)
+  bool escalated = false;
+  bool may_escalate = true;  // kf_solve_batch escalates members after the batched loop
+  bool wants_escalation = false;
+  double t_lf_own = 0.0;  // a batch member's own stepping time after an escalation
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -1680,7 +1877,8 @@ int solve_refine_now(kf_problem* p, SolveState& s) {
   if (s.rr_pending) KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
   s.rr_pending = false;
   KF_HIP(hipEventRecord(p->ev[3], st));
-  KF_TRY(refine_mixed(p, s.cur, s.tol, s.chk, p->opt.want_vectors != 0, s.fin, s.target, s.b));
+  KF_TRY(refine_mixed(p, s.cur, s.tol, s.chk, p->opt.want_vectors != 0, s.fin, &s.ref_lf_steps, s.target, s.b,
+                      s.margin));
   KF_HIP(hipEventRecord(p->ev[4], st));
   KF_HIP(hipEventSynchronize(p->ev[4]));
   KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_ref));
@@ -1688,6 +1886,8 @@ int solve_refine_now(kf_problem* p, SolveState& s) {
   ++s.refines;
   return KF_OK;
 }
+
+int load_start(kf_problem* p, SolveState& s, int* kept_out);
 
 int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, double tol, SolveState& s) {
   s = SolveState();
@@ -1708,28 +1908,11 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   hipStream_t st = p->st;
   KF_TRY(ensure_basis(p, m_max + s.bk));
   KF_TRY(ensure_misc(p));
-  const int32_t n = p->n;
-  // start block: row-major in host or device memory (the runtime tells them
-  // apart) -> V (scratch), checked there for non-finite entries (on the
-  // device, so a device block is never read by the host) -> B[:, 0:b]
-  KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyDefault, st));
-  {
-    int32_t* fin = p->flags + 48;
-    int32_t hf = 0;
-    KF_HIP(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
-    KF_TRY(nonfinite_flag((int64_t)n * b, p->V, fin, st));
-    Readback rb(p);
-    KF_TRY(rb.get(&hf, fin, sizeof(int32_t)));
-    KF_HIP(hipStreamSynchronize(st));
-    rb.land();
-    if (hf) return fail(KF_EINVAL, "kf_solve: non-finite start block");
-  }
-  KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, p->ldb, st));
+  s.Aop = &p->A;
+  s.sbop = &p->sb;
+  s.start = start;
   int kept = 0;
-  KF_HIP(hipEventRecord(p->ev[1], st));
-  KF_TRY(orth_block(p, 0, 0, b, &kept, s.ref, p->ev[2]));
-  KF_TRY(elapsed_acc(p->ev[1], p->ev[2], s.t_gs));
-  if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
+  KF_TRY(load_start(p, s, &kept));
   // Mixed precision: float32 time stepping leaves a residual floor of about
   // eps32 * lambda_max / omega^2 (lambda_max <= 4/tau^2 by the CFL bound); the
   // Krylov loop accepts at ten times that floor and the float64 refinement
@@ -1748,6 +1931,76 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   // k columns hold at most k Ritz pairs: no check can meet the target earlier
   s.next_check = std::max(s.target, 0);
   for (double v : p->w) s.wsum += std::fabs(v);
+  return KF_OK;
+}
+
+// The caller's start block (row-major in host or device memory; the runtime
+// tells them apart) -> V (scratch), checked there for non-finite entries (on
+// the device, so a device block is never read by the host) -> B[:, 0:b],
+// M-orthonormalised; *kept receives the columns kept.
+int load_start(kf_problem* p, SolveState& s, int* kept_out) {
+  hipStream_t st = p->st;
+  const int32_t n = p->n;
+  const int b = s.b;
+  const double* start = s.start;
+  KF_HIP(hipMemcpyAsync(p->V, start, sizeof(double) * n * b, hipMemcpyDefault, st));
+  {
+    int32_t* fin = p->flags + 48;
+    int32_t hf = 0;
+    KF_HIP(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+    KF_TRY(nonfinite_flag((int64_t)n * b, p->V, fin, st));
+    Readback rb(p);
+    KF_TRY(rb.get(&hf, fin, sizeof(int32_t)));
+    KF_HIP(hipStreamSynchronize(st));
+    rb.land();
+    if (hf) return fail(KF_EINVAL, "kf_solve: non-finite start block");
+  }
+  KF_TRY(launch_scale_copy(n, b, b, p->V, b, 1, 1.0, p->B, 1, p->ldb, st));
+  int kept = 0;
+  KF_HIP(hipEventRecord(p->ev[1], st));
+  KF_TRY(orth_block(p, 0, 0, b, &kept, s.ref, p->ev[2]));
+  KF_TRY(elapsed_acc(p->ev[1], p->ev[2], s.t_gs));
+  if (kept == 0) return fail(KF_EINVAL, "kf_solve: start block is zero");
+  *kept_out = kept;
+  return KF_OK;
+}
+
+// Mixed precision, when the float64 refinement misses the target although
+// the float32 loop had reached it at its own tolerance: float32 round-off
+// seeds, at every step, the directions of an eigenspace of multiplicity
+// above b that the start block cannot reach; their partial copies pollute
+// the Ritz vectors of the other eigenvalues along directions with the same
+// filter value, so neither more float64 filtering nor a float64 continuation
+// of this basis removes them.  The loop starts again from the start block
+// with float64 stepping (no further refinement).
+int escalate_restart(kf_problem* p, SolveState& s) {
+  s.escalated = true;
+  s.Aop = &p->A64;
+  s.sbop = &p->sb64;
+  s.refine = false;
+  s.tol_loop = s.tol;
+  s.margin = 0.0;
+  s.proj_every = std::min(p->opt.proj_every, 15);
+  s.since_proj = 0;
+  s.ahead_ready = false;
+  KF_TRY(tune_block(p, p->A64, p->sb64, s.bk));
+  int kept = 0;
+  KF_TRY(load_start(p, s, &kept));
+  s.cur = kept;
+  s.q0 = 0;
+  s.qn = kept;
+  s.prev0 = 0;
+  s.pending = kept;
+  s.checked_at = -1;
+  s.next_check = std::max(s.target, 0);
+  s.pred_k = -1;
+  s.pred_theta.clear();
+  s.pred_res.clear();
+  s.chk = CheckOut();
+  s.fin = CheckOut();
+  s.fin_at = -1;
+  s.next_refine = 0;
+  s.done = false;
   return KF_OK;
 }
 
@@ -1812,7 +2065,7 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   const int64_t ldb = p->ldb;
   const std::function<int()> ahead = [&]() -> int {
     KF_HIP(hipEventRecord(p->ev[5], st));
-    KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.cur * ldb, 1, ldb, s.bk, s.bk, p->B + (int64_t)cur1 * ldb, 1,
+    KF_TRY(run_filter(p, *s.Aop, *s.sbop, p->B + (int64_t)s.cur * ldb, 1, ldb, s.bk, s.bk, p->B + (int64_t)cur1 * ldb, 1,
                       ldb, s.bk, p->w));
     KF_HIP(hipEventRecord(p->ev[6], st));
     return KF_OK;
@@ -1873,7 +2126,21 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
         // still miss the requested tolerance
         KF_TRY(solve_refine_now(p, s));
         s.next_refine = (int)std::ceil(s.cur * 1.1);
-        if (distinct_count(s.fin.acc_theta, s.b) >= s.target || s.refines >= kMaxRefines) s.done = true;
+        const bool met = distinct_count(s.fin.acc_theta, s.b) >= s.target;
+        if (met) {
+          s.done = true;
+        } else if (p->opt.escalate) {
+          // missed: float32 round-off left pollution no refinement of this
+          // basis removes (see escalate_restart); the batch defers it
+          if (s.may_escalate) {
+            KF_TRY(escalate_restart(p, s));
+          } else {
+            s.wants_escalation = true;
+            s.done = true;
+          }
+        } else if (s.refines >= kMaxRefines) {
+          s.done = true;
+        }
       }
     }
   }
@@ -1881,9 +2148,65 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   return KF_OK;
 }
 
+// A library-owned result holding the accepted pairs of `fin` (host arrays).
+int new_result(kf_problem* p, const CheckOut& fin, kf_result** out) {
+  const int32_t n = p->n;
+  kf_result* r = (kf_result*)std::calloc(1, sizeof(kf_result));
+  if (!r) return fail(KF_ENOMEM, "kf: result allocation");
+  const int na = (int)fin.acc_theta.size();
+  r->n = n;
+  r->n_pairs = na;
+  r->omega2 = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->omega = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->residual = (double*)std::malloc(sizeof(double) * std::max(na, 1));
+  r->n_ritz = (int)fin.ritz.size();
+  r->ritz = (double*)std::malloc(sizeof(double) * std::max(r->n_ritz, 1));
+  if (!r->omega2 || !r->omega || !r->residual || !r->ritz) {
+    kf_result_free(r);
+    return fail(KF_ENOMEM, "kf: result allocation");
+  }
+  for (int i = 0; i < na; ++i) {
+    r->omega2[i] = fin.acc_theta[(size_t)i];
+    r->omega[i] = std::sqrt(std::max(fin.acc_theta[(size_t)i], 0.0));
+    r->residual[i] = fin.acc_res[(size_t)i];
+  }
+  if (r->n_ritz) std::memcpy(r->ritz, fin.ritz.data(), sizeof(double) * r->n_ritz);
+  if (p->opt.want_vectors && na > 0) {
+    r->vectors = (double*)std::malloc(sizeof(double) * (size_t)n * na);
+    if (!r->vectors) {
+      kf_result_free(r);
+      return fail(KF_ENOMEM, "kf: vector allocation");
+    }
+    std::memcpy(r->vectors, fin.vectors.data(), sizeof(double) * (size_t)n * na);
+  }
+  *out = r;
+  return KF_OK;
+}
+
+// The Krylov loop of one problem on its own stream (kf_solve, and members
+// of a batch solved on their own after an escalation).
+int solve_loop(kf_problem* p, SolveState& s) {
+  s.timed_filter = true;
+  s.ahead_ok = true;
+  const int64_t ldb = p->ldb;
+  while (solve_wants_filter(p, s)) {
+    if (s.ahead_ready) {
+      // queued during the previous step's orthogonalisation (same input
+      // column q0, same output column cur)
+      s.ahead_ready = false;
+    } else {
+      KF_HIP(hipEventRecord(p->ev[0], p->st));
+      KF_TRY(run_filter(p, *s.Aop, *s.sbop, p->B + (int64_t)s.q0 * ldb, 1, ldb, s.qn, s.bk,
+                        p->B + (int64_t)s.cur * ldb, 1, ldb, s.bk, p->w));
+      KF_HIP(hipEventRecord(p->ev[1], p->st));
+    }
+    KF_TRY(solve_after_filter(p, s));
+  }
+  return KF_OK;
+}
+
 int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   hipStream_t st = p->st;
-  const int32_t n = p->n;
   const int b = s.b;
   CheckOut& chk = s.chk;
   if (s.checked_at != s.cur) KF_TRY(solve_check_now(p, s));
@@ -1912,34 +2235,8 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   const int64_t lf_steps = s.lf_steps;
   const double t_lf = s.t_lf, t_gs = s.t_gs, t_rr = s.t_rr, t_ref = s.t_ref, t0 = s.t0;
   const int full_passes = s.full_passes;
-  kf_result* r = (kf_result*)std::calloc(1, sizeof(kf_result));
-  if (!r) return fail(KF_ENOMEM, "kf_solve: result allocation");
-  const int na = (int)fin.acc_theta.size();
-  r->n = n;
-  r->n_pairs = na;
-  r->omega2 = (double*)std::malloc(sizeof(double) * std::max(na, 1));
-  r->omega = (double*)std::malloc(sizeof(double) * std::max(na, 1));
-  r->residual = (double*)std::malloc(sizeof(double) * std::max(na, 1));
-  r->n_ritz = (int)fin.ritz.size();
-  r->ritz = (double*)std::malloc(sizeof(double) * std::max(r->n_ritz, 1));
-  if (!r->omega2 || !r->omega || !r->residual || !r->ritz) {
-    kf_result_free(r);
-    return fail(KF_ENOMEM, "kf_solve: result allocation");
-  }
-  for (int i = 0; i < na; ++i) {
-    r->omega2[i] = fin.acc_theta[(size_t)i];
-    r->omega[i] = std::sqrt(std::max(fin.acc_theta[(size_t)i], 0.0));
-    r->residual[i] = fin.acc_res[(size_t)i];
-  }
-  std::memcpy(r->ritz, fin.ritz.data(), sizeof(double) * r->n_ritz);
-  if (p->opt.want_vectors && na > 0) {
-    r->vectors = (double*)std::malloc(sizeof(double) * (size_t)n * na);
-    if (!r->vectors) {
-      kf_result_free(r);
-      return fail(KF_ENOMEM, "kf_solve: vector allocation");
-    }
-    std::memcpy(r->vectors, fin.vectors.data(), sizeof(double) * (size_t)n * na);
-  }
+  kf_result* r = nullptr;
+  KF_TRY(new_result(p, fin, &r));
   r->krylov_steps = iters;
   r->basis_size = cur;
   r->breakdown = breakdown ? 1 : 0;
@@ -1951,6 +2248,8 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   r->t_refine = t_ref;
   r->orth_error = chk.orth;
   r->full_passes = full_passes;
+  r->refine_vector_steps = s.ref_lf_steps;
+  r->escalated = s.escalated ? 1 : 0;
   KF_HIP(hipStreamSynchronize(st));
   r->t_total = now_s() - t0;
   *out = r;
@@ -1968,23 +2267,80 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   if (!p) return fail(KF_EINVAL, "kf_solve: NULL argument");
   SolveState s;
   KF_TRY(solve_begin(p, start, b, m_max, tol, s));
-  s.timed_filter = true;
-  s.ahead_ok = true;
-  const int64_t ldb = p->ldb;
-  while (solve_wants_filter(p, s)) {
-    if (s.ahead_ready) {
-      // queued during the previous step's orthogonalisation (same input
-      // column q0, same output column cur)
-      s.ahead_ready = false;
-    } else {
-      KF_HIP(hipEventRecord(p->ev[0], p->st));
-      KF_TRY(run_filter(p, p->A, p->sb, p->B + (int64_t)s.q0 * ldb, 1, ldb, s.qn, s.bk, p->B + (int64_t)s.cur * ldb,
-                        1, ldb, s.bk, p->w));
-      KF_HIP(hipEventRecord(p->ev[1], p->st));
-    }
-    KF_TRY(solve_after_filter(p, s));
-  }
+  KF_TRY(solve_loop(p, s));
   return solve_finish(p, s, out);
+}
+
+int kf_subspace_solve(kf_problem* p, const double* start, int32_t ncols, int32_t max_iters, double tol,
+                      kf_result** out) {
+  if (!out) return fail(KF_EINVAL, "kf_subspace_solve: NULL argument");
+  *out = nullptr;
+  if (!p || !start) return fail(KF_EINVAL, "kf_subspace_solve: NULL argument");
+  if (ncols < 1 || ncols > 2048) return fail(KF_EINVAL, "kf_subspace_solve: ncols must lie in [1, 2048]");
+  if (max_iters < 1) return fail(KF_EINVAL, "kf_subspace_solve: max_iters must be >= 1");
+  if (!(tol > 0)) return fail(KF_EINVAL, "kf_subspace_solve: tol must be positive");
+  const double t0 = now_s();
+  hipStream_t st = p->st;
+  const int32_t n = p->n;
+  KF_TRY(ensure_basis(p, 16));
+  KF_TRY(ensure_misc(p));
+  KF_TRY(ensure_refine(p, ncols, ncols));
+  // start block: row-major in host or device memory -> Yy (contiguous),
+  // checked for non-finite entries, then into Vx column by column
+  KF_HIP(hipMemcpyAsync(p->Yy, start, sizeof(double) * (size_t)n * ncols, hipMemcpyDefault, st));
+  {
+    int32_t* fin = p->flags + 48;
+    int32_t hf = 0;
+    KF_HIP(hipMemsetAsync(fin, 0, sizeof(int32_t), st));
+    KF_TRY(nonfinite_flag((int64_t)n * ncols, p->Yy, fin, st));
+    KF_HIP(hipMemcpyAsync(&hf, fin, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KF_HIP(hipStreamSynchronize(st));
+    if (hf) return fail(KF_EINVAL, "kf_subspace_solve: non-finite start block");
+  }
+  KF_TRY(launch_scale_copy(n, ncols, ncols, p->Yy, ncols, 1, 1.0, p->Vx, 1, p->ldb, st));
+  double* X = p->Vx;
+  double* Q = p->Yy;
+  const bool mixed = p->opt.precision == KF_MIXED;
+  const bool has64 = p->A64.val != nullptr;
+  const int target = p->opt.target;
+  SubspaceStats s32, s64;
+  CheckOut chk;
+  int used = 0;
+  if (mixed) {
+    // float32 stepping until the pairs reach the float32 floor
+    // (eps32 * lambda_max / omega^2, lambda_max <= 4/tau^2), then, when a
+    // float64 operator is kept (refine != 0), float64 stepping to tol
+    const double floor32 = 5.96e-8 * 4.0 / (p->tau * p->tau) / std::max(p->omega_min * p->omega_min, 1e-300);
+    const double tol32 = has64 ? std::max(tol, std::min(1e-3, 10.0 * floor32)) : tol;
+    KF_TRY(subspace_iterate(p, p->A, p->sb, X, Q, ncols, max_iters, tol32, target, ncols, 0.0,
+                            has64 ? false : p->opt.want_vectors != 0, chk, s32));
+    used = s32.iters;
+    if (has64 && used < max_iters && s32.dim > 0)
+      KF_TRY(subspace_iterate(p, p->A64, p->sb64, X, Q, s32.dim, max_iters - used, tol, target, ncols, 0.0,
+                              p->opt.want_vectors != 0, chk, s64));
+  } else {
+    KF_TRY(subspace_iterate(p, p->A, p->sb, X, Q, ncols, max_iters, tol, target, ncols, 0.0,
+                            p->opt.want_vectors != 0, chk, s64));
+  }
+  const int iters = s32.iters + s64.iters;
+  int inside = 0, accepted = (int)chk.acc_theta.size();
+  const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
+  for (double t : chk.cand_theta) inside += (t >= lo2 && t <= hi2) ? 1 : 0;
+  kf_result* r = nullptr;
+  KF_TRY(new_result(p, chk, &r));
+  r->krylov_steps = iters;
+  r->basis_size = (s64.iters ? s64.dim : s32.dim);
+  r->status = (target > 0 ? accepted < target : accepted < inside || inside == 0) ? KF_ENOTCONV : KF_OK;
+  r->leapfrog_vector_steps = s32.lf_steps + s64.lf_steps;
+  r->refine_vector_steps = mixed ? s64.lf_steps : 0;
+  r->t_leapfrog = s32.t_lf + s64.t_lf;
+  r->t_gs = s32.t_orth + s64.t_orth;
+  r->t_rr = s32.t_rr + s64.t_rr;
+  r->t_refine = mixed ? s64.t_lf + s64.t_orth + s64.t_rr : 0.0;
+  KF_HIP(hipStreamSynchronize(st));
+  r->t_total = now_s() - t0;
+  *out = r;
+  return KF_OK;
 }
 
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols) {
@@ -2240,6 +2596,7 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
       set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
       return rc;
     }
+    S[(size_t)q].may_escalate = false;
   }
   const int bk = pow2ceil(b);
   double t_lf = 0.0;
@@ -2309,8 +2666,29 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
     }
     KF_TRY(elapsed_acc(bt->ev[0], bt->ev[1], t_lf));
   }
+  // members whose float64 refinement missed the target: their own float64
+  // Krylov loop from the start block (see escalate_restart), one member after
+  // another on its own stream, outside the batched stepping
+  double t_esc = 0.0;
   for (int q = 0; q < bt->P; ++q) {
-    S[(size_t)q].t_lf = t_lf;  // the batched stepping time, shared by all members
+    SolveState& s = S[(size_t)q];
+    if (!s.wants_escalation) continue;
+    kf_problem* p = bt->probs[(size_t)q];
+    const double te = now_s();
+    s.may_escalate = true;
+    s.t_lf = 0.0;
+    int rc = escalate_restart(p, s);
+    if (!rc) rc = solve_loop(p, s);
+    if (rc) {
+      set_error("kf_solve_batch: problem " + std::to_string(q) + " (float64 restart): " + kf_last_error());
+      return rc;
+    }
+    s.t_lf_own = s.t_lf;
+    t_esc += now_s() - te;
+  }
+  (void)t_esc;
+  for (int q = 0; q < bt->P; ++q) {
+    S[(size_t)q].t_lf = t_lf + S[(size_t)q].t_lf_own;  // the batched stepping time, shared by all members
     int rc = solve_finish(bt->probs[(size_t)q], S[(size_t)q], &results[q]);
     if (rc) {
       for (int r = 0; r < q; ++r) {

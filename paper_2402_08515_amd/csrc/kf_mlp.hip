@@ -560,6 +560,23 @@ int kf_mlp_train(kf_mlp* net, const double* samples, int32_t n, const int32_t* o
   return KF_OK;
 }
 
+int kf_mlp_weights(kf_mlp* net, const double* samples, int32_t n, double* w_out) {
+  if (!net || !samples || !w_out || n < 1) return mfail(KF_EINVAL, "kf_mlp_weights: bad arguments");
+  // padded to a multiple of 64 rows by repeating the last sample
+  const int np = (n + 63) / 64 * 64;
+  std::vector<double> rep((size_t)4 * np);
+  std::memcpy(rep.data(), samples, sizeof(double) * 4 * (size_t)n);
+  for (int i = n; i < np; ++i) std::memcpy(&rep[4 * (size_t)i], samples + 4 * (size_t)(n - 1), sizeof(double) * 4);
+  KF_TRY(ensure_batch(net, np));
+  KF_TRY(upload_samples(net, rep.data(), np));
+  KF_TRY(fwd_bwd(net, np, nullptr, true, false, nullptr));
+  std::vector<float> wl((size_t)n * kLM);
+  KF_HIP(hipMemcpyAsync(wl.data(), net->w, sizeof(float) * wl.size(), hipMemcpyDeviceToHost, net->st));
+  KF_HIP(hipStreamSynchronize(net->st));
+  for (size_t i = 0; i < wl.size(); ++i) w_out[i] = wl[i];
+  return KF_OK;
+}
+
 int kf_weights_from_mlp(kf_mlp* net, double omega_min, double omega_max, double tau, double lambda_max, int32_t L,
                         double* w_out, int32_t* used_learned, double* j_learned, double* j_fourier) {
   if (!net || !w_out || !used_learned) return mfail(KF_EINVAL, "kf_weights_from_mlp: NULL argument");

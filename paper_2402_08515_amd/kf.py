@@ -54,6 +54,7 @@ class OptionsT(C.Structure):
         ("reorth_tol", C.c_double),
         ("proj_every", C.c_int32),
         ("refine", C.c_int32),
+        ("escalate", C.c_int32),
         ("want_vectors", C.c_int32),
         ("index_bytes", C.c_int32),
         ("xcd_remap", C.c_int32),
@@ -89,6 +90,8 @@ class ResultT(C.Structure):
         ("t_refine", C.c_double),
         ("orth_error", C.c_double),
         ("full_passes", C.c_int32),
+        ("refine_vector_steps", C.c_int64),
+        ("escalated", C.c_int32),
     ]
 
 
@@ -122,10 +125,15 @@ _SIGNATURES = {
     ),
     "kf_time_step_rule": (C.c_int, [C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "kf_filter_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "kf_window_weights": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                    C.c_void_p]),
+    "kf_notch_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p]),
     "kf_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_apply_filter_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.POINTER(ResultT))]),
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
+    "kf_subspace_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double,
+                                    C.POINTER(C.POINTER(ResultT))]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "kf_sym_eig": (C.c_int, [C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int32),
                              C.c_void_p, C.c_void_p]),
@@ -143,6 +151,7 @@ _SIGNATURES = {
     "kf_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
     "kf_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_double,
                                C.c_void_p]),
+    "kf_mlp_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "kf_weights_from_mlp": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
                                       C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
@@ -215,6 +224,26 @@ def sym_eig(A, lo: float = 0.0, hi: float = -1.0, vectors: bool = False):
     return theta
 
 
+WINDOWS = {"indicator": 0, "triangle": 1, "gaussian": 2}
+
+
+def window_weights(kind: str, omega_min: float, omega_max: float, tau: float, L: int, width: float = 1.0):
+    """Filter coefficients tau*alpha(l tau), l < L, of an analytic window."""
+    out = np.empty(int(L))
+    _check(lib().kf_window_weights(WINDOWS[kind], float(omega_min), float(omega_max), float(tau), int(L),
+                                   float(width), _ptr(out)))
+    return out
+
+
+def notch_weights(w, tau: float, omegas):
+    """The weights nearest to w whose filter vanishes at the given omegas."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    om = np.ascontiguousarray(np.atleast_1d(omegas), dtype=np.float64)
+    out = np.empty_like(w)
+    _check(lib().kf_notch_weights(_ptr(w), int(w.size), float(tau), _ptr(om), int(om.size), _ptr(out)))
+    return out
+
+
 def time_step_rule(lambda_est: float, omega_min: float, safety: float = 0.9):
     tau = C.c_double()
     L = C.c_int32()
@@ -250,6 +279,8 @@ class SolveResult:
     t_refine: float
     orth_error: float
     full_passes: int
+    refine_vector_steps: int
+    escalated: bool
 
 
 def _take_result(res, n: int) -> SolveResult:
@@ -278,15 +309,17 @@ def _take_result(res, n: int) -> SolveResult:
             t_refine=r.t_refine,
             orth_error=r.orth_error,
             full_passes=r.full_passes,
+            refine_vector_steps=r.refine_vector_steps,
+            escalated=bool(r.escalated),
         )
     finally:
         lib().kf_result_free(res)
 
 
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
-             drop_tol=1e-10, refine=2, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
+             drop_tol=1e-10, refine=None, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
              autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0,
-             block_band=0):
+             block_band=0, escalate=None):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -300,7 +333,10 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
         opt.reorth_tol = reorth_tol
     if proj_every is not None:
         opt.proj_every = proj_every
-    opt.refine = int(refine)
+    if refine is not None:
+        opt.refine = int(refine)
+    if escalate is not None:
+        opt.escalate = int(escalate)
     opt.want_vectors = int(want_vectors)
     opt.index_bytes = index_bytes
     opt.xcd_remap = int(xcd_remap)
@@ -459,6 +495,23 @@ class Problem:
         _check(lib().kf_solve(self._h, ptr, b, int(m_max), float(tol), C.byref(res)))
         return _take_result(res, self.n)
 
+    def subspace_solve(self, start, max_iters: int, tol: float) -> SolveResult:
+        """Fixed-dimension filtered subspace iteration from the n x ncols block
+        start (host array or contiguous CUDA tensor, float64)."""
+        if isinstance(start, torch.Tensor) and start.is_cuda:
+            X0 = start if start.dim() == 2 else start[:, None]
+            if X0.dtype != torch.float64 or not X0.is_contiguous() or X0.shape[0] != self.n:
+                raise ValueError("start must be a contiguous float64 tensor with n rows")
+            ptr, nc = X0.data_ptr(), int(X0.shape[1])
+        else:
+            X0 = np.ascontiguousarray(start, dtype=np.float64)
+            if X0.ndim == 1:
+                X0 = X0[:, None]
+            ptr, nc = _ptr(X0), int(X0.shape[1])
+        res = C.POINTER(ResultT)()
+        _check(lib().kf_subspace_solve(self._h, ptr, nc, int(max_iters), float(tol), C.byref(res)))
+        return _take_result(res, self.n)
+
     def basis(self, max_cols: int) -> np.ndarray:
         out = np.empty((max_cols, self.n))
         nc = C.c_int32()
@@ -511,6 +564,13 @@ class Mlp:
         _check(lib().kf_mlp_train(self._h, _ptr(s), int(s.shape[0]), _ptr(o), int(epochs), int(batch), float(lr),
                                   _ptr(hist)))
         return hist
+
+    def batch_weights(self, samples) -> np.ndarray:
+        """The network's weights (n x 512, no gate) for n sample rows."""
+        s = np.ascontiguousarray(samples, dtype=np.float64)
+        out = np.empty((s.shape[0], 512))
+        _check(lib().kf_mlp_weights(self._h, _ptr(s), int(s.shape[0]), _ptr(out)))
+        return out
 
     def weights(self, omega_min, omega_max, tau, lambda_max, L):
         w = np.empty(int(L))
