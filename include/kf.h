@@ -169,6 +169,16 @@ typedef struct kf_options {
                             gathers from the caches; 0 = timed with
                             lanes_per_row when autotune is on (else from the
                             caches).  Other values: KF_EINVAL */
+  int32_t stepper;       /* time-stepping scheme (Remark 2.4, Section 4.2: any
+                            explicit scheme that is a function of M^{-1} S):
+                            2 = leapfrog, eq. 2stepmethod (stable for
+                            tau omega_max < 2); 4 = its fourth-order variant
+                            y+ = 2y - y- - A y + A^2 y / 12, A = tau^2 M^{-1} S
+                            (two products with S per step, stable for
+                            tau omega_max < sqrt(12)); 0 = 2.  The filter of
+                            Lemma 2.3 uses the scheme's scalar recurrence
+                            (factor 2 - x + x^2/12, x = tau^2 omega^2, for 4).
+                            Batches: 2 only */
   void* stream;          /* hipStream_t */
 } kf_options;
 
@@ -212,7 +222,7 @@ typedef struct kf_result {
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0.3, three-term
  * orthogonalisation (full_reorth 0), no target, no cap,
- * drop_tol 1e-10, reorth_tol 1e-9, proj_every 12, refine 8, escalate 1, no vectors, automatic index width, XCD remap on,
+ * drop_tol 1e-10, reorth_tol 1e-9, proj_every 12, refine 8, escalate 1, stepper 2, no vectors, automatic index width, XCD remap on,
  * cached operator loads, no autotuning, lanes_per_row 0,
  * default stream. */
 void kf_default_options(kf_options* opt);
@@ -371,6 +381,23 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
  * KF_EUNSTABLE, KF_EHIP. */
 int kf_subspace_solve(kf_problem* p, const double* start, int32_t ncols, int32_t max_iters, double tol,
                       kf_result** out);
+
+/* The end time T = L tau by experiment.  Section 3.1.3 shows that a longer
+ * T separates the sought eigenvalues better and needs fewer Krylov steps but
+ * not always fewer time steps in total, and that the filter alone does not
+ * predict which T is cheaper; the conclusion notes that the method's
+ * parameters can be optimised experimentally at negligible cost next to
+ * repeated solves.  For each of the n_cand step counts L_cand[c] (>= 1) the
+ * problem is created with opt (opt->target should be set) and solved from
+ * start (as kf_solve: n x b row-major, host or device memory); *L_best
+ * receives the L whose solve met the target in the shortest time.
+ * seconds[c] and krylov_steps[c] (optional, n_cand entries) receive each
+ * solve's time (-1 when the target was missed) and filter applications.
+ * Errors: as kf_create and kf_solve; KF_ENOTCONV when no candidate met the
+ * target. */
+int kf_tune_steps(const kf_csr* S, const double* m_diag, double omega_min, double omega_max, double tau,
+                  const int32_t* L_cand, int32_t n_cand, const double* start, int32_t b, int32_t m_max, double tol,
+                  const kf_options* opt, int32_t* L_best, double* seconds, int32_t* krylov_steps);
 
 /* Release a result (NULL accepted). */
 int kf_result_free(kf_result* r);

@@ -40,6 +40,7 @@ struct StepBufs {
   void* Y0 = nullptr;
   void* Y1 = nullptr;
   void* R = nullptr;
+  void* Z = nullptr;  // fourth-order stepper: z = A y
   int cap = 0;  // block width held
   int vb = 0;   // value bytes
 };
@@ -274,14 +275,16 @@ void dfree(void* p) {
 }
 
 int ensure_step_buffers(kf_problem* p, StepBufs& sb, int bk, int vb) {
-  if (sb.cap >= bk && sb.vb == vb) return KF_OK;
+  const bool needz = p->opt.stepper == 4;
+  if (sb.cap >= bk && sb.vb == vb && (!needz || sb.Z)) return KF_OK;
   dfree(sb.Y0);
   dfree(sb.Y1);
   dfree(sb.R);
+  dfree(sb.Z);
   sb = StepBufs();
   const size_t bytes = (size_t)p->n * bk * vb;
   if (hipMalloc(&sb.Y0, bytes) != hipSuccess || hipMalloc(&sb.Y1, bytes) != hipSuccess ||
-      hipMalloc(&sb.R, bytes) != hipSuccess)
+      hipMalloc(&sb.R, bytes) != hipSuccess || (needz && hipMalloc(&sb.Z, bytes) != hipSuccess))
     return fail(KF_ENOMEM, "kf: time-stepping buffers");
   sb.cap = bk;
   sb.vb = vb;
@@ -315,18 +318,21 @@ int scratch_address(void** out) {
   return KF_OK;
 }
 
-// The three n x bk time-stepping blocks carved out of the scratch array.
-int scratch_step_buffers(int32_t n, int bk, int vb, StepBufs& sb) {
+// The n x bk time-stepping blocks (three, four for the fourth-order
+// stepper) carved out of the scratch array.
+int scratch_step_buffers(int32_t n, int bk, int vb, StepBufs& sb, int nbuf = 3) {
   const size_t one = ((size_t)n * bk * vb + 255) / 256 * 256;
-  if (3 * one > kScratchBytes)
-    return fail(KF_EINVAL, "kf_apply_filter_noalloc: 3 x n x " + std::to_string(bk) + " x " + std::to_string(vb) +
-                               " bytes exceed the fixed " + std::to_string(kScratchBytes >> 20) + " MiB");
+  if (nbuf * one > kScratchBytes)
+    return fail(KF_EINVAL, "kf_apply_filter_noalloc: " + std::to_string(nbuf) + " x n x " + std::to_string(bk) +
+                               " x " + std::to_string(vb) + " bytes exceed the fixed " +
+                               std::to_string(kScratchBytes >> 20) + " MiB");
   void* base = nullptr;
   KF_TRY(scratch_address(&base));
   char* c = static_cast<char*>(base);
   sb.Y0 = c;
   sb.Y1 = c + one;
   sb.R = c + 2 * one;
+  sb.Z = nbuf > 3 ? c + 3 * one : nullptr;
   sb.cap = bk;
   sb.vb = vb;
   return KF_OK;
@@ -336,6 +342,7 @@ void free_step_buffers(StepBufs& sb) {
   dfree(sb.Y0);
   dfree(sb.Y1);
   dfree(sb.R);
+  dfree(sb.Z);
   sb = StepBufs();
 }
 
@@ -350,7 +357,7 @@ int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, 
   if (L == 1) return launch_scale_copy(p->n, bout, std::min(bsrc, bout), src, srs, scs, w[0], dst, drs, dcs, st);
   if (may_alloc) {
     KF_TRY(ensure_step_buffers(p, sb, bk, A.val_bytes));
-  } else if (sb.cap < bk || sb.vb != A.val_bytes || !sb.Y0 || !sb.Y1 || !sb.R) {
+  } else if (sb.cap < bk || sb.vb != A.val_bytes || !sb.Y0 || !sb.Y1 || !sb.R || (p->opt.stepper == 4 && !sb.Z)) {
     return fail(KF_EINVAL, "kf: time-stepping buffers too small");
   }
   // a single float64 vector stored contiguously already has the layout of a
@@ -368,8 +375,12 @@ int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, 
     const void* cur = l == 1 ? y0 : Y[l & 1];
     void* nxt = Y[(l + 1) & 1];
     const void* prv = l == 2 ? y0 : nxt;
-    KF_TRY(launch_leapfrog(A, bk, sp.mode, cur, prv, nxt, sb.R, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic), wt(sp.in),
-                           p->opt.xcd_remap, st));
+    if (p->opt.stepper == 4)
+      KF_TRY(launch_leapfrog4(A, bk, sp.mode, cur, prv, nxt, sb.R, sb.Z, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic),
+                              wt(sp.in), p->opt.xcd_remap, st));
+    else
+      KF_TRY(launch_leapfrog(A, bk, sp.mode, cur, prv, nxt, sb.R, dst, drs, dcs, bout, wt(sp.ip), wt(sp.ic),
+                             wt(sp.in), p->opt.xcd_remap, st));
   }
   return KF_OK;
 }
@@ -789,7 +800,9 @@ struct CheckOut {
 // ||S v|| and acceptance (theta inside the interval and residual <= tol).
 // ew.Y holds the k x nsel eigenvectors for sel.
 int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const std::vector<double>& sel_in, double tol,
-                   bool want_vectors, CheckOut& out, bool rayleigh = false) {
+                   bool want_vectors, CheckOut& out, bool rayleigh = false, const double* Ysel = nullptr) {
+  // Ysel: the k x sel eigenvectors (default: ew.Y)
+  if (!Ysel) Ysel = p->ew.Y;
   std::vector<double> sel = sel_in;
   hipStream_t st = p->st;
   const int nsel = (int)sel.size();
@@ -805,7 +818,7 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
   double* d_den = p->small + 2048 + 128;
   for (int c0 = 0; c0 < nsel; c0 += 64) {
     const int nc = std::min(64, nsel - c0);
-    KF_TRY(gemm_nn(p->n, k, Bk, ldb, p->ew.Y + (int64_t)c0 * k, k, p->V, p->n, nc, st));
+    KF_TRY(gemm_nn(p->n, k, Bk, ldb, Ysel + (int64_t)c0 * k, k, p->V, p->n, nc, st));
     KF_TRY(spmv_cols(p->S, p->V, p->n, p->SV, p->n, nc, nullptr, st));
     if (rayleigh) {
       // theta <- v^T S v / v^T M v for each Ritz vector
@@ -1046,13 +1059,14 @@ struct SubspaceStats {
 // On return X points at the last M-orthonormal block, st.dim its columns.
 int subspace_iterate(kf_problem* p, const SellOp& A, StepBufs& sb, double*& X, double*& Q, int nc, int max_iters,
                      double tol, int target, int cnt_b, double margin, bool want_vectors, CheckOut& out,
-                     SubspaceStats& stats) {
+                     SubspaceStats& stats, int stall_limit = 0) {
   hipStream_t st = p->st;
   const int n = p->n;
   const int64_t ld = p->ldb;
   const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
   const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
   int prev_inside = -1;
+  int best = -1, stalled = 0;
   int cur = nc;
   auto lap = [&](hipEvent_t a, hipEvent_t b, double& acc) -> int {
     KF_HIP(hipEventSynchronize(b));
@@ -1126,21 +1140,140 @@ int subspace_iterate(kf_problem* p, const SellOp& A, StepBufs& sb, double*& X, d
         if (!(out.cand_res[q] <= tol)) all = false;
       }
     }
-    if (target > 0 && distinct_count(out.acc_theta, cnt_b) >= target) break;
+    const int cnt = distinct_count(out.acc_theta, cnt_b);
+    if (target > 0 && cnt >= target) break;
     if (target <= 0 && inside > 0 && all && inside == prev_inside) break;
     prev_inside = inside;
+    // stall_limit > 0: stop once the accepted count has not grown for that
+    // many iterations
+    if (cnt > best) {
+      best = cnt;
+      stalled = 0;
+    } else if (stall_limit > 0 && ++stalled >= stall_limit) {
+      break;
+    }
   }
   stats.dim = cur;
   return KF_OK;
 }
 
+// The subspace iteration with locking (the mixed-precision refinement): Ritz
+// pairs accepted at tol (inside the interval) are kept in the space but no
+// longer filtered; every other Ritz vector of the space stays active, so the
+// dimension is kept.  X holds [locked | active] (nl + na columns, leading
+// dimension ldb) on entry (nl = 0) and between iterations.  One iteration:
+//   Q = [locked | C active], the filtered part made M-orthogonal to the
+//   locked columns (classical Gram-Schmidt twice) and M-orthonormalised;
+//   Rayleigh-Ritz on span(Q) (all Ritz vectors), residuals for the Ritz
+//   values in the interval widened by `margin`;
+//   X = [accepted Ritz vectors | all other Ritz vectors].
+int subspace_iterate_locked(kf_problem* p, const SellOp& A, StepBufs& sb, int nc, int max_iters, double tol,
+                            int target, int cnt_b, double margin, bool want_vectors, CheckOut& out,
+                            SubspaceStats& stats, int stall_limit) {
+  hipStream_t st = p->st;
+  const int n = p->n;
+  const int64_t ld = p->ldb;
+  double* X = p->Vx;
+  double* Q = p->Yy;
+  const double lo = std::max(p->omega_min - margin, 0.0), hi = p->omega_max + margin;
+  const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
+  int nl = 0, na = nc, best = -1, stalled = 0;
+  auto lap = [&](hipEvent_t a, hipEvent_t b, double& acc) -> int {
+    KF_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    KF_HIP(hipEventElapsedTime(&ms, a, b));
+    acc += 1e-3 * ms;
+    return KF_OK;
+  };
+  for (int it = 0; it < max_iters && na > 0; ++it) {
+    KF_HIP(hipEventRecord(p->sev[0], st));
+    for (int c0 = 0; c0 < na; c0 += 16) {
+      const int nb = std::min(16, na - c0);
+      KF_TRY(run_filter(p, A, sb, X + (int64_t)(nl + c0) * ld, 1, ld, nb, pow2ceil(nb), Q + (int64_t)(nl + c0) * ld, 1,
+                        ld, nb, p->w));
+    }
+    KF_HIP(hipEventRecord(p->sev[1], st));
+    stats.lf_steps += (int64_t)na * ((int64_t)p->w.size() - 1);
+    KF_TRY(lap(p->sev[0], p->sev[1], stats.t_lf));
+    ++stats.iters;
+    if (nl > 0) {
+      KF_TRY(copy_cols(n, X, ld, Q, ld, nl, st));
+      // the filtered columns against the locked ones, twice
+      for (int pass = 0; pass < 2; ++pass)
+        for (int c0 = 0; c0 < na; c0 += 32) {
+          const int nb = std::min(32, na - c0);
+          double* Qc = Q + (int64_t)(nl + c0) * ld;
+          KF_TRY(gemv_t(n, nl, Q, ld, nullptr, 0, 0, Qc, nb, ld, p->d_m, p->Ysel, nl, p->gw, st));
+          KF_TRY(gemv_n_sub(n, nl, Q, ld, p->Ysel, nl, Qc, ld, nb, st));
+        }
+    }
+    int r = 0, r2 = 0;
+    KF_TRY(eig_orthonormalise(p, Q + (int64_t)nl * ld, na, X + (int64_t)nl * ld, &r));
+    if (r > 0) KF_TRY(eig_orthonormalise(p, X + (int64_t)nl * ld, r, Q + (int64_t)nl * ld, &r2));
+    KF_HIP(hipEventRecord(p->sev[2], st));
+    KF_TRY(lap(p->sev[1], p->sev[2], stats.t_orth));
+    const int k = nl + r2;
+    if (k == 0) break;
+    // projected pencil on span(Q): S Q into X, H = Q^T S Q
+    for (int c0 = 0; c0 < k; c0 += 16) {
+      const int nb = std::min(16, k - c0);
+      KF_TRY(spmv_cols(p->S, Q + (int64_t)c0 * ld, ld, X + (int64_t)c0 * ld, ld, nb, nullptr, st));
+    }
+    for (int c0 = 0; c0 < k; c0 += 32) {
+      const int nb = std::min(32, k - c0);
+      KF_TRY(gemv_t(n, k, Q, ld, X + (int64_t)c0 * ld, nb, ld, nullptr, 0, 0, nullptr, p->Gm + (int64_t)c0 * k, k,
+                    p->gw, st));
+    }
+    KF_TRY(symmetrize(k, p->Gm, k, st));
+    std::vector<double> th, all;
+    KF_TRY(small_eigen(p, k, p->Gm, k, th, [](double) { return true; }, all));
+    // the Ritz values in the widened interval form a contiguous range
+    int i0 = 0, i1 = 0;
+    while (i0 < k && std::sqrt(std::max(th[(size_t)i0], 0.0)) < lo) ++i0;
+    i1 = i0;
+    while (i1 < k && std::sqrt(std::max(th[(size_t)i1], 0.0)) <= hi) ++i1;
+    std::vector<double> sel(th.begin() + i0, th.begin() + i1);
+    KF_TRY(ritz_residuals(p, Q, ld, k, sel, tol, want_vectors, out, true, p->ew.Y + (int64_t)i0 * k));
+    out.ritz = th;
+    KF_HIP(hipEventRecord(p->sev[3], st));
+    KF_TRY(lap(p->sev[2], p->sev[3], stats.t_rr));
+    const int cnt = distinct_count(out.acc_theta, cnt_b);
+    if (target > 0 && cnt >= target) break;
+    if (cnt > best) {
+      best = cnt;
+      stalled = 0;
+    } else if (stall_limit > 0 && ++stalled >= stall_limit) {
+      break;
+    }
+    // next block: accepted Ritz vectors first (locked), then all others
+    std::vector<char> acc((size_t)k, 0);
+    for (int a : out.acc_sel) {
+      const double t = out.cand_theta[(size_t)a];
+      if (t >= lo2 && t <= hi2) acc[(size_t)(i0 + a)] = 1;
+    }
+    std::vector<int> order;
+    for (int i = 0; i < k; ++i)
+      if (acc[(size_t)i]) order.push_back(i);
+    const int nl_new = (int)order.size();
+    for (int i = 0; i < k; ++i)
+      if (!acc[(size_t)i]) order.push_back(i);
+    for (int j = 0; j < k; ++j)
+      KF_HIP(hipMemcpyAsync(p->Ysel + (int64_t)j * k, p->ew.Y + (int64_t)order[(size_t)j] * k, sizeof(double) * k,
+                            hipMemcpyDeviceToDevice, st));
+    KF_TRY(gemm_nn(n, k, Q, ld, p->Ysel, k, X, ld, k, st));
+    nl = nl_new;
+    na = k - nl;
+  }
+  stats.dim = nl + na;
+  return KF_OK;
+}
+
 // Mixed-precision refinement: the float64 filtered subspace iteration started
 // from the Ritz vectors of the float32 Krylov space whose omega lies in the
-// interval widened by the margin (all of them: a half-converged copy of a
-// multiple eigenvalue, seeded by float32 round-off, must stay in the space
-// until it has converged, or it keeps contaminating its neighbours).  At most
-// opt.refine iterations; it stops once `target` pairs (distinct_count with
-// block width b) are accepted.
+// interval widened by the margin.  At most opt.refine iterations; it stops
+// once `target` pairs (distinct_count with block width b) are accepted, or
+// when two iterations in a row accepted no more pairs (pollution along
+// directions with the same filter value as the pairs' own does not decay).
 int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want_vectors, CheckOut& out,
                  int64_t* lf_steps, int target = 0, int b = 1, double margin = 0.0) {
   hipStream_t st = p->st;
@@ -1153,11 +1286,9 @@ int refine_mixed(kf_problem* p, int k, double tol, const CheckOut& in, bool want
   KF_TRY(ensure_refine(p, nc, k));
   // X = B * (eigenvectors of the last check's candidates, ew.Y), into Vx
   KF_TRY(gemm_nn(n, k, p->B, p->ldb, p->ew.Y, k, p->Vx, ld, nc, st));
-  double* X = p->Vx;
-  double* Q = p->Yy;
   SubspaceStats stats;
-  KF_TRY(subspace_iterate(p, p->A64, p->sb64, X, Q, nc, std::max(1, p->opt.refine), tol, target, b, margin,
-                          want_vectors, out, stats));
+  KF_TRY(subspace_iterate_locked(p, p->A64, p->sb64, nc, std::max(1, p->opt.refine), tol, target, b, margin,
+                                 want_vectors, out, stats, 2));
   *lf_steps += stats.lf_steps;
   out.ritz = in.ritz;
   out.orth = in.orth;
@@ -1362,6 +1493,7 @@ void kf_default_options(kf_options* o) {
   o->proj_every = 12;
   o->refine = 8;
   o->escalate = 1;
+  o->stepper = 2;
   o->want_vectors = 0;
   o->index_bytes = 0;
   o->xcd_remap = 1;
@@ -1417,6 +1549,8 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
       o.gather_unroll != 6)
     return fail(KF_EINVAL, "kf_create: gather_unroll must be 0, 2, 3, 4 or 6");
   if (o.block_band < -1 || o.block_band > 1) return fail(KF_EINVAL, "kf_create: block_band must be -1, 0 or 1");
+  if (o.stepper == 0) o.stepper = 2;
+  if (o.stepper != 2 && o.stepper != 4) return fail(KF_EINVAL, "kf_create: stepper must be 2 or 4");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 
@@ -1662,7 +1796,8 @@ int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, doub
   if (!p || (n > 0 && (!omega || !beta_out)) || n < 0) return fail(KF_EINVAL, "kf_filter_response: bad arguments");
   // Lemma 2.3: beta~(omega) = sum_l w_l q_l(omega), q by the scalar recurrence
   for (int32_t i = 0; i < n; ++i) {
-    const double f = 2.0 - p->tau * p->tau * omega[i] * omega[i];
+    const double x = p->tau * p->tau * omega[i] * omega[i];
+    const double f = 2.0 - x + (p->opt.stepper == 4 ? x * x / 12.0 : 0.0);
     double qm = 1.0, q = 1.0, s = 0.0;
     for (size_t l = 0; l < p->w.size(); ++l) {
       s += p->w[l] * q;
@@ -1757,7 +1892,7 @@ int kf_apply_filter_noalloc(kf_problem* p, const double* x, double* y, int32_t b
                                ", the current device is " + std::to_string(dev));
   const int bk = pow2ceil(b);
   StepBufs sb;
-  KF_TRY(scratch_step_buffers(p->n, bk, p->A.val_bytes, sb));
+  KF_TRY(scratch_step_buffers(p->n, bk, p->A.val_bytes, sb, p->opt.stepper == 4 ? 4 : 3));
   return run_filter(p, p->A, sb, x, b, 1, b, bk, y, b, 1, b, p->w, false);
 }
 
@@ -2343,6 +2478,39 @@ int kf_subspace_solve(kf_problem* p, const double* start, int32_t ncols, int32_t
   return KF_OK;
 }
 
+int kf_tune_steps(const kf_csr* S, const double* m_diag, double omega_min, double omega_max, double tau,
+                  const int32_t* L_cand, int32_t n_cand, const double* start, int32_t b, int32_t m_max, double tol,
+                  const kf_options* opt, int32_t* L_best, double* seconds, int32_t* krylov_steps) {
+  if (!L_best || !L_cand || n_cand < 1 || !start) return fail(KF_EINVAL, "kf_tune_steps: bad arguments");
+  *L_best = 0;
+  double best = 1e300;
+  for (int32_t c = 0; c < n_cand; ++c) {
+    if (L_cand[c] < 1) return fail(KF_EINVAL, "kf_tune_steps: every candidate L must be >= 1");
+    kf_problem* p = nullptr;
+    KF_TRY(kf_create(S, m_diag, omega_min, omega_max, tau, L_cand[c], opt, &p));
+    kf_result* r = nullptr;
+    // the problem's first solve of this width also times the block step
+    // variant when autotuning is on: it is set up before the timed solve
+    int rc = tune_block(p, p->A, p->sb, pow2ceil(b));
+    if (!rc) rc = kf_solve(p, start, b, m_max, tol, &r);
+    if (rc) {
+      kf_destroy(p);
+      return rc;
+    }
+    const bool met = r->status == KF_OK;
+    if (seconds) seconds[c] = met ? r->t_total : -1.0;
+    if (krylov_steps) krylov_steps[c] = r->krylov_steps;
+    if (met && r->t_total < best) {
+      best = r->t_total;
+      *L_best = L_cand[c];
+    }
+    kf_result_free(r);
+    kf_destroy(p);
+  }
+  if (*L_best == 0) return fail(KF_ENOTCONV, "kf_tune_steps: no candidate reached the target");
+  return KF_OK;
+}
+
 int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* ncols) {
   if (!p || !out || !ncols || max_cols < 0) return fail(KF_EINVAL, "kf_copy_basis: bad arguments");
   const int k = std::min(max_cols, (int32_t)p->basis_cols);
@@ -2439,6 +2607,10 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     return fail(KF_EINVAL, "kf_create_batch: batch_workers must be >= 0");
   }
   bt->workers = o.batch_workers > 0 ? std::min<int>(o.batch_workers, P) : std::min<int>(8, P);
+  if (o.stepper != 0 && o.stepper != 2) {
+    delete bt;
+    return fail(KF_EINVAL, "kf_create_batch: batches step with the second-order scheme (stepper 2)");
+  }
   int rc = KF_OK;
   do {
     if (hipStreamCreate(&bt->st) != hipSuccess) {

@@ -102,6 +102,13 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
                     double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
                     hipStream_t st);
 
+// The fourth-order two-step scheme, same modes and schedule:
+//   z = A cur;  nxt = 2 cur - prev - z + (A z)/12
+// (two launches; z is an n x b work block in the stepping precision).
+int launch_leapfrog4(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc, void* z,
+                     double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
+                     hipStream_t st);
+
 // The accumulation schedule of one filter application (L - 1 steps): for
 // step l, the mode and the weights (wp, wc, wn) of prev, cur and nxt.  Every
 // y_j enters once: y_0 and y_1 at step 1, then three at a time at steps

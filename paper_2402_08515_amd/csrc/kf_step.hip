@@ -203,6 +203,107 @@ __global__ __launch_bounds__(256) void k_leapfrog(int32_t n, int32_t nslices, co
   }
 }
 
+// ------------------------------------------------ fourth-order two-step scheme
+// y_{l+1} = 2 y_l - y_{l-1} - A y_l + (1/12) A (A y_l), A = tau^2 M^{-1} S
+// (a high-order variant of the leapfrog step; its iteration is a polynomial
+// in M^{-1} S).  Two launches per step: k_apply_block forms z = A y_l, then
+// k_leapfrog4 gathers A z and does the update and the accumulation with the
+// same modes and schedule as k_leapfrog.  One lane per row.
+template <typename T, typename IT, int B>
+__global__ __launch_bounds__(256) void k_apply_block(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                     const T* __restrict__ val, const IT* __restrict__ idx,
+                                                     const T* __restrict__ x, T* __restrict__ z, int remap) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int slice = wg * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int row = slice * 64 + lane;
+  if (row >= n) return;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  const T* __restrict__ vp = val + base + lane;
+  const IT* __restrict__ ip = idx + base + lane;
+  T sum[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) sum[j] = (T)0;
+#pragma unroll 4
+  for (int q = 0; q < width; ++q) {
+    const T a = vp[(int64_t)q * 64];
+    const IT ci = ip[(int64_t)q * 64];
+    const int c = relative ? row + (int)ci : (int)ci;
+    const Row<T, B> xv = *reinterpret_cast<const Row<T, B>*>(x + (int64_t)c * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) sum[j] = fma(a, xv.v[j], sum[j]);
+  }
+  Row<T, B> o;
+#pragma unroll
+  for (int j = 0; j < B; ++j) o.v[j] = sum[j];
+  *reinterpret_cast<Row<T, B>*>(z + (int64_t)row * B) = o;
+}
+
+template <typename T, typename IT, int B, int MODE>
+__global__ __launch_bounds__(256) void k_leapfrog4(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                   const T* __restrict__ val, const IT* __restrict__ idx,
+                                                   const T* __restrict__ cur, const T* prev, T* out,
+                                                   T* __restrict__ acc, const T* __restrict__ z,
+                                                   double* __restrict__ rout, int64_t rs, int64_t cs, int bout, T wp,
+                                                   T wc, T wn, int remap) {
+  constexpr bool relative = sizeof(IT) == 2;
+  const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int slice = wg * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slice >= nslices) return;
+  const int row = slice * 64 + lane;
+  if (row >= n) return;
+  const int64_t base = sptr[slice];
+  const int width = (int)((sptr[slice + 1] - base) >> 6);
+  const T* __restrict__ vp = val + base + lane;
+  const IT* __restrict__ ip = idx + base + lane;
+  T sum[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) sum[j] = (T)0;
+#pragma unroll 4
+  for (int q = 0; q < width; ++q) {
+    const T a = vp[(int64_t)q * 64];
+    const IT ci = ip[(int64_t)q * 64];
+    const int c = relative ? row + (int)ci : (int)ci;
+    const Row<T, B> zv = *reinterpret_cast<const Row<T, B>*>(z + (int64_t)c * B);
+#pragma unroll
+    for (int j = 0; j < B; ++j) sum[j] = fma(a, zv.v[j], sum[j]);
+  }
+  const int64_t off = (int64_t)row * B;
+  const Row<T, B> yc = *reinterpret_cast<const Row<T, B>*>(cur + off);
+  const Row<T, B> zc = *reinterpret_cast<const Row<T, B>*>(z + off);
+  Row<T, B> yp;
+  if (MODE & kFirst)
+    yp = yc;
+  else
+    yp = *reinterpret_cast<const Row<T, B>*>(prev + off);
+  constexpr T twelfth = (T)(1.0 / 12.0);
+  Row<T, B> nx;
+#pragma unroll
+  for (int j = 0; j < B; ++j) nx.v[j] = fma(twelfth, sum[j], (T)2 * yc.v[j] - yp.v[j] - zc.v[j]);
+  if (!(MODE & kLast)) *reinterpret_cast<Row<T, B>*>(out + off) = nx;
+  if (MODE == kMid) return;
+  Row<T, B> r;
+  if (MODE & kFirst) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = fma(wn, nx.v[j], wc * yc.v[j]);
+  } else {
+    r = *reinterpret_cast<const Row<T, B>*>(acc + off);
+#pragma unroll
+    for (int j = 0; j < B; ++j) r.v[j] = fma(wn, nx.v[j], fma(wc, yc.v[j], fma(wp, yp.v[j], r.v[j])));
+  }
+  if (MODE & kLast) {
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (j < bout) rout[(int64_t)row * rs + (int64_t)j * cs] = (double)r.v[j];
+  } else {
+    *reinterpret_cast<Row<T, B>*>(acc + off) = r;
+  }
+}
+
 // ------------------------------------------------------- batched leapfrog
 // Many independent problems stacked into one block-diagonal operator: every
 // problem owns whole 64-row slices (rows padded to a multiple of 64), slice s
@@ -427,6 +528,49 @@ int launch_lf_t(const SellOp& A, int b, int mode, const void* cur, const void* p
   }
 }
 
+template <typename T, typename IT, int B>
+int launch_lf4_b(const SellOp& A, int mode, const void* cur, const void* prev, void* out, void* acc, void* z,
+                 double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap,
+                 hipStream_t st) {
+  const int grid = ceil_div64(A.nslices, 4);
+  const T* v = static_cast<const T*>(A.val);
+  const IT* ix = static_cast<const IT*>(A.idx);
+  const T* c = static_cast<const T*>(cur);
+  const T* p = static_cast<const T*>(prev);
+  T* o = static_cast<T*>(out);
+  T* a = static_cast<T*>(acc);
+  T* zz = static_cast<T*>(z);
+  hipLaunchKernelGGL((k_apply_block<T, IT, B>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr, v, ix, c, zz,
+                     remap);
+#define KF_LF4(M)                                                                                                  \
+  hipLaunchKernelGGL((k_leapfrog4<T, IT, B, M>), dim3(grid), dim3(256), 0, st, A.n, A.nslices, A.slice_ptr, v, ix, c, \
+                     p, o, a, zz, rout, rs, cs, bout, (T)wp, (T)wc, (T)wn, remap)
+  switch (mode) {
+    case kMid: KF_LF4(kMid); break;
+    case kFirst: KF_LF4(kFirst); break;
+    case kMidAcc: KF_LF4(kMidAcc); break;
+    case kLast: KF_LF4(kLast); break;
+    default: KF_LF4(kFirstLast); break;
+  }
+#undef KF_LF4
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+template <typename T, typename IT>
+int launch_lf4_t(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc, void* z,
+                 double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int remap,
+                 hipStream_t st) {
+  switch (b) {
+    case 1: return launch_lf4_b<T, IT, 1>(A, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 2: return launch_lf4_b<T, IT, 2>(A, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 4: return launch_lf4_b<T, IT, 4>(A, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 8: return launch_lf4_b<T, IT, 8>(A, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    case 16: return launch_lf4_b<T, IT, 16>(A, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, remap, st);
+    default: set_error("fourth-order step: block width must be 1, 2, 4, 8 or 16"); return KF_EINVAL;
+  }
+}
+
 }  // namespace
 
 
@@ -540,6 +684,23 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
   if (A.idx_bytes == 2)
     return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
   return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
+}
+
+int launch_leapfrog4(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc, void* z,
+                     double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
+                     hipStream_t st) {
+  if (A.val_bytes == 8) {
+    if (A.idx_bytes == 2)
+      return launch_lf4_t<double, int16_t>(A, b, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn,
+                                           xcd_remap, st);
+    return launch_lf4_t<double, int32_t>(A, b, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, xcd_remap,
+                                         st);
+  }
+  if (A.idx_bytes == 2)
+    return launch_lf4_t<float, int16_t>(A, b, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, xcd_remap,
+                                        st);
+  return launch_lf4_t<float, int32_t>(A, b, mode, cur, prev, out, acc, z, rout, rs, cs, bout, wp, wc, wn, xcd_remap,
+                                      st);
 }
 
 StepPlan step_plan(int l, int L) {

@@ -64,6 +64,7 @@ class OptionsT(C.Structure):
         ("lanes_per_row", C.c_int32),
         ("gather_unroll", C.c_int32),
         ("block_band", C.c_int32),
+        ("stepper", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -134,6 +135,9 @@ _SIGNATURES = {
     "kf_result_free": (C.c_int, [C.POINTER(ResultT)]),
     "kf_subspace_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double,
                                     C.POINTER(C.POINTER(ResultT))]),
+    "kf_tune_steps": (C.c_int, [C.POINTER(CsrT), C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(OptionsT),
+                                C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]),
     "kf_copy_basis": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "kf_sym_eig": (C.c_int, [C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.POINTER(C.c_int32),
                              C.c_void_p, C.c_void_p]),
@@ -222,6 +226,26 @@ def sym_eig(A, lo: float = 0.0, hi: float = -1.0, vectors: bool = False):
     if vectors:
         return theta, np.ascontiguousarray(Y[:, : nsel.value])
     return theta
+
+
+def tune_steps(S, m, omega_min: float, omega_max: float, tau: float, L_candidates, start, m_max: int, tol: float,
+               **options):
+    """The L among the candidates whose solve meets options['target'] fastest;
+    returns (L_best, seconds per candidate, Krylov steps per candidate)."""
+    c, keep = _host_csr(S)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    Lc = np.ascontiguousarray(L_candidates, dtype=np.int32)
+    V0 = np.ascontiguousarray(start, dtype=np.float64)
+    if V0.ndim == 1:
+        V0 = V0[:, None]
+    opt = _options(**options)
+    best = C.c_int32()
+    secs = np.zeros(Lc.size)
+    its = np.zeros(Lc.size, dtype=np.int32)
+    _check(lib().kf_tune_steps(C.byref(c), _ptr(m), float(omega_min), float(omega_max), float(tau), _ptr(Lc),
+                               int(Lc.size), _ptr(V0), int(V0.shape[1]), int(m_max), float(tol), C.byref(opt),
+                               C.byref(best), _ptr(secs), _ptr(its)))
+    return best.value, secs, its
 
 
 WINDOWS = {"indicator": 0, "triangle": 1, "gaussian": 2}
@@ -319,7 +343,7 @@ def _take_result(res, n: int) -> SolveResult:
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=None, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
              autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0,
-             block_band=0, escalate=None):
+             block_band=0, escalate=None, stepper=2):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -345,6 +369,7 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
     opt.lanes_per_row = int(lanes_per_row)
     opt.gather_unroll = int(gather_unroll)
     opt.block_band = int(block_band)
+    opt.stepper = int(stepper)
     opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt
