@@ -137,6 +137,35 @@ def batch64_problems(count: int = 64, seed: int = 3):
     return out
 
 
+def batch64_slices(max_target: int = 150, count: int = 64, seed: int = 3):
+    """The uneven batch with every member's interval cut into slices whose
+    block-4 target (distinct eigenvalues, each counted up to 4 times) is at
+    most ``max_target``; cuts lie halfway (in omega) between consecutive
+    distinct eigenvalues of the closed-form spectrum, so no eigenvalue sits on
+    a cut.  Returns [(member index, Problem, omega_lo, omega_hi, target)]; a
+    member with a small target is one slice, its own interval."""
+    import math
+
+    out = []
+    for i, P in enumerate(batch64_problems(count, seed)):
+        lam = grid_spectrum(P.meta["dim"], P.meta["n"])
+        t, vals, mult = distinct_target(lam, P.omega_min, P.omega_max, P.block)
+        if t <= max_target:
+            out.append((i, P, P.omega_min, P.omega_max, t))
+            continue
+        w = np.minimum(mult, P.block)
+        cum = np.cumsum(w)
+        k = int(math.ceil(t / max_target))
+        start_i, start_om = 0, P.omega_min
+        for s in range(1, k):
+            j = max(int(np.searchsorted(cum, s * t / k)), start_i)
+            cut = 0.5 * (math.sqrt(vals[j]) + math.sqrt(vals[j + 1]))
+            out.append((i, P, start_om, cut, int(w[start_i:j + 1].sum())))
+            start_i, start_om = j + 1, cut
+        out.append((i, P, start_om, P.omega_max, int(w[start_i:].sum())))
+    return out
+
+
 def grid3d_128_intervals(count: int = 32, seed: int = 4):
     """Evaluation intervals of the learned-weight comparison: stream 1 of
     seed 4 (stream 0 is reserved for training samples)."""
