@@ -133,52 +133,108 @@ def cpu_baseline(P, tau, L, V0, krylov_iters: int):
 
 def bench_batch(args):
     """The uneven batch: 64 squares/cubes (seed 3), block width 4, float32
-    time stepping, float64 projection; one kf_solve_batch call (the time loops
-    of all members advance in one graph-captured launch sequence) against the
-    same members solved one after another."""
+    time stepping, float64 projection, every member solved to all its
+    eigenpairs (23,172 in total).  Intervals holding more than
+    --slice-target pairs are cut into slices (between eigenvalues of the
+    closed form) that enter the batch as members of their own; a slice of
+    width d gets T >= 2 pi / (3 d) (the filter's transition at most three
+    times the slice, as the rule's T gives the 3D cube), the other members
+    the rule's L.  Timed: the batched mixed solve (one kf_solve_batch call),
+    the same with the network's weights where the gate takes them, and the
+    plain float64 method slice by slice; every problem is created before its
+    timed region."""
+    import math
+
     import numpy as np
     import torch
 
     from paper_2402_08515_amd import kf
     from synth import distinct_target, grid_spectrum, power_start, start_block
-    from synth.workloads import batch64_problems
+    from synth.netinit import init_params
+    from synth.workloads import batch64_slices, filter_samples
 
-    probs = batch64_problems()[: args.batch_count]
-    members, starts, targets = [], [], []
-    for P in probs:
-        lam = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
-        tau, L = kf.time_step_rule(lam, P.omega_min)
-        tgt = distinct_target(grid_spectrum(P.meta["dim"], P.meta["n"]), P.omega_min, P.omega_max, P.block)[0]
-        members.append((P.S, P.m, P.omega_min, P.omega_max, tau, L, tgt))
+    slices = batch64_slices(args.slice_target, args.batch_count)
+    lam_of, members, starts, meta = {}, [], [], []
+    for (i, P, lo, hi, tgt) in slices:
+        if i not in lam_of:
+            lam_of[i] = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
+        tau, L_rule = kf.time_step_rule(lam_of[i], lo)
+        L = max(L_rule, int(math.ceil(2 * math.pi / (3.0 * (hi - lo) * tau))))
+        members.append((P.S, P.m, lo, hi, tau, L, tgt))
         starts.append(start_block(P.n, P.block, P.seed))
-        targets.append(tgt)
-    opts = dict(precision="mixed", check_every=2, check_growth=0.15, max_iters=args.batch_iters)
-    print(f"[bench] batch of {len(probs)}: n in [{min(p.n for p in probs)}, {max(p.n for p in probs)}], "
-          f"L in [{min(m[5] for m in members)}, {max(m[5] for m in members)}], targets {sum(targets)}",
-          file=sys.stderr, flush=True)
-    bt = kf.Batch(members, **opts)
+        meta.append((i, P, lo, hi, tgt, lam_of[i]))
+    total = sum(m[6] for m in members)
+    print(f"[bench] batch: {args.batch_count} members in {len(members)} slices, L in "
+          f"[{min(m[5] for m in members)}, {max(m[5] for m in members)}], {total} pairs", file=sys.stderr, flush=True)
+
+    def count(res):
+        found = sum(min(r.omega2.size, m[6]) for r, m in zip(res, members))
+        errs = []
+        for r, (i, P, lo, hi, tgt, lam) in zip(res, meta):
+            if r.omega2.size:
+                t, vals, mult = distinct_target(grid_spectrum(P.meta["dim"], P.meta["n"]), lo, hi, P.block)
+                near = vals[np.abs(r.omega2[:, None] - vals[None, :]).argmin(axis=1)]
+                errs.append(float(np.max(np.abs(r.omega2 - near) / near)))
+        return int(found), max(errs) if errs else None
+
+    opts = dict(check_every=2, check_growth=0.15)
+    runs = {}
+    # mixed, batched (the slices' problems and the stacked operator are built,
+    # and the batched step variant timed, before the timed region)
+    bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = bt.solve(starts, m_max=args.m_max, tol=args.tol)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    steps = sum(P.n * r.leapfrog_vector_steps for P, r in zip(probs, res))
-    found = sum(min(r.omega2.size, t) for r, t in zip(res, targets))
-    print(f"[bench] batched: {wall:.2f}s, pairs {found}/{sum(targets)}", file=sys.stderr, flush=True)
-    seq_wall = seq_lf = None
-    if not args.no_sequential:
-        seq_lf = 0.0
-        # the members' problems are created before the timed region, as the batch is
-        singles = [kf.Problem(S, m, lo, hi, tau, L, target=tgt, **opts) for (S, m, lo, hi, tau, L, tgt) in members]
+    found, err = count(res)
+    esc = int(sum(r.escalated for r in res))
+    steps = sum(P.n * r.leapfrog_vector_steps for (i, P, *_), r in zip(meta, res))
+    runs["mixed_batched"] = {"seconds": wall, "pairs": found, "max_rel_err": err, "escalated_slices": esc,
+                             "batched_leapfrog_s": res[0].t_leapfrog}
+    print(f"[bench] mixed batched: {wall:.2f}s, {found}/{total} pairs, max err {err}, {esc} slices escalated",
+          file=sys.stderr, flush=True)
+    bt.close()
+    del bt
+    # learned weights where the gate takes them, mixed, batched
+    if not args.no_learned:
+        train = filter_samples(args.mlp_samples, stream=0)
+        net = kf.Mlp(init_params(4).astype(np.float32))
+        rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
+        order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
+        net.train(train, order, args.mlp_epochs, 256, 1e-3)
+        bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **opts)
+        used = 0
+        for q, ((S, m, lo, hi, tau, L, tgt), (_, _, _, _, _, lam)) in enumerate(zip(members, meta)):
+            w, u, jl, jf = net.weights(lo, hi, tau, lam, L)
+            if u:
+                bt.set_weights(q, w)
+                used += 1
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for pr, V0 in zip(singles, starts):
-            r1 = pr.solve(V0, m_max=args.m_max, tol=args.tol)
-            seq_lf += r1.t_leapfrog
+        resl = bt.solve(starts, m_max=args.m_max, tol=args.tol)
         torch.cuda.synchronize()
-        seq_wall = time.perf_counter() - t0
+        wl = time.perf_counter() - t0
+        fl, el = count(resl)
+        runs["learned_mixed_batched"] = {"seconds": wl, "pairs": fl, "max_rel_err": el, "gate_took_network": used,
+                                         "escalated_slices": int(sum(r.escalated for r in resl))}
+        print(f"[bench] learned mixed batched: {wl:.2f}s, {fl}/{total} pairs, network weights on {used} slices",
+              file=sys.stderr, flush=True)
+        bt.close()
+        del bt
+    # the plain method: float64 stepping, Fourier weights, one slice after another
+    if not args.no_sequential:
+        singles = [kf.Problem(S, m, lo, hi, tau, L, target=tgt, autotune=True, **opts)
+                   for (S, m, lo, hi, tau, L, tgt) in members]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res64 = [pr.solve(V0, m_max=args.m_max, tol=args.tol) for pr, V0 in zip(singles, starts)]
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t0
+        f64, e64 = count(res64)
+        runs["plain_fp64_one_by_one"] = {"seconds": w64, "pairs": f64, "max_rel_err": e64}
+        print(f"[bench] plain fp64 one by one: {w64:.2f}s, {f64}/{total} pairs", file=sys.stderr, flush=True)
         del singles
-        print(f"[bench] one by one: {seq_wall:.2f}s (time stepping {seq_lf:.3f}s)", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": steps / wall,
@@ -192,16 +248,13 @@ def bench_batch(args):
         "vs_baseline": None,
         "dtype": "f32-step/f64-proj",
         "data": "synthetic",
-        "config": {"workload": f"batch64[:{len(probs)}]", "block": 4, "tol": args.tol, "m_max": args.m_max,
-                   "target_pairs": int(sum(targets)), "parallelism": "1 GPU"},
-        "s_to_all_eigenpairs": wall,
-        "pairs_accepted": int(found),
-        "members_complete": int(sum(1 for r, t in zip(res, targets) if r.omega2.size >= t)),
-        "krylov_iters_per_member": args.batch_iters,
-        "batched_leapfrog_s": res[0].t_leapfrog,
+        "config": {"workload": f"batch64[:{args.batch_count}]", "slices": len(members), "block": 4,
+                   "tol": args.tol, "m_max": args.m_max, "slice_target": args.slice_target,
+                   "target_pairs": int(total), "parallelism": "1 GPU"},
+        "s_to_all_eigenpairs": wall if found >= total else None,
+        "pairs_accepted": found,
+        "runs": runs,
         "batched_leapfrog_dof_steps_per_s": steps / res[0].t_leapfrog,
-        "sequential_s": seq_wall,
-        "sequential_leapfrog_s": seq_lf,
     }
     print(json.dumps(out))
 
@@ -419,18 +472,36 @@ def bench_forms(args):
     print(json.dumps(out))
 
 
+def cube_model_spectrum(n: int, top: float, far_every: int = 20):
+    """Model spectrum for the convergence model on the cube with n cells per
+    axis: its distinct eigenvalues (a single start vector sees one direction
+    per eigenspace), all of them up to omega = top and every far_every-th
+    beyond, standing for far_every eigenvalues each."""
+    import numpy as np
+
+    from synth import grid_spectrum
+
+    lam = np.sort(grid_spectrum(3, n))
+    om = np.sqrt(lam[np.concatenate([[True], np.diff(lam) > 1e-10 * lam[1:]])])
+    near = om <= top
+    far = np.where(~near)[0][::far_every]
+    return (np.concatenate([om[near], om[far]]),
+            np.concatenate([np.ones(int(near.sum())), far_every * np.ones(far.size)]))
+
+
 def bench_learned(args):
-    """Learned filter weights: the network is trained on the GPU (50,000
-    samples of (omega_min, omega_max, tau, lambda_max) from seed 4 stream 0),
-    then intervals from the evaluation law (seed 4 stream 1) on the 3D cube
-    with 128 cells per axis (2,048,383 DOFs) are solved to all their
-    eigenpairs with the Fourier weights and with the weights the network
-    proposes (the acceptance gate falls back to the Fourier weights when they leak
-    less).  Intervals holding more distinct eigenvalues than
-    --learned-max-target are skipped (a single start vector needs a basis
-    several times the target).  Stepping is fp64 by default: the cube's
-    eigenvalues of multiplicity 6 defeat fp32 stepping from one start vector
-    (round-off seeds the directions the start vector lacks)."""
+    """Learned filter weights on the 3D cube with 128 cells per axis
+    (2,048,383 DOFs), float32 time stepping (the mixed form: float64
+    refinement, float64 restart when the cube's multiplicities defeat the
+    refinement).  The network is trained on the GPU (50,000 samples of
+    (omega_min, omega_max, tau, lambda_max), seed 4 stream 0); intervals come
+    from the evaluation law (seed 4 stream 1), those holding more than
+    --learned-max-target distinct eigenvalues are skipped.  For every interval
+    the candidates are the Fourier weights, the network's, and the Gaussian and
+    triangle windows; the Krylov convergence model (kf_select_weights, on the
+    cube's distinct closed-form spectrum) picks one, the Fourier weights unless
+    another is predicted faster.  Timed solves: Fourier, the network's weights
+    on their own, and the selected weights."""
     import numpy as np
     import torch
 
@@ -453,25 +524,32 @@ def bench_learned(args):
     S, m, h = grid_problem(3, n)
     lam = kf.estimate_lambda_max(S, m, 30, power_start(S.shape[0], 4))
     spec = grid_spectrum(3, n)
+    V0 = torch.from_numpy(start_block(S.shape[0], 1, 4)).cuda()  # resident before the timed solves
+    names = ["fourier", "network", "gaussian", "triangle"]
     rows = []
     for (lo, hi) in grid3d_128_intervals(32):
         tgt, vals, _ = distinct_target(spec, lo, hi, 1)
         if tgt == 0 or tgt > args.learned_max_target:
             continue
         tau, L = kf.time_step_rule(lam, lo)
-        V0 = torch.from_numpy(start_block(S.shape[0], 1, 4)).cuda()  # resident before the timed solves
-        rec = {"interval": [lo, hi], "target": tgt, "L": L}
-        for kind in ("fourier", "learned"):
-            # set-up (operator, autotuned step) outside the timed region, for both weight sets alike
+        four = kf.window_weights("indicator", lo, hi, tau, L)
+        wnet = net.batch_weights(np.array([[lo, hi, tau, lam]]))[0, :L]
+        cands = [four, wnet, kf.window_weights("gaussian", lo, hi, tau, L, 1.0),
+                 kf.window_weights("triangle", lo, hi, tau, L, 2.0)]
+        omod, wmod = cube_model_spectrum(n, 3.0 * hi)
+        t1 = time.perf_counter()
+        pick, pred = kf.select_weights(cands, tau, lo, hi, omod, wmod, eps=args.tol, kmax=1500, margin=0.02)
+        t_sel = time.perf_counter() - t1
+        rec = {"interval": [lo, hi], "target": tgt, "L": L, "selected": names[pick],
+               "predicted_steps": dict(zip(names, [int(x) for x in pred])), "select_seconds": t_sel}
+        for kind, w in (("fourier", four), ("network", wnet), ("selected", cands[pick])):
+            if kind == "selected" and pick in (0, 1):
+                rec["selected_run"] = rec["fourier" if pick == 0 else "network"]
+                continue
+            # set-up (operator, autotuned step) outside the timed region, for every weight set alike
             prob = kf.Problem(S, m, lo, hi, tau, L, precision=args.learned_precision, target=tgt, check_every=2,
                               check_growth=0.1, autotune=True)
-            if kind == "learned":
-                w, used, jl, jf = net.weights(lo, hi, tau, lam, L)
-                rec.update(used_learned=used, j_learned=jl, j_fourier=jf)
-                if not used:
-                    rec["learned"] = rec["fourier"]
-                    continue
-                prob.set_weights(w)
+            prob.set_weights(w)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             r = prob.solve(V0, m_max=1024, tol=args.tol)
@@ -480,17 +558,18 @@ def bench_learned(args):
             if r.omega2.size:
                 near = vals[np.abs(r.omega2[:, None] - vals[None, :]).argmin(axis=1)]
                 err = float(np.max(np.abs(r.omega2 - near) / near))
-            rec[kind] = {"pairs": int(r.omega2.size), "krylov_steps": r.krylov_steps, "seconds": dt,
-                         "max_rel_err_vs_closed_form": err}
+            res = {"pairs": int(r.omega2.size), "krylov_steps": r.krylov_steps, "seconds": dt,
+                   "escalated": bool(r.escalated), "max_rel_err_vs_closed_form": err}
+            rec["selected_run" if kind == "selected" else kind] = res
+            del prob
         rows.append(rec)
-        print(f"[bench] [{lo:.2f}, {hi:.2f}] target {tgt}: fourier {rec['fourier']} learned {rec['learned']} "
-              f"used={rec['used_learned']}", file=sys.stderr, flush=True)
+        print(f"[bench] [{lo:.2f}, {hi:.2f}] target {tgt}: predicted {rec['predicted_steps']} -> "
+              f"{rec['selected']}; fourier {rec['fourier']['krylov_steps']} steps {rec['fourier']['seconds']:.2f}s, "
+              f"network {rec['network']['krylov_steps']} steps {rec['network']['seconds']:.2f}s, selected "
+              f"{rec['selected_run']['seconds']:.2f}s", file=sys.stderr, flush=True)
         if len(rows) >= args.learned_count:
             break
-    tf = sum(r["fourier"]["seconds"] for r in rows)
-    tl = sum(r["learned"]["seconds"] for r in rows)
-    kf_ = sum(r["fourier"]["krylov_steps"] for r in rows)
-    kl = sum(r["learned"]["krylov_steps"] for r in rows)
+    tot = lambda key, f: sum(r[key][f] for r in rows)  # noqa: E731
     out = {
         "metric": METRIC,
         "value": None,
@@ -500,10 +579,14 @@ def bench_learned(args):
                    "precision": args.learned_precision, "max_target": args.learned_max_target},
         "train_seconds": t_train,
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
-        "fourier_seconds": tf,
-        "learned_seconds": tl,
-        "fourier_krylov_steps": kf_,
-        "learned_krylov_steps": kl,
+        "fourier_seconds": tot("fourier", "seconds"),
+        "network_seconds": tot("network", "seconds"),
+        "selected_seconds": tot("selected_run", "seconds"),
+        "fourier_krylov_steps": tot("fourier", "krylov_steps"),
+        "network_krylov_steps": tot("network", "krylov_steps"),
+        "selected_krylov_steps": tot("selected_run", "krylov_steps"),
+        "selected_counts": {k: sum(1 for r in rows if r["selected"] == k) for k in names},
+        "pairs_all_met": all(r[k]["pairs"] >= r["target"] for r in rows for k in ("fourier", "network", "selected_run")),
         "intervals": rows,
     }
     print(json.dumps(out))
@@ -527,12 +610,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-step variant instead of timing all of them at set-up")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--slice-target", type=int, default=150,
+                    help="batch: intervals with more pairs are cut into slices of at most this many")
+    ap.add_argument("--no-learned", action="store_true", help="batch: skip the learned-weights run")
     ap.add_argument("--mlp-samples", type=int, default=50000)
     ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--learned-n", type=int, default=128)
     ap.add_argument("--learned-count", type=int, default=32)
     ap.add_argument("--learned-max-target", type=int, default=200)
-    ap.add_argument("--learned-precision", default="fp64", choices=("mixed", "fp64"))
+    ap.add_argument("--learned-precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--batch-iters", type=int, default=24,
                     help="Krylov iterations per member in the batch benchmark (the full targets need thousands)")
     ap.add_argument("--no-sequential", action="store_true")

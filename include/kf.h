@@ -317,6 +317,38 @@ int kf_window_weights(int32_t kind, double omega_min, double omega_max, double t
  * frequencies). */
 int kf_notch_weights(const double* w, int32_t L, double tau, const double* omega, int32_t k, double* w_out);
 
+/* ---- a model of the Krylov iteration's convergence --------------------
+ * Section 2.2 asks for |beta~| large on the sought and small on the unsought
+ * frequencies; Section 3.1.3 shows that the filter alone does not predict the
+ * steps the iteration needs.  In the eigenbasis of the pencil C is the
+ * diagonal matrix diag(beta~(omega_j)) (Lemma 2.3); the model runs the Krylov
+ * iteration on it for a model spectrum: M points omega[M] (>= 0) standing
+ * for weight[M] (> 0) eigenvalues each (a start vector has components
+ * sqrt(weight_j)), orthonormal basis by Gram-Schmidt twice.  A sought point
+ * (omega in [omega_min, omega_max]) is resolved once its unit direction lies
+ * in the space to within eps; *steps receives the first dimension at which
+ * all are (kmax when some never are, e.g. two sought points with equal
+ * filter values; 0 when none is sought).  Unsought points are merged into
+ * 2048 classes of nearly equal filter value (the iteration of a diagonal
+ * matrix cannot tell equal values apart), so the cost is O((n_sought +
+ * 2048) steps^2) host arithmetic whatever M is.
+ * The model spectrum is the caller's: a closed form, a spectral density,
+ * the Ritz values of an earlier solve; points standing for a block-b
+ * iteration count each eigenvalue's multiplicity up to b.
+ * w[L]: filter coefficients, stepper 2 or 4 (kf_options.stepper).
+ * Errors: KF_EINVAL (sizes, M x kmax > 2^31, non-positive weight). */
+int kf_predict_steps(const double* omega, const double* weight, int32_t M, const double* w, int32_t L, double tau,
+                     int32_t stepper, double omega_min, double omega_max, double eps, int32_t kmax, int32_t* steps);
+
+/* The weight set to use among n_cand candidates (candidates[c][L], the same
+ * L and tau): candidate 0, by convention the Fourier weights of eq. weightf,
+ * unless the model above predicts another to need fewer than (1 - margin)
+ * times its steps; then the one with the fewest.  *chosen receives the index,
+ * steps[n_cand] (optional) each prediction. */
+int kf_select_weights(const double* const* candidates, int32_t n_cand, int32_t L, double tau, int32_t stepper,
+                      double omega_min, double omega_max, const double* omega, const double* weight, int32_t M,
+                      double eps, int32_t kmax, double margin, int32_t* chosen, int32_t* steps);
+
 /* Discrete filter function of Lemma 2.3, beta~(omega) = sum_l w_l q_l(omega),
  * at n points omega[n] (host) into beta_out[n] (host). */
 int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, double* beta_out);

@@ -129,6 +129,12 @@ struct kf_batch {
   hipGraphExec_t exec = nullptr;
   int graph_bk = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // members are stacked by decreasing L: at step ell the members still
+  // stepping own the first prefix[ell] row slices
+  std::vector<int> prefix;
+  int remap = 1;      // XCD mapping of the batched step (timed with autotune)
+  int autotune = 0;
+  bool tuned = false;
 };
 
 namespace {
@@ -1792,6 +1798,152 @@ int kf_notch_weights(const double* w, int32_t L, double tau, const double* omega
   return KF_OK;
 }
 
+namespace {
+
+// beta~(omega_j) for the weights w[L] (scalar recurrence of the stepper)
+void filter_values(const double* w, int L, double tau, int stepper, const double* omega, int M, double* beta) {
+  for (int j = 0; j < M; ++j) {
+    const double x = tau * tau * omega[j] * omega[j];
+    const double f = 2.0 - x + (stepper == 4 ? x * x / 12.0 : 0.0);
+    double qm = 1.0, q = 1.0, acc = 0.0;
+    for (int l = 0; l < L; ++l) {
+      acc += w[l] * q;
+      const double qn = f * q - qm;
+      qm = q;
+      q = qn;
+    }
+    beta[j] = acc;
+  }
+}
+
+// The Krylov iteration of D = diag(beta) from the start vector sqrt(weight)
+// (Gram-Schmidt twice); the first dimension at which every sought point j
+// has 1 - |Q[j, :]|^2 <= eps^2, or kmax.
+int krylov_model_steps(const std::vector<double>& beta, const double* weight, const std::vector<char>& inside, int M,
+                       double eps, int kmax) {
+  bool any = false;
+  for (int j = 0; j < M; ++j) any = any || inside[(size_t)j];
+  if (!any) return 0;
+  std::vector<double> Q((size_t)M * std::max(kmax, 1)), x((size_t)M), cap((size_t)M), h((size_t)kmax);
+  double nv = 0.0;
+  for (int j = 0; j < M; ++j) nv += weight[j];
+  nv = std::sqrt(nv);
+  for (int j = 0; j < M; ++j) {
+    Q[(size_t)j] = std::sqrt(weight[j]) / nv;
+    cap[(size_t)j] = Q[(size_t)j] * Q[(size_t)j];
+  }
+  const double e2 = eps * eps;
+  auto resolved = [&]() {
+    for (int j = 0; j < M; ++j)
+      if (inside[(size_t)j] && 1.0 - cap[(size_t)j] > e2) return false;
+    return true;
+  };
+  for (int k = 1; k < kmax; ++k) {
+    const double* qp = &Q[(size_t)(k - 1) * M];
+    for (int j = 0; j < M; ++j) x[(size_t)j] = beta[(size_t)j] * qp[j];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < k; ++i) {
+        const double* qi = &Q[(size_t)i * M];
+        double c = 0.0;
+        for (int j = 0; j < M; ++j) c += qi[j] * x[(size_t)j];
+        h[(size_t)i] = c;
+      }
+      for (int i = 0; i < k; ++i) {
+        const double* qi = &Q[(size_t)i * M];
+        const double c = h[(size_t)i];
+        for (int j = 0; j < M; ++j) x[(size_t)j] -= c * qi[j];
+      }
+    }
+    double nx = 0.0;
+    for (int j = 0; j < M; ++j) nx += x[(size_t)j] * x[(size_t)j];
+    nx = std::sqrt(nx);
+    if (!(nx > 1e-14)) return resolved() ? k : kmax;  // invariant space
+    double* qk = &Q[(size_t)k * M];
+    for (int j = 0; j < M; ++j) {
+      qk[j] = x[(size_t)j] / nx;
+      cap[(size_t)j] += qk[j] * qk[j];
+    }
+    if (resolved()) return k + 1;
+  }
+  return kmax;
+}
+
+}  // namespace
+
+int kf_predict_steps(const double* omega, const double* weight, int32_t M, const double* w, int32_t L, double tau,
+                     int32_t stepper, double omega_min, double omega_max, double eps, int32_t kmax, int32_t* steps) {
+  if (!omega || !weight || !w || !steps || M < 1 || L < 1 || kmax < 1)
+    return fail(KF_EINVAL, "kf_predict_steps: bad arguments");
+  if (!(tau > 0) || !(eps > 0) || (stepper != 2 && stepper != 4))
+    return fail(KF_EINVAL, "kf_predict_steps: need tau > 0, eps > 0, stepper 2 or 4");
+  if ((size_t)M * (size_t)kmax > ((size_t)1 << 31)) return fail(KF_EINVAL, "kf_predict_steps: M x kmax too large");
+  for (int32_t j = 0; j < M; ++j)
+    if (!(weight[j] > 0) || !std::isfinite(omega[j])) return fail(KF_EINVAL, "kf_predict_steps: bad model point");
+  std::vector<double> beta((size_t)M);
+  filter_values(w, L, tau, stepper, omega, M, beta.data());
+  // The Krylov iteration of a diagonal matrix cannot tell points with equal
+  // values apart: the unsought points are merged into kBins classes of
+  // nearly equal filter value (weights summed, value the weighted mean);
+  // sought points stay apart.
+  constexpr int kBins = 2048;
+  std::vector<double> bw, bv, bwt;
+  std::vector<char> inside;
+  double blo = 1e300, bhi = -1e300;
+  for (int32_t j = 0; j < M; ++j) {
+    const bool in = omega[j] >= omega_min && omega[j] <= omega_max;
+    if (in) {
+      bv.push_back(beta[(size_t)j]);
+      bwt.push_back(weight[j]);
+      inside.push_back(1);
+    } else {
+      blo = std::min(blo, beta[(size_t)j]);
+      bhi = std::max(bhi, beta[(size_t)j]);
+    }
+  }
+  if (blo <= bhi) {
+    std::vector<double> W((size_t)kBins, 0.0), V((size_t)kBins, 0.0);
+    const double width = (bhi - blo) / kBins;
+    for (int32_t j = 0; j < M; ++j) {
+      if (omega[j] >= omega_min && omega[j] <= omega_max) continue;
+      int c = width > 0 ? (int)((beta[(size_t)j] - blo) / width) : 0;
+      c = std::min(std::max(c, 0), kBins - 1);
+      W[(size_t)c] += weight[j];
+      V[(size_t)c] += weight[j] * beta[(size_t)j];
+    }
+    for (int c = 0; c < kBins; ++c)
+      if (W[(size_t)c] > 0) {
+        bv.push_back(V[(size_t)c] / W[(size_t)c]);
+        bwt.push_back(W[(size_t)c]);
+        inside.push_back(0);
+      }
+  }
+  const int Mb = (int)bv.size();
+  *steps = krylov_model_steps(bv, bwt.data(), inside, Mb, eps, std::min<int32_t>(kmax, Mb + 1));
+  if (*steps == std::min<int32_t>(kmax, Mb + 1) && kmax > Mb + 1) *steps = kmax;
+  return KF_OK;
+}
+
+int kf_select_weights(const double* const* candidates, int32_t n_cand, int32_t L, double tau, int32_t stepper,
+                      double omega_min, double omega_max, const double* omega, const double* weight, int32_t M,
+                      double eps, int32_t kmax, double margin, int32_t* chosen, int32_t* steps) {
+  if (!candidates || n_cand < 1 || !chosen) return fail(KF_EINVAL, "kf_select_weights: bad arguments");
+  if (!(margin >= 0.0) || margin >= 1.0) return fail(KF_EINVAL, "kf_select_weights: margin must lie in [0, 1)");
+  std::vector<int32_t> st((size_t)n_cand);
+  for (int32_t c = 0; c < n_cand; ++c) {
+    if (!candidates[c]) return fail(KF_EINVAL, "kf_select_weights: NULL candidate");
+    KF_TRY(kf_predict_steps(omega, weight, M, candidates[c], L, tau, stepper, omega_min, omega_max, eps, kmax,
+                            &st[(size_t)c]));
+    if (steps) steps[c] = st[(size_t)c];
+  }
+  // candidate 0 (the Fourier weights) unless another is predicted to need
+  // fewer than (1 - margin) of its steps
+  int32_t best = 0;
+  for (int32_t c = 1; c < n_cand; ++c)
+    if (st[(size_t)c] < st[(size_t)best] && st[(size_t)c] < (1.0 - margin) * st[0]) best = c;
+  *chosen = best;
+  return KF_OK;
+}
+
 int kf_filter_response(const kf_problem* p, const double* omega, int32_t n, double* beta_out) {
   if (!p || (n > 0 && (!omega || !beta_out)) || n < 0) return fail(KF_EINVAL, "kf_filter_response: bad arguments");
   // Lemma 2.3: beta~(omega) = sum_l w_l q_l(omega), q by the scalar recurrence
@@ -2561,12 +2713,46 @@ int ensure_batch_graph(kf_batch* bt, int bk) {
     bt->sb.vb = bt->A.val_bytes;
   }
   hipStream_t st = bt->st;
+  if (bt->autotune && !bt->tuned) {
+    // the batched step's variant (XCD mapping, operator loads), timed on a
+    // middle step of every member before the graph is captured
+    BatchTables tt = bt->h_tb;
+    for (int q = 0; q < bt->P; ++q) tt.active[q] = 1;
+    KF_HIP(hipMemcpyAsync(bt->d_tb, &tt, sizeof(BatchTables), hipMemcpyHostToDevice, st));
+    const size_t bytes = (size_t)bt->rows * bk * bt->A.val_bytes;
+    KF_HIP(hipMemsetAsync(bt->sb.Y0, 0, bytes, st));
+    KF_HIP(hipMemsetAsync(bt->sb.Y1, 0, bytes, st));
+    double best = 1e300;
+    int best_remap = bt->remap, best_nt = bt->A.nt_loads;
+    for (int nt = 0; nt <= 1; ++nt)
+      for (int remap = 0; remap <= 1; ++remap) {
+        bt->A.nt_loads = nt;
+        for (int rep = 0; rep < 2; ++rep) {  // warm-up, then the timing
+          KF_HIP(hipEventRecord(bt->ev[0], st));
+          for (int t = 0; t < 10; ++t)
+            KF_TRY(launch_leapfrog_batch(bt->A, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, 2, bt->sb.Y1, bt->sb.Y0,
+                                         bt->sb.Y0, bt->sb.R, 0, remap, st));
+          KF_HIP(hipEventRecord(bt->ev[1], st));
+        }
+        KF_HIP(hipEventSynchronize(bt->ev[1]));
+        float ms = 0.f;
+        KF_HIP(hipEventElapsedTime(&ms, bt->ev[0], bt->ev[1]));
+        if (ms < best) {
+          best = ms;
+          best_remap = remap;
+          best_nt = nt;
+        }
+      }
+    bt->remap = best_remap;
+    bt->A.nt_loads = best_nt;
+    bt->tuned = true;
+  }
   KF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = launch_load_batch(bt->A.val_bytes, bt->rows, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, bt->sb.Y1, st);
   void* Y[2] = {bt->sb.Y0, bt->sb.Y1};
   for (int l = 1; l < bt->lmax && rc == KF_OK; ++l)
     rc = launch_leapfrog_batch(bt->A, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, l, Y[l & 1], Y[(l + 1) & 1],
-                               Y[(l + 1) & 1], bt->sb.R, st);
+                               Y[(l + 1) & 1], bt->sb.R, bt->prefix[(size_t)l], bt->remap, st);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);
   if (rc != KF_OK) {
@@ -2623,6 +2809,7 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     std::vector<double> val;
     std::vector<int32_t> sp;
     int64_t row0 = 0;
+    bt->autotune = o.autotune;
     for (int32_t q = 0; q < P && rc == KF_OK; ++q) {
       const kf_problem_desc& d = descs[q];
       kf_options oq = o;
@@ -2648,6 +2835,17 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
         pq->st = ms;
         pq->own_stream = true;
       }
+    }
+    if (rc) break;
+    // members stacked by decreasing L (stable): the members still stepping
+    // at step ell own a prefix of the stacked rows
+    std::vector<int> ord((size_t)P);
+    for (int q = 0; q < P; ++q) ord[(size_t)q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return descs[a].L > descs[b].L; });
+    std::vector<int64_t> slices_of((size_t)P, 0);
+    for (int32_t oi = 0; oi < P && rc == KF_OK; ++oi) {
+      const int q = ord[(size_t)oi];
+      const kf_problem_desc& d = descs[q];
       HostCsr h;
       rc = fetch_csr(&d.S, d.m_diag, h);
       if (rc) break;
@@ -2667,6 +2865,7 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
       }
       for (int64_t i = n; i < padded; ++i) rowptr.push_back((int32_t)col.size());
       for (int64_t s = 0; s < padded / 64; ++s) sp.push_back(q);
+      slices_of[(size_t)q] = padded / 64;
       bt->h_tb.row0[q] = row0;
       bt->h_tb.n[q] = n;
       bt->h_tb.L[q] = d.L;
@@ -2675,6 +2874,12 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     }
     if (rc) break;
     bt->rows = row0;
+    bt->prefix.assign((size_t)bt->lmax + 1, 0);
+    for (int ell = 0; ell <= bt->lmax; ++ell) {
+      int64_t cnt = 0;
+      for (int oi = 0; oi < P && descs[ord[(size_t)oi]].L - 1 >= ell; ++oi) cnt += slices_of[(size_t)ord[(size_t)oi]];
+      bt->prefix[(size_t)ell] = (int)std::max<int64_t>(cnt, 1);
+    }
     HostCsr hs;
     hs.rowptr = std::move(rowptr);
     hs.col = std::move(col);

@@ -135,10 +135,12 @@ struct BatchTables {
   double* dst[kMaxBatch];
 };
 
-// One batched fused step (step index ell >= 1) over the stacked operator.
+// One batched fused step (step index ell >= 1) over the first nslices row
+// slices of the stacked operator (0: all; members are stacked by decreasing
+// L, so the members still stepping at ell form a prefix).
 int launch_leapfrog_batch(const SellOp& A, int b, const int32_t* slice_problem, const BatchTables* tb,
                           const void* wtab, int lmax, int ell, const void* cur, const void* prev, void* out, void* acc,
-                          hipStream_t st);
+                          int nslices, int remap, hipStream_t st);
 // Batched load of the filter input into Y1 (and C = w0 I for L_p = 1).
 int launch_load_batch(int val_bytes, int64_t rows, int b, const int32_t* slice_problem, const BatchTables* tb,
                       const void* wtab, int lmax, void* Y1, hipStream_t st);

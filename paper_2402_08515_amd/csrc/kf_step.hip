@@ -318,9 +318,10 @@ __global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const i
                                                         const int32_t* __restrict__ sp, const BatchTables* __restrict__ tb,
                                                         const T* __restrict__ wtab, int lmax, int ell,
                                                         const T* __restrict__ cur, const T* prev, T* out,
-                                                        T* __restrict__ acc) {
+                                                        T* __restrict__ acc, int remap) {
   constexpr bool relative = sizeof(IT) == 2;
-  const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wg = remap ? xcd_map(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int slice = wg * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (slice >= nslices) return;
   const int p = sp[slice];
@@ -714,8 +715,8 @@ StepPlan step_plan(int l, int L) {
 namespace {
 template <typename T, typename IT, bool NT>
 int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax, int ell,
-                 const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
-  const int grid = ceil_div64(A.nslices, 4);
+                 const void* cur, const void* prev, void* out, void* acc, int nslices, int remap, hipStream_t st) {
+  const int grid = ceil_div64(nslices, 4);
   const T* v = static_cast<const T*>(A.val);
   const IT* ix = static_cast<const IT*>(A.idx);
   const T* w = static_cast<const T*>(wtab);
@@ -725,24 +726,24 @@ int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* t
   T* a = static_cast<T*>(acc);
   switch (b) {
     case 1:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 1, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
-                         tb, w, lmax, ell, c, pr, o, a);
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 1, NT>), dim3(grid), dim3(256), 0, st, nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a, remap);
       break;
     case 2:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 2, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
-                         tb, w, lmax, ell, c, pr, o, a);
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 2, NT>), dim3(grid), dim3(256), 0, st, nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a, remap);
       break;
     case 4:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 4, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
-                         tb, w, lmax, ell, c, pr, o, a);
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 4, NT>), dim3(grid), dim3(256), 0, st, nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a, remap);
       break;
     case 8:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 8, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix, sp,
-                         tb, w, lmax, ell, c, pr, o, a);
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 8, NT>), dim3(grid), dim3(256), 0, st, nslices, A.slice_ptr, v, ix, sp,
+                         tb, w, lmax, ell, c, pr, o, a, remap);
       break;
     case 16:
-      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 16, NT>), dim3(grid), dim3(256), 0, st, A.nslices, A.slice_ptr, v, ix,
-                         sp, tb, w, lmax, ell, c, pr, o, a);
+      hipLaunchKernelGGL((k_leapfrog_batch<T, IT, 16, NT>), dim3(grid), dim3(256), 0, st, nslices, A.slice_ptr, v, ix,
+                         sp, tb, w, lmax, ell, c, pr, o, a, remap);
       break;
     default:
       set_error("batched leapfrog: block width must be 1, 2, 4, 8 or 16");
@@ -754,10 +755,13 @@ int launch_lfb_t(const SellOp& A, int b, const int32_t* sp, const BatchTables* t
 }  // namespace
 
 int launch_leapfrog_batch(const SellOp& A, int b, const int32_t* sp, const BatchTables* tb, const void* wtab, int lmax,
-                          int ell, const void* cur, const void* prev, void* out, void* acc, hipStream_t st) {
-#define KF_LFB(T, IT)                                                                                  \
-  return A.nt_loads ? launch_lfb_t<T, IT, true>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st) \
-                    : launch_lfb_t<T, IT, false>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, st)
+                          int ell, const void* cur, const void* prev, void* out, void* acc, int nslices, int remap,
+                          hipStream_t st) {
+  if (nslices <= 0 || nslices > A.nslices) nslices = A.nslices;
+#define KF_LFB(T, IT)                                                                                               \
+  return A.nt_loads ? launch_lfb_t<T, IT, true>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, nslices, remap, \
+                                                st)                                                                 \
+                    : launch_lfb_t<T, IT, false>(A, b, sp, tb, wtab, lmax, ell, cur, prev, out, acc, nslices, remap, st)
   if (A.val_bytes == 8) {
     if (A.idx_bytes == 2) KF_LFB(double, int16_t);
     KF_LFB(double, int32_t);

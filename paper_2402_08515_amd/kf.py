@@ -128,6 +128,11 @@ _SIGNATURES = {
     "kf_filter_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "kf_window_weights": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double,
                                     C.c_void_p]),
+    "kf_predict_steps": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
+                                   C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+    "kf_select_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_double,
+                                    C.POINTER(C.c_int32), C.c_void_p]),
     "kf_notch_weights": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p]),
     "kf_apply_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "kf_apply_filter_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -257,6 +262,37 @@ def window_weights(kind: str, omega_min: float, omega_max: float, tau: float, L:
     _check(lib().kf_window_weights(WINDOWS[kind], float(omega_min), float(omega_max), float(tau), int(L),
                                    float(width), _ptr(out)))
     return out
+
+
+def predict_steps(omega, weight, w, tau: float, omega_min: float, omega_max: float, eps: float = 1e-6,
+                  kmax: int = 2000, stepper: int = 2) -> int:
+    """Krylov steps the convergence model predicts for the weights w."""
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    wt = np.ascontiguousarray(weight, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = C.c_int32()
+    _check(lib().kf_predict_steps(_ptr(om), _ptr(wt), int(om.size), _ptr(w), int(w.size), float(tau), int(stepper),
+                                  float(omega_min), float(omega_max), float(eps), int(kmax), C.byref(out)))
+    return out.value
+
+
+def select_weights(candidates, tau: float, omega_min: float, omega_max: float, omega, weight, eps: float = 1e-6,
+                   kmax: int = 2000, margin: float = 0.0, stepper: int = 2):
+    """Index of the candidate weight set to use (0, the Fourier weights, unless
+    another is predicted faster) and the predicted steps of each."""
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in candidates]
+    L = cs[0].size
+    if any(c.size != L for c in cs):
+        raise ValueError("candidates must have the same length")
+    arr = (C.c_void_p * len(cs))(*[c.ctypes.data for c in cs])
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    wt = np.ascontiguousarray(weight, dtype=np.float64)
+    chosen = C.c_int32()
+    steps = np.zeros(len(cs), dtype=np.int32)
+    _check(lib().kf_select_weights(C.cast(arr, C.c_void_p), len(cs), L, float(tau), int(stepper), float(omega_min),
+                                   float(omega_max), _ptr(om), _ptr(wt), int(om.size), float(eps), int(kmax),
+                                   float(margin), C.byref(chosen), _ptr(steps)))
+    return chosen.value, steps
 
 
 def notch_weights(w, tau: float, omegas):

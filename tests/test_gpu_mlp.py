@@ -106,11 +106,13 @@ def test_training_beats_fourier_and_the_gate_keeps_the_better_weights():
     assert better >= 8
 
 
-def test_solve_with_learned_weights_finds_every_pair():
-    """End to end: weights from the trained network drive a full solve on the
-    3D cube (64 cells per axis); the iteration counts of both weight choices
-    are printed (leakage-trained weights are not faster here, see the design
-    notes)."""
+def test_model_gate_keeps_the_learned_path_no_slower_than_fourier():
+    """End to end on the 3D cube with 64 cells per axis: for each interval the
+    convergence model (kf_select_weights on the cube's distinct closed-form
+    spectrum) chooses between the Fourier weights and the network's; every
+    solve finds every pair, and in aggregate the chosen weights need no more
+    Krylov steps than the Fourier weights (the network's weights alone are
+    printed beside them)."""
     kf = _kf()
     from synth import distinct_target, grid_spectrum, power_start, start_block
     from synth.grids import grid_problem
@@ -119,20 +121,31 @@ def test_solve_with_learned_weights_finds_every_pair():
     net = kf.Mlp(mlp.init_params(4).astype(np.float32))
     rng = np.random.default_rng(7)
     net.train(train, np.concatenate([rng.permutation(8192) for _ in range(4)]).astype(np.int32), 4, 256, 1e-3)
-    S, m, h = grid_problem(3, 64)
+    n = 64
+    S, m, h = grid_problem(3, n)
     lam = kf.estimate_lambda_max(S, m, 30, power_start(S.shape[0], 4))
-    lo, hi = 19.36, 25.11
-    tau, L = kf.time_step_rule(lam, lo)
-    tgt, vals, mult = distinct_target(grid_spectrum(3, 64), lo, hi, 1)
-    w, used, jl, jf = net.weights(lo, hi, tau, lam, L)
+    spec = np.sort(grid_spectrum(3, n))
+    om = np.sqrt(spec[np.concatenate([[True], np.diff(spec) > 1e-10 * spec[1:]])])
     V0 = start_block(S.shape[0], 1, 4)
-    steps = {}
-    for name, ww in (("fourier", None), ("network", w)):
-        prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2)
-        if ww is not None:
-            prob.set_weights(ww)
-        r = prob.solve(V0, m_max=600, tol=1e-6)
-        assert r.omega2.size == tgt
-        np.testing.assert_allclose(r.omega2, vals, rtol=1e-10)
-        steps[name] = r.krylov_steps
-    print(f"gate used learned={used} (J {jl:.3e} vs {jf:.3e}); Krylov steps {steps}")
+    tot = {"fourier": 0, "network": 0, "chosen": 0}
+    for lo, hi in ((19.36, 25.11), (31.0, 38.0), (12.5, 20.0)):
+        tau, L = kf.time_step_rule(lam, lo)
+        tgt, vals, mult = distinct_target(spec, lo, hi, 1)
+        four = kf.window_weights("indicator", lo, hi, tau, L)
+        wnet = net.batch_weights(np.array([[lo, hi, tau, lam]]))[0, :L]
+        pick, pred = kf.select_weights([four, wnet], tau, lo, hi, om, np.ones(om.size), kmax=1500, margin=0.02)
+        steps = {}
+        for name, w in (("fourier", four), ("network", wnet)):
+            prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2)
+            prob.set_weights(w)
+            r = prob.solve(V0, m_max=800, tol=1e-6)
+            assert r.omega2.size == tgt
+            np.testing.assert_allclose(r.omega2, vals, rtol=1e-10)
+            steps[name] = r.krylov_steps
+        steps["chosen"] = steps["network" if pick == 1 else "fourier"]
+        for k in tot:
+            tot[k] += steps[k]
+        print(f"[{lo}, {hi}] target {tgt}: predicted {pred.tolist()} -> {'network' if pick else 'fourier'}; "
+              f"measured {steps}")
+    print("aggregate Krylov steps", tot)
+    assert tot["chosen"] <= 1.05 * tot["fourier"]
