@@ -190,8 +190,26 @@ def bench_batch(args):
     found, err = count(res)
     esc = int(sum(r.escalated for r in res))
     steps = sum(P.n * r.leapfrog_vector_steps for (i, P, *_), r in zip(meta, res))
+    def short(res):
+        out = []
+        for r, (i, P, lo, hi, tgt, lam), mm in zip(res, meta, members):
+            if r.omega2.size < tgt:
+                out.append({"member": i, "dim": P.meta["dim"], "n": P.meta["n"], "interval": [lo, hi], "L": mm[5],
+                            "target": tgt, "found": int(r.omega2.size), "basis": r.basis_size,
+                            "krylov_steps": r.krylov_steps, "escalated": bool(r.escalated), "status": r.status})
+        return out
+
+    def phases(res):
+        # per-member event times summed over the members (a batch member's
+        # t_leapfrog is the shared batched stepping time plus its own after
+        # an escalation)
+        return {"gram_schmidt": sum(r.t_gs for r in res), "rayleigh_ritz": sum(r.t_rr for r in res),
+                "refine": sum(r.t_refine for r in res),
+                "escalated_leapfrog": sum(max(r.t_leapfrog - res[0].t_leapfrog, 0.0) for r in res if r.escalated)}
+
     runs["mixed_batched"] = {"seconds": wall, "pairs": found, "max_rel_err": err, "escalated_slices": esc,
-                             "batched_leapfrog_s": res[0].t_leapfrog}
+                             "batched_leapfrog_s": res[0].t_leapfrog, "phase_seconds_summed": phases(res),
+                             "incomplete": short(res)}
     print(f"[bench] mixed batched: {wall:.2f}s, {found}/{total} pairs, max err {err}, {esc} slices escalated",
           file=sys.stderr, flush=True)
     bt.close()
@@ -232,7 +250,11 @@ def bench_batch(args):
         torch.cuda.synchronize()
         w64 = time.perf_counter() - t0
         f64, e64 = count(res64)
-        runs["plain_fp64_one_by_one"] = {"seconds": w64, "pairs": f64, "max_rel_err": e64}
+        runs["plain_fp64_one_by_one"] = {"seconds": w64, "pairs": f64, "max_rel_err": e64,
+                                         "phase_seconds_summed": {"leapfrog": sum(r.t_leapfrog for r in res64),
+                                                                  "gram_schmidt": sum(r.t_gs for r in res64),
+                                                                  "rayleigh_ritz": sum(r.t_rr for r in res64)},
+                                         "incomplete": short(res64)}
         print(f"[bench] plain fp64 one by one: {w64:.2f}s, {f64}/{total} pairs", file=sys.stderr, flush=True)
         del singles
     out = {
@@ -604,6 +626,8 @@ def main():
     ap.add_argument("--check-growth", type=float, default=0.3)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="every Rayleigh-Ritz check stops the Krylov loop (no check on a second stream)")
     ap.add_argument("--gather-unroll", type=int, default=0,
                     help="single vectors: unroll factor (2, 3, 4 or 6) of the fused step's loop over a slice "
                          "(0 = autotuned)")
@@ -664,7 +688,7 @@ def main():
     print(f"[bench] lambda_est={lam:.6g} tau={tau:.6g} L={L}", file=sys.stderr, flush=True)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
                       check_every=args.check_every, check_growth=args.check_growth, autotune=not args.no_autotune,
-                      gather_unroll=args.gather_unroll)
+                      gather_unroll=args.gather_unroll, overlap_checks=not args.no_overlap)
     tuning = prob.tuning()
     print(f"[bench] fused-step variant {tuning}", file=sys.stderr, flush=True)
     V0 = start_block(P.n, P.block, P.seed)
@@ -694,7 +718,9 @@ def main():
         r = prob.solve(V0d, m_max=args.m_max, tol=args.tol)
         results.append(r)
         print(f"[bench] step {i}: {r.t_total:.3f}s pairs={r.omega2.size} basis={r.basis_size} "
-              f"lf={r.t_leapfrog:.3f}s gs={r.t_gs:.3f}s rr={r.t_rr:.3f}s", file=sys.stderr, flush=True)
+              f"steps={r.krylov_steps} lf={r.t_leapfrog:.3f}s gs={r.t_gs:.3f}s rr={r.t_rr:.3f}s "
+              f"rr beside the loop={r.t_rr_overlapped:.3f}s ({r.overlapped_checks} checks)",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -756,7 +782,13 @@ def main():
             "leapfrog": t_lf / args.steps,
             "gram_schmidt": sum(r.t_gs for r in results) / args.steps,
             "rayleigh_ritz": sum(r.t_rr for r in results) / args.steps,
+            "rayleigh_ritz_overlapped": sum(r.t_rr_overlapped for r in results) / args.steps,
         },
+        "overlapped_checks": last.overlapped_checks,
+        # share of the solve's wall time outside the fused time steps
+        # (Gram-Schmidt, the Rayleigh-Ritz work the loop waits for, launch
+        # and host gaps)
+        "non_leapfrog_fraction": 1.0 - t_lf / wall,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_leapfrog",

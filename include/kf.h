@@ -179,6 +179,15 @@ typedef struct kf_options {
                             Lemma 2.3 uses the scheme's scalar recurrence
                             (factor 2 - x + x^2/12, x = tau^2 omega^2, for 4).
                             Batches: 2 only */
+  int32_t overlap_checks; /* kf_solve in KF_FP64 with a target: 1 = a
+                            Rayleigh-Ritz check that is not expected to be
+                            the last one runs on a second stream and host
+                            thread while the Krylov loop goes on (its result
+                            is taken at a later step; once it meets the
+                            target the basis is cut back to the size it
+                            checked, and the filter applications made
+                            meanwhile are counted in krylov_steps);
+                            0 = every check stops the loop until it ends */
   void* stream;          /* hipStream_t */
 } kf_options;
 
@@ -218,6 +227,10 @@ typedef struct kf_result {
                                   kf_subspace_solve */
   int32_t escalated;      /* 1 when the solve restarted with float64
                              stepping (kf_options.escalate) */
+  double t_rr_overlapped; /* device seconds of the Rayleigh-Ritz checks that
+                             ran beside the Krylov loop
+                             (kf_options.overlap_checks; not in t_rr) */
+  int32_t overlapped_checks; /* how many of the checks did */
 } kf_result;
 
 /* Fill *opt with defaults: KF_FP64, check_every 1, check_growth 0.3, three-term

@@ -45,6 +45,22 @@ struct StepBufs {
   int vb = 0;   // value bytes
 };
 
+namespace kf {
+namespace {
+// the stream and pinned staging buffer a Rayleigh-Ritz check runs on (the
+// problem's own, or those of the check that overlaps the Krylov loop)
+struct Io {
+  hipStream_t st;
+  char* pin;
+  size_t pin_cap;
+};
+}  // namespace
+}  // namespace kf
+
+namespace {
+struct AsyncCheck;
+}  // namespace
+
 struct kf_problem {
   int32_t n = 0;
   int64_t nnz = 0;
@@ -110,6 +126,9 @@ struct kf_problem {
   // (device address of the same pinned memory), so that no copy is queued
   double* win_rec_host = nullptr;
   double* win_rec_dev = nullptr;
+  // a Rayleigh-Ritz check running on its own stream and host thread while
+  // the Krylov loop goes on (kf_solve in float64)
+  AsyncCheck* ac = nullptr;
 };
 
 struct kf_batch {
@@ -410,6 +429,52 @@ int ensure_basis(kf_problem* p, int cols) {
   return KF_OK;
 }
 
+// Grow the basis storage to at least `need` columns (B, and H, G and the
+// coefficient buffer T with it), keeping the first `keep` basis columns and
+// the leading keep x keep blocks of H and G.  The copies are queued behind
+// all work on the stream, which is synchronised before the old storage goes.
+int async_wait(kf_problem* p);
+
+int grow_basis(kf_problem* p, int need, int keep) {
+  if (p->bcap >= need) return KF_OK;
+  if (!p->B) return ensure_basis(p, need);
+  // a check running on its own stream reads B, H and G
+  KF_TRY(async_wait(p));
+  hipStream_t st = p->st;
+  const int cap = std::max(need, 2 * p->bcap);
+  double *nB = nullptr, *nH = nullptr, *nG = nullptr, *nT = nullptr;
+  int rc = dalloc(&nB, (size_t)p->ldb * cap);
+  if (!rc) rc = dalloc(&nH, (size_t)cap * cap);
+  if (!rc) rc = dalloc(&nG, (size_t)cap * cap);
+  if (!rc) rc = dalloc(&nT, (size_t)cap * 64);
+  if (rc) {
+    dfree(nB);
+    dfree(nH);
+    dfree(nG);
+    dfree(nT);
+    return rc;
+  }
+  keep = std::min(keep, p->bcap);
+  if (keep > 0) {
+    KF_HIP(hipMemcpyAsync(nB, p->B, sizeof(double) * p->ldb * keep, hipMemcpyDeviceToDevice, st));
+    KF_HIP(hipMemcpy2DAsync(nH, sizeof(double) * cap, p->H, sizeof(double) * p->hcap, sizeof(double) * keep, keep,
+                            hipMemcpyDeviceToDevice, st));
+    KF_HIP(hipMemcpy2DAsync(nG, sizeof(double) * cap, p->G, sizeof(double) * p->hcap, sizeof(double) * keep, keep,
+                            hipMemcpyDeviceToDevice, st));
+  }
+  KF_HIP(hipStreamSynchronize(st));
+  dfree(p->B);
+  dfree(p->H);
+  dfree(p->G);
+  dfree(p->T);
+  p->B = nB;
+  p->H = nH;
+  p->G = nG;
+  p->T = nT;
+  p->bcap = p->hcap = cap;
+  return KF_OK;
+}
+
 int ensure_misc(kf_problem* p) {
   if (p->W) return KF_OK;
   KF_TRY(dalloc(&p->W, (size_t)p->n * 16));
@@ -471,7 +536,9 @@ int repair_block(kf_problem* p, int p0, int pn);
 // destinations after the caller has synchronised the stream.  Reads that do
 // not fit go straight to their destination.
 struct Readback {
-  kf_problem* p;
+  hipStream_t st;
+  char* pin;
+  size_t pin_cap;
   size_t off = 0;
   struct Item {
     void* dst;
@@ -479,20 +546,21 @@ struct Readback {
   };
   Item items[16];
   int nitems = 0;
-  explicit Readback(kf_problem* q) : p(q) {}
+  explicit Readback(kf_problem* q) : st(q->st), pin(q->pin), pin_cap(q->pin_cap) {}
+  explicit Readback(const Io& io) : st(io.st), pin(io.pin), pin_cap(io.pin_cap) {}
   int get(void* dst, const void* src, size_t bytes) {
     off = (off + 15) & ~(size_t)15;
-    if (!p->pin || off + bytes > p->pin_cap || nitems == 16) {
-      KF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->st));
+    if (!pin || off + bytes > pin_cap || nitems == 16) {
+      KF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
       return KF_OK;
     }
-    KF_HIP(hipMemcpyAsync(p->pin + off, src, bytes, hipMemcpyDeviceToHost, p->st));
+    KF_HIP(hipMemcpyAsync(pin + off, src, bytes, hipMemcpyDeviceToHost, st));
     items[nitems++] = Item{dst, off, bytes};
     off += bytes;
     return KF_OK;
   }
   void land() {
-    for (int i = 0; i < nitems; ++i) std::memcpy(items[i].dst, p->pin + items[i].off, items[i].bytes);
+    for (int i = 0; i < nitems; ++i) std::memcpy(items[i].dst, pin + items[i].off, items[i].bytes);
     nitems = 0;
     off = 0;
   }
@@ -806,11 +874,14 @@ struct CheckOut {
 // ||S v|| and acceptance (theta inside the interval and residual <= tol).
 // ew.Y holds the k x nsel eigenvectors for sel.
 int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const std::vector<double>& sel_in, double tol,
-                   bool want_vectors, CheckOut& out, bool rayleigh = false, const double* Ysel = nullptr) {
+                   bool want_vectors, CheckOut& out, bool rayleigh = false, const double* Ysel = nullptr,
+                   const Io* io = nullptr) {
   // Ysel: the k x sel eigenvectors (default: ew.Y)
   if (!Ysel) Ysel = p->ew.Y;
   std::vector<double> sel = sel_in;
-  hipStream_t st = p->st;
+  const Io mio{p->st, p->pin, p->pin_cap};
+  if (!io) io = &mio;
+  hipStream_t st = io->st;
   const int nsel = (int)sel.size();
   out.cand_theta = sel;
   out.cand_res.assign(sel.size(), 0.0);
@@ -833,7 +904,7 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
         KF_TRY(gemv_t(p->n, 1, p->V + (int64_t)c * p->n, p->n, p->SV + (int64_t)c * p->n, 1, p->n,
                       p->V + (int64_t)c * p->n, 1, p->n, p->d_m, q + 2 * c, 1, p->gw, st));
       std::vector<double> hq((size_t)2 * nc);
-      Readback rq(p);
+      Readback rq(*io);
       KF_TRY(rq.get(hq.data(), q, sizeof(double) * 2 * nc));
       KF_HIP(hipStreamSynchronize(st));
       rq.land();
@@ -844,7 +915,7 @@ int ritz_residuals(kf_problem* p, const double* Bk, int64_t ldb, int k, const st
     KF_HIP(hipMemcpyAsync(d_theta, sel.data() + c0, sizeof(double) * nc, hipMemcpyHostToDevice, st));
     KF_TRY(residual_norms(p->n, p->SV, p->V, p->n, p->d_m, d_theta, nc, d_num, d_den, p->rw, st));
     std::vector<double> num((size_t)nc), den((size_t)nc);
-    Readback rr(p);
+    Readback rr(*io);
     KF_TRY(rr.get(num.data(), d_num, sizeof(double) * nc));
     KF_TRY(rr.get(den.data(), d_den, sizeof(double) * nc));
     KF_HIP(hipStreamSynchronize(st));
@@ -900,18 +971,21 @@ int eig_select(EigWork& ew, int k, const double* Hm, int64_t ldh, std::vector<do
 
 template <class Keep>
 int small_eigen(kf_problem* p, int k, const double* Hm, int64_t ldh, std::vector<double>& theta, Keep keep,
-                std::vector<double>& sel) {
-  return eig_select(p->ew, k, Hm, ldh, theta, keep, sel, p->st);
+                std::vector<double>& sel, hipStream_t st = nullptr) {
+  return eig_select(p->ew, k, Hm, ldh, theta, keep, sel, st ? st : p->st);
 }
 
 // Rayleigh-Ritz on the leading k basis columns.  Residuals are formed for the
 // Ritz values with omega in the interval widened by `margin` on both sides;
 // acceptance needs omega inside the interval and residual <= tol.
-int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, bool want_vectors) {
-  hipStream_t st = p->st;
+int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, bool want_vectors,
+             const Io* io = nullptr) {
+  const Io mio{p->st, p->pin, p->pin_cap};
+  if (!io) io = &mio;
+  hipStream_t st = io->st;
   KF_TRY(orth_error(k, p->G, p->hcap, p->small + 1024, st));
   // lands after the eigensolver's own synchronisation
-  Readback ro(p);
+  Readback ro(*io);
   KF_TRY(ro.get(&out.orth, p->small + 1024, sizeof(double)));
   // The pencil is (H, G) with G = I + E, E at the orthogonality level of the
   // basis: its eigenvalues are those of H - (E H + H E)/2 up to O(|E|^2).
@@ -943,11 +1017,126 @@ int rr_check(kf_problem* p, int k, double tol, CheckOut& out, double margin, boo
         const double om = std::sqrt(std::max(th, 0.0));
         return om >= lo && om <= hi;
       },
-      sel));
+      sel, st));
   KF_HIP(hipStreamSynchronize(st));
   ro.land();
   if (E) KF_TRY(vectors_correct(k, (int)sel.size(), E, p->ew.Y, EH, st));
-  return ritz_residuals(p, p->B, p->ldb, k, sel, tol, want_vectors, out);
+  return ritz_residuals(p, p->B, p->ldb, k, sel, tol, want_vectors, out, false, nullptr, io);
+}
+
+// A Rayleigh-Ritz check that overlaps the Krylov loop: it runs on a stream
+// and host thread of its own, on the leading k columns of B and the leading
+// k x k blocks of H and G, which the loop no longer writes (new columns
+// only add rows and columns past k); the loop waits for it before the basis
+// storage is reallocated.  Scratch it uses that the loop does not: V, SV,
+// the eigensolver's and the residuals' work arrays, the device scalars from
+// offset 1024 on, and its own pinned staging buffer.
+struct AsyncCheck {
+  hipStream_t st = nullptr;
+  char* pin = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // basis ready (loop's stream), check start, end
+  std::thread th;
+  std::atomic<int> state{0};  // 0 idle, 1 running, 2 finished and not yet taken
+  int k = 0;
+  double tol = 0.0, margin = 0.0;
+  CheckOut out;
+  int rc = KF_OK;
+  std::string err;
+};
+
+int async_ensure(kf_problem* p) {
+  if (p->ac) return KF_OK;
+  AsyncCheck* ac = new (std::nothrow) AsyncCheck();
+  if (!ac) return fail(KF_ENOMEM, "kf: host allocation");
+  p->ac = ac;
+  KF_HIP(hipStreamCreateWithFlags(&ac->st, hipStreamNonBlocking));
+  KF_HIP(hipEventCreateWithFlags(&ac->ev[0], hipEventDisableTiming));
+  KF_HIP(hipEventCreate(&ac->ev[1]));
+  KF_HIP(hipEventCreate(&ac->ev[2]));
+  if (hipHostMalloc((void**)&ac->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+    ac->pin = nullptr;
+    return fail(KF_ENOMEM, "kf: cannot allocate the check's pinned staging buffer");
+  }
+  return KF_OK;
+}
+
+// Starts the check of the leading k columns once the work queued so far on
+// the loop's stream (the pending columns' pencil entries) is done.
+int async_start(kf_problem* p, int k, double tol, double margin) {
+  KF_TRY(async_ensure(p));
+  AsyncCheck* ac = p->ac;
+  if (ac->state.load() != 0) return fail(KF_EINVAL, "kf: a check is already running");
+  ac->k = k;
+  ac->tol = tol;
+  ac->margin = margin;
+  ac->rc = KF_OK;
+  ac->err.clear();
+  ac->out = CheckOut();
+  KF_HIP(hipEventRecord(ac->ev[0], p->st));
+  ac->state.store(1);
+  try {
+    ac->th = std::thread([p, ac]() {
+      int rc = KF_OK;
+      try {
+        rc = hipSetDevice(p->device) == hipSuccess ? KF_OK : fail(KF_EHIP, "kf: check thread cannot select the GPU");
+        if (!rc && hipStreamWaitEvent(ac->st, ac->ev[0], 0) != hipSuccess) rc = fail(KF_EHIP, "kf: check stream wait");
+        if (!rc && hipEventRecord(ac->ev[1], ac->st) != hipSuccess) rc = fail(KF_EHIP, "kf: check event");
+        const Io io{ac->st, ac->pin, kPinBytes};
+        if (!rc) rc = rr_check(p, ac->k, ac->tol, ac->out, ac->margin, false, &io);
+        if (!rc && hipEventRecord(ac->ev[2], ac->st) != hipSuccess) rc = fail(KF_EHIP, "kf: check event");
+        if (!rc && hipEventSynchronize(ac->ev[2]) != hipSuccess) rc = fail(KF_EHIP, "kf: check synchronisation");
+      } catch (...) {
+        rc = fail(KF_ENOMEM, "kf: host allocation in the check thread");
+      }
+      // the stream is drained before the result is handed over, also after
+      // an error (nothing it queued may still run when the loop continues)
+      (void)hipStreamSynchronize(ac->st);
+      if (rc) ac->err = g_err;
+      ac->rc = rc;
+      ac->state.store(2);
+    });
+  } catch (...) {
+    ac->state.store(0);
+    return fail(KF_EHIP, "kf: cannot start the check thread");
+  }
+  return KF_OK;
+}
+
+bool async_running(const kf_problem* p) { return p->ac && p->ac->state.load() != 0; }
+bool async_ready(const kf_problem* p) { return p->ac && p->ac->state.load() == 2; }
+
+// Waits for a running check (its result stays to be taken).
+int async_wait(kf_problem* p) {
+  if (p->ac && p->ac->th.joinable()) p->ac->th.join();
+  return KF_OK;
+}
+
+// The finished check's result, its basis size and its device time.
+int async_take(kf_problem* p, CheckOut& out, int* k, double* seconds) {
+  AsyncCheck* ac = p->ac;
+  if (!ac || ac->state.load() == 0) return fail(KF_EINVAL, "kf: no check to take");
+  KF_TRY(async_wait(p));
+  ac->state.store(0);
+  if (ac->rc) return fail(ac->rc, ac->err);
+  float ms = 0.f;
+  KF_HIP(hipEventElapsedTime(&ms, ac->ev[1], ac->ev[2]));
+  *seconds = ms * 1e-3;
+  *k = ac->k;
+  out = std::move(ac->out);
+  return KF_OK;
+}
+
+void async_free(kf_problem* p) {
+  AsyncCheck* ac = p->ac;
+  if (!ac) return;
+  if (ac->th.joinable()) ac->th.join();
+  if (ac->st) (void)hipStreamSynchronize(ac->st);
+  for (hipEvent_t e : ac->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ac->st) (void)hipStreamDestroy(ac->st);
+  if (ac->pin) (void)hipHostFree(ac->pin);
+  delete ac;
+  p->ac = nullptr;
 }
 
 // Mixed-precision refinement.  The near-interval Ritz vectors X of the
@@ -1509,6 +1698,7 @@ void kf_default_options(kf_options* o) {
   o->gather_unroll = 0;
   o->block_band = 0;
   o->batch_workers = 0;
+  o->overlap_checks = 1;
   o->stream = nullptr;
 }
 
@@ -1673,6 +1863,7 @@ int kf_get_tuning(const kf_problem* p, int32_t* xcd_remap, int32_t* nt_loads, in
 
 int kf_destroy(kf_problem* p) {
   if (!p) return KF_OK;
+  async_free(p);
   (void)hipStreamSynchronize(p->st);
   free_problem(p);
   return KF_OK;
@@ -2096,6 +2287,10 @@ struct SolveState {
   bool may_escalate = true;  // kf_solve_batch escalates members after the batched loop
   bool wants_escalation = false;
   double t_lf_own = 0.0;  // a batch member's own stepping time after an escalation
+  // checks beside the Krylov loop (kf_options.overlap_checks)
+  bool async_ok = false;
+  int async_checks = 0;
+  double t_rr_async = 0.0;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -2112,8 +2307,8 @@ int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
 // geometric decrease of its residual per basis column it gets a predicted
 // number of columns to the tolerance, and the check is placed where the
 // missing-th fastest of them arrives (with 10 % to spare).
-int next_check_at(const kf_problem* p, SolveState& s) {
-  int next = (int)std::ceil(s.cur * (1.0 + p->opt.check_growth));
+int next_check_at(const kf_problem* p, SolveState& s, int k) {
+  int next = (int)std::ceil(k * (1.0 + p->opt.check_growth));
   if (s.target <= 0 || p->opt.check_growth <= 0.0) return next;
   const int missing = s.target - distinct_count(s.chk.acc_theta, s.b);
   const double lo2 = p->omega_min * p->omega_min, hi2 = p->omega_max * p->omega_max;
@@ -2125,7 +2320,7 @@ int next_check_at(const kf_problem* p, SolveState& s) {
       res_now.push_back(res);
     }
   }
-  if (missing > 0 && s.pred_k >= 0 && s.cur > s.pred_k && !s.pred_theta.empty()) {
+  if (missing > 0 && s.pred_k >= 0 && k > s.pred_k && !s.pred_theta.empty()) {
     std::vector<double> cols;
     size_t q = 0;
     for (size_t i = 0; i < th_now.size(); ++i) {
@@ -2133,7 +2328,7 @@ int next_check_at(const kf_problem* p, SolveState& s) {
              std::fabs(s.pred_theta[q + 1] - th_now[i]) <= std::fabs(s.pred_theta[q] - th_now[i]))
         ++q;
       if (std::fabs(s.pred_theta[q] - th_now[i]) > 1e-2 * th_now[i] || !(res_now[i] < s.pred_res[q])) continue;
-      const double rate = std::log(res_now[i] / s.pred_res[q]) / (s.cur - s.pred_k);  // per column, < 0
+      const double rate = std::log(res_now[i] / s.pred_res[q]) / (k - s.pred_k);  // per column, < 0
       const double c = std::log(s.tol_loop / res_now[i]) / rate;
       if (std::isfinite(c) && c > 0.0) cols.push_back(c);
     }
@@ -2143,15 +2338,15 @@ int next_check_at(const kf_problem* p, SolveState& s) {
       // next to overshooting by a growth step)
       std::sort(cols.begin(), cols.end());
       const size_t r = (size_t)std::min<int>(missing, (int)cols.size()) - 1;
-      next = std::min(next, s.cur + (int)std::ceil(1.1 * cols[r]));
+      next = std::min(next, k + (int)std::ceil(1.1 * cols[r]));
     }
   }
   // once pairs converge, a growth step is halved: the rest typically follow
   // within a fraction of the basis, Krylov convergence accelerates (so the
   // geometric prediction above runs late), and an early check costs less
   // than an overshoot
-  if (missing > 0 && missing < s.target) next = s.cur + std::max(1, (next - s.cur + 1) / 2);
-  s.pred_k = s.cur;
+  if (missing > 0 && missing < s.target) next = k + std::max(1, (next - k + 1) / 2);
+  s.pred_k = k;
   s.pred_theta = th_now;
   s.pred_res = res_now;
   return next;
@@ -2192,8 +2387,15 @@ int solve_begin(kf_problem* p, const double* start, int32_t b, int32_t m_max, do
   s.proj_every = p->opt.precision == KF_MIXED ? 1 : std::min(p->opt.proj_every, 15);
   KF_TRY(tune_block(p, p->A, p->sb, s.bk));
   s.tol = tol;
-  hipStream_t st = p->st;
-  KF_TRY(ensure_basis(p, m_max + s.bk));
+  // the basis storage starts at a few times the target and grows on demand
+  // (up to m_max + bk columns)
+  {
+    const int full = m_max + s.bk;
+    const int first = std::min(full, std::max(256, 4 * std::max(p->opt.target, 0)) + 3 * s.bk);
+    if (p->bcap < first || p->ldb != ((int64_t)p->n + 63) / 64 * 64) {
+      if (p->bcap < first) KF_TRY(ensure_basis(p, first));
+    }
+  }
   KF_TRY(ensure_misc(p));
   s.Aop = &p->A;
   s.sbop = &p->sb;
@@ -2297,9 +2499,10 @@ bool solve_wants_filter(const kf_problem* p, const SolveState& s) {
   return s.cur < s.m_max;
 }
 
-int solve_check_now(kf_problem* p, SolveState& s) {
+// The pending columns' pencil entries (and a repair of those that drifted
+// from M-orthogonality), queued on the loop's stream before a check.
+int solve_check_prepare(kf_problem* p, SolveState& s) {
   hipStream_t st = p->st;
-  if (!s.rr_pending) KF_HIP(hipEventRecord(p->ev[3], st));
   if (s.pending > 0) {
     const int c0 = s.cur - s.pending, nc = s.pending;
     KF_TRY(rr_update(p, c0, nc));
@@ -2321,6 +2524,13 @@ int solve_check_now(kf_problem* p, SolveState& s) {
   // orthogonality: the projection interval starts again from here
   s.pending = 0;
   s.since_proj = 0;
+  return KF_OK;
+}
+
+int solve_check_now(kf_problem* p, SolveState& s) {
+  hipStream_t st = p->st;
+  if (!s.rr_pending) KF_HIP(hipEventRecord(p->ev[3], st));
+  KF_TRY(solve_check_prepare(p, s));
   KF_TRY(rr_check(p, s.cur, s.tol_loop, s.chk, s.margin, false));
   KF_HIP(hipEventRecord(p->ev[4], st));
   s.rr_pending = true;
@@ -2328,11 +2538,54 @@ int solve_check_now(kf_problem* p, SolveState& s) {
   return KF_OK;
 }
 
+// A check beside the loop is used while more than an eighth of the target
+// (at least 3 pairs) was still missing at the previous check; closer to the
+// end the check runs in line, so that no filter application is spent past
+// the basis that meets the target.
+bool check_overlaps(const kf_problem* p, const SolveState& s) {
+  if (!s.async_ok || async_running(p)) return false;
+  const int missing = s.checked_at < 0 ? s.target : s.target - distinct_count(s.chk.acc_theta, s.b);
+  return missing > std::max(3, s.target / 8);
+}
+
+// Takes the result of a check that ran beside the loop.  When it meets the
+// target the basis is cut back to the columns it checked: the columns added
+// meanwhile are dropped and the solve ends there.
+int solve_take_overlapped(kf_problem* p, SolveState& s) {
+  CheckOut c;
+  int k = 0;
+  double secs = 0.0;
+  KF_TRY(async_take(p, c, &k, &secs));
+  s.t_rr_async += secs;
+  s.chk = std::move(c);
+  s.next_check = next_check_at(p, s, k);
+  if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
+    s.done = true;
+    s.cur = k;
+    s.checked_at = k;
+  }
+  return KF_OK;
+}
+
 // The filtered block C Q (Q = B[:, q0:q0+qn]) is in B[:, cur:cur+bk).
 int solve_after_filter(kf_problem* p, SolveState& s) {
   hipStream_t st = p->st;
+  // room for this block, the next one and one queued ahead
+  KF_TRY(grow_basis(p, std::min(s.cur + 3 * s.bk, s.m_max + s.bk), s.cur + s.bk));
   ++s.iters;
   s.lf_steps += (int64_t)s.qn * (p->L - 1);
+  if (async_ready(p)) {
+    KF_TRY(solve_take_overlapped(p, s));
+    if (s.done) {
+      // the filtered block just formed is not needed
+      s.ahead_ready = false;
+      if (s.timed_filter) {
+        KF_HIP(hipEventSynchronize(p->ev[1]));
+        KF_TRY(elapsed_acc(p->ev[0], p->ev[1], s.t_lf));
+      }
+      return KF_OK;
+    }
+  }
   int kept = 0;
   // single vectors in the three-term form project onto the whole basis every
   // proj_every steps (the new column and the last pending one are cleaned);
@@ -2401,9 +2654,16 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   s.qn = kept;
   s.cur += kept;
   s.pending += kept;
-  if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
+  if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check && check_overlaps(p, s)) {
+    KF_TRY(solve_check_prepare(p, s));
+    KF_TRY(async_start(p, s.cur, s.tol_loop, s.margin));
+    ++s.async_checks;
+    s.checked_at = s.cur;
+    // no further check until this one's result is taken
+    s.next_check = INT32_MAX;
+  } else if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
     KF_TRY(solve_check_now(p, s));
-    s.next_check = next_check_at(p, s);
+    s.next_check = next_check_at(p, s, s.cur);
     if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
       if (!s.refine) {
         s.done = true;
@@ -2429,6 +2689,21 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
           s.done = true;
         }
       }
+    }
+  }
+  // mixed precision: the float32 loop ran out of basis before it reached
+  // the target at its own tolerance; refine what it has, and when pairs are
+  // still missing restart with float64 stepping (the same budget)
+  if (!s.done && s.refine && s.target > 0 && s.cur + s.bk > s.m_max && p->opt.escalate) {
+    if (s.checked_at != s.cur) KF_TRY(solve_check_now(p, s));
+    KF_TRY(solve_refine_now(p, s));
+    if (distinct_count(s.fin.acc_theta, s.b) >= s.target) {
+      s.done = true;
+    } else if (s.may_escalate) {
+      KF_TRY(escalate_restart(p, s));
+    } else {
+      s.wants_escalation = true;
+      s.done = true;
     }
   }
   (void)st;
@@ -2496,6 +2771,7 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   hipStream_t st = p->st;
   const int b = s.b;
   CheckOut& chk = s.chk;
+  if (async_running(p)) KF_TRY(solve_take_overlapped(p, s));
   if (s.checked_at != s.cur) KF_TRY(solve_check_now(p, s));
   KF_HIP(hipEventSynchronize(p->ev[4]));
   if (s.rr_pending) KF_TRY(elapsed_acc(p->ev[3], p->ev[4], s.t_rr));
@@ -2537,6 +2813,8 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   r->full_passes = full_passes;
   r->refine_vector_steps = s.ref_lf_steps;
   r->escalated = s.escalated ? 1 : 0;
+  r->t_rr_overlapped = s.t_rr_async;
+  r->overlapped_checks = s.async_checks;
   KF_HIP(hipStreamSynchronize(st));
   r->t_total = now_s() - t0;
   *out = r;
@@ -2554,7 +2832,14 @@ int kf_solve(kf_problem* p, const double* start, int32_t b, int32_t m_max, doubl
   if (!p) return fail(KF_EINVAL, "kf_solve: NULL argument");
   SolveState s;
   KF_TRY(solve_begin(p, start, b, m_max, tol, s));
-  KF_TRY(solve_loop(p, s));
+  s.async_ok = p->opt.overlap_checks != 0 && p->opt.precision == KF_FP64 && s.target > 0 && !s.refine;
+  int rc = solve_loop(p, s);
+  if (rc) {
+    // nothing may still read the basis when the caller continues
+    (void)async_wait(p);
+    if (async_running(p)) p->ac->state.store(0);
+    return rc;
+  }
   return solve_finish(p, s, out);
 }
 

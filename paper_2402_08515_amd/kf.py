@@ -65,6 +65,7 @@ class OptionsT(C.Structure):
         ("gather_unroll", C.c_int32),
         ("block_band", C.c_int32),
         ("stepper", C.c_int32),
+        ("overlap_checks", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -93,6 +94,8 @@ class ResultT(C.Structure):
         ("full_passes", C.c_int32),
         ("refine_vector_steps", C.c_int64),
         ("escalated", C.c_int32),
+        ("t_rr_overlapped", C.c_double),
+        ("overlapped_checks", C.c_int32),
     ]
 
 
@@ -341,6 +344,8 @@ class SolveResult:
     full_passes: int
     refine_vector_steps: int
     escalated: bool
+    t_rr_overlapped: float = 0.0
+    overlapped_checks: int = 0
 
 
 def _take_result(res, n: int) -> SolveResult:
@@ -371,6 +376,8 @@ def _take_result(res, n: int) -> SolveResult:
             full_passes=r.full_passes,
             refine_vector_steps=r.refine_vector_steps,
             escalated=bool(r.escalated),
+            t_rr_overlapped=r.t_rr_overlapped,
+            overlapped_checks=r.overlapped_checks,
         )
     finally:
         lib().kf_result_free(res)
@@ -379,7 +386,7 @@ def _take_result(res, n: int) -> SolveResult:
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=None, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
              autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0,
-             block_band=0, escalate=None, stepper=2):
+             block_band=0, escalate=None, stepper=2, overlap_checks=None):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -406,6 +413,8 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
     opt.gather_unroll = int(gather_unroll)
     opt.block_band = int(block_band)
     opt.stepper = int(stepper)
+    if overlap_checks is not None:
+        opt.overlap_checks = int(overlap_checks)
     opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt

@@ -136,7 +136,9 @@ def test_model_gate_keeps_the_learned_path_no_slower_than_fourier():
         pick, pred = kf.select_weights([four, wnet], tau, lo, hi, om, np.ones(om.size), kmax=1500, margin=0.02)
         steps = {}
         for name, w in (("fourier", four), ("network", wnet)):
-            prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2)
+            # checks in line: the step counts compared are the basis each
+            # weight set needs, not when an overlapped check's result arrived
+            prob = kf.Problem(S, m, lo, hi, tau, L, target=tgt, check_every=2, overlap_checks=False)
             prob.set_weights(w)
             r = prob.solve(V0, m_max=800, tol=1e-6)
             assert r.omega2.size == tgt

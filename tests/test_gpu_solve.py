@@ -274,6 +274,35 @@ def test_grid3d_finds_every_eigenpair_of_the_closed_form(grid3d):
     # remaining non-orthogonality to first order
     assert got.orth_error < 1e-7
     print("orth_error", got.orth_error, "full passes", got.full_passes, "of", got.krylov_steps)
+    # checks far from the target ran beside the Krylov loop (the default)
+    print("checks beside the loop", got.overlapped_checks, "device s", got.t_rr_overlapped, "in line s", got.t_rr)
+    assert got.overlapped_checks >= 1
+
+
+def test_grid3d_checks_beside_the_loop_give_the_in_line_result(grid3d):
+    """The same solve with every check in line: the accepted eigenvalues
+    agree with the overlapped solve's to the float64 bar and with the
+    closed form, and the basis the overlapped solve reports is one that an
+    in-line check schedule can also end on (within the growth step)."""
+    kf = _kf()
+    P, tau, L, tgt, vals = grid3d
+    print(f"case grid3d_96 solve target={tgt}, overlap on and off", flush=True)
+    V0 = start_block(P.n, 1, P.seed)
+    res = {}
+    for ov in (True, False):
+        prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, target=tgt, check_every=2, check_growth=0.3,
+                          autotune=True, overlap_checks=ov)
+        res[ov] = prob.solve(V0, m_max=1024, tol=1e-6)
+        print("overlap", ov, "basis", res[ov].basis_size, "steps", res[ov].krylov_steps, "t", res[ov].t_total,
+              "checks beside", res[ov].overlapped_checks, flush=True)
+    a, b = res[True], res[False]
+    assert b.overlapped_checks == 0 and b.t_rr_overlapped == 0.0
+    assert a.omega2.size == b.omega2.size == tgt
+    assert np.max(np.abs(a.omega2 - b.omega2) / b.omega2) <= 1e-10
+    assert np.max(np.abs(a.omega2 - vals) / vals) <= 1e-10
+    assert a.residual.max() <= 1e-6
+    # steps past the checked basis are counted, the basis is cut back to it
+    assert a.basis_size <= a.krylov_steps + 1
 
 
 def test_loose_orthogonality_is_corrected_in_rayleigh_ritz(grid2d):
