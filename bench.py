@@ -153,6 +153,7 @@ def bench_batch(args):
     from synth.netinit import init_params
     from synth.workloads import batch64_slices, filter_samples
 
+    os.environ.setdefault("KF_PROGRESS", "1")  # the library reports the batched loop's progress on stderr
     slices = batch64_slices(args.slice_target, args.batch_count)
     lam_of, members, starts, meta = {}, [], [], []
     for (i, P, lo, hi, tgt) in slices:

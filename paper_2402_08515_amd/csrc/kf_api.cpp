@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -131,29 +132,39 @@ struct kf_problem {
   AsyncCheck* ac = nullptr;
 };
 
+// One stacked block-diagonal operator of a batch with its step buffers,
+// weight table and captured filter graph.  A batch in KF_MIXED holds two:
+// the float32 stack every member starts on, and a float64 stack that the
+// members restarted with float64 stepping (kf_options.escalate) continue on
+// inside the same batched loop.
+struct BatchStack {
+  SellOp A;
+  void* wtab = nullptr;  // P x lmax weights, in the stack's precision
+  StepBufs sb;
+  BatchTables h_tb{};    // per-member tables of the next launch (active members of this stack)
+  BatchTables* d_tb = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_bk = 0;
+  int remap = 1;  // XCD mapping of the batched step (timed with autotune)
+  bool tuned = false;
+};
+
 struct kf_batch {
   int P = 0;
   int workers = 1;  // host threads driving the members' projection work
   std::vector<kf_problem*> probs;
   hipStream_t st = nullptr;
-  SellOp A;                  // stacked block-diagonal operator, stepping precision
+  BatchStack stk[2];
+  int nstk = 1;
   int32_t* d_sp = nullptr;   // slice -> problem
-  BatchTables h_tb{};
-  BatchTables* d_tb = nullptr;
-  void* wtab = nullptr;      // P x lmax weights, stepping precision
   int lmax = 1;
   int64_t rows = 0;
-  StepBufs sb;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int graph_bk = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // members are stacked by decreasing L: at step ell the members still
   // stepping own the first prefix[ell] row slices
   std::vector<int> prefix;
-  int remap = 1;      // XCD mapping of the batched step (timed with autotune)
   int autotune = 0;
-  bool tuned = false;
 };
 
 namespace {
@@ -2284,7 +2295,8 @@ struct SolveState {
   StepBufs* sbop = nullptr;
   const double* start = nullptr;  // the caller's start block (valid for the call)
   bool escalated = false;
-  bool may_escalate = true;  // kf_solve_batch escalates members after the batched loop
+  bool may_escalate = true;  // false: a batch without a float64 stack escalates members after its loop
+  bool in_batch = false;     // the filter is the batch's stacked launch
   bool wants_escalation = false;
   double t_lf_own = 0.0;  // a batch member's own stepping time after an escalation
   // checks beside the Krylov loop (kf_options.overlap_checks)
@@ -2472,7 +2484,8 @@ int escalate_restart(kf_problem* p, SolveState& s) {
   s.proj_every = std::min(p->opt.proj_every, 15);
   s.since_proj = 0;
   s.ahead_ready = false;
-  KF_TRY(tune_block(p, p->A64, p->sb64, s.bk));
+  // (a batch member steps in the batch's float64 stack instead)
+  if (!s.in_batch) KF_TRY(tune_block(p, p->A64, p->sb64, s.bk));
   int kept = 0;
   KF_TRY(load_start(p, s, &kept));
   s.cur = kept;
@@ -2962,61 +2975,70 @@ int kf_copy_basis(const kf_problem* p, double* out, int32_t max_cols, int32_t* n
 
 namespace {
 
+void free_stack(BatchStack& k) {
+  if (k.exec) (void)hipGraphExecDestroy(k.exec);
+  if (k.graph) (void)hipGraphDestroy(k.graph);
+  k.exec = nullptr;
+  k.graph = nullptr;
+  free_sell(k.A);
+  dfree(k.d_tb);
+  k.d_tb = nullptr;
+  dfree(k.wtab);
+  k.wtab = nullptr;
+  free_step_buffers(k.sb);
+}
+
 void free_batch(kf_batch* bt) {
   if (!bt) return;
   if (bt->st) (void)hipStreamSynchronize(bt->st);
-  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  for (BatchStack& k : bt->stk) free_stack(k);
   for (kf_problem* p : bt->probs) kf_destroy(p);
-  free_sell(bt->A);
   dfree(bt->d_sp);
-  dfree(bt->d_tb);
-  dfree(bt->wtab);
-  free_step_buffers(bt->sb);
   for (hipEvent_t e : bt->ev)
     if (e) (void)hipEventDestroy(e);
   if (bt->st) (void)hipStreamDestroy(bt->st);
   delete bt;
 }
 
-// Record the batched filter application (load + lmax-1 fused steps) for block
-// width bk once; replays read the per-problem tables from device memory.
-int ensure_batch_graph(kf_batch* bt, int bk) {
-  if (bt->exec && bt->graph_bk == bk) return KF_OK;
-  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-  if (bt->graph) (void)hipGraphDestroy(bt->graph);
-  bt->exec = nullptr;
-  bt->graph = nullptr;
+// Record the batched filter application of a stack (load + lmax-1 fused
+// steps) for block width bk once; replays read the per-problem tables from
+// device memory.
+int ensure_batch_graph(kf_batch* bt, BatchStack& k, int bk) {
+  if (k.exec && k.graph_bk == bk) return KF_OK;
+  if (k.exec) (void)hipGraphExecDestroy(k.exec);
+  if (k.graph) (void)hipGraphDestroy(k.graph);
+  k.exec = nullptr;
+  k.graph = nullptr;
   // stacked time-stepping buffers (rows x bk)
-  if (bt->sb.cap < bk || bt->sb.vb != bt->A.val_bytes) {
-    free_step_buffers(bt->sb);
-    const size_t bytes = (size_t)bt->rows * bk * bt->A.val_bytes;
-    if (hipMalloc(&bt->sb.Y0, bytes) != hipSuccess || hipMalloc(&bt->sb.Y1, bytes) != hipSuccess ||
-        hipMalloc(&bt->sb.R, bytes) != hipSuccess)
+  if (k.sb.cap < bk || k.sb.vb != k.A.val_bytes) {
+    free_step_buffers(k.sb);
+    const size_t bytes = (size_t)bt->rows * bk * k.A.val_bytes;
+    if (hipMalloc(&k.sb.Y0, bytes) != hipSuccess || hipMalloc(&k.sb.Y1, bytes) != hipSuccess ||
+        hipMalloc(&k.sb.R, bytes) != hipSuccess)
       return fail(KF_ENOMEM, "kf_batch: time-stepping buffers");
-    bt->sb.cap = bk;
-    bt->sb.vb = bt->A.val_bytes;
+    k.sb.cap = bk;
+    k.sb.vb = k.A.val_bytes;
   }
   hipStream_t st = bt->st;
-  if (bt->autotune && !bt->tuned) {
+  if (bt->autotune && !k.tuned) {
     // the batched step's variant (XCD mapping, operator loads), timed on a
     // middle step of every member before the graph is captured
-    BatchTables tt = bt->h_tb;
+    BatchTables tt = k.h_tb;
     for (int q = 0; q < bt->P; ++q) tt.active[q] = 1;
-    KF_HIP(hipMemcpyAsync(bt->d_tb, &tt, sizeof(BatchTables), hipMemcpyHostToDevice, st));
-    const size_t bytes = (size_t)bt->rows * bk * bt->A.val_bytes;
-    KF_HIP(hipMemsetAsync(bt->sb.Y0, 0, bytes, st));
-    KF_HIP(hipMemsetAsync(bt->sb.Y1, 0, bytes, st));
+    KF_HIP(hipMemcpyAsync(k.d_tb, &tt, sizeof(BatchTables), hipMemcpyHostToDevice, st));
+    const size_t bytes = (size_t)bt->rows * bk * k.A.val_bytes;
+    KF_HIP(hipMemsetAsync(k.sb.Y0, 0, bytes, st));
+    KF_HIP(hipMemsetAsync(k.sb.Y1, 0, bytes, st));
     double best = 1e300;
-    int best_remap = bt->remap, best_nt = bt->A.nt_loads;
+    int best_remap = k.remap, best_nt = k.A.nt_loads;
     for (int nt = 0; nt <= 1; ++nt)
       for (int remap = 0; remap <= 1; ++remap) {
-        bt->A.nt_loads = nt;
+        k.A.nt_loads = nt;
         for (int rep = 0; rep < 2; ++rep) {  // warm-up, then the timing
           KF_HIP(hipEventRecord(bt->ev[0], st));
           for (int t = 0; t < 10; ++t)
-            KF_TRY(launch_leapfrog_batch(bt->A, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, 2, bt->sb.Y1, bt->sb.Y0,
-                                         bt->sb.Y0, bt->sb.R, 0, remap, st));
+            KF_TRY(launch_leapfrog_batch(k.A, bk, bt->d_sp, k.d_tb, k.wtab, bt->lmax, 2, k.sb.Y1, k.sb.Y0, k.sb.Y0,
+                                         k.sb.R, 0, remap, st));
           KF_HIP(hipEventRecord(bt->ev[1], st));
         }
         KF_HIP(hipEventSynchronize(bt->ev[1]));
@@ -3028,16 +3050,16 @@ int ensure_batch_graph(kf_batch* bt, int bk) {
           best_nt = nt;
         }
       }
-    bt->remap = best_remap;
-    bt->A.nt_loads = best_nt;
-    bt->tuned = true;
+    k.remap = best_remap;
+    k.A.nt_loads = best_nt;
+    k.tuned = true;
   }
   KF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  int rc = launch_load_batch(bt->A.val_bytes, bt->rows, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, bt->sb.Y1, st);
-  void* Y[2] = {bt->sb.Y0, bt->sb.Y1};
+  int rc = launch_load_batch(k.A.val_bytes, bt->rows, bk, bt->d_sp, k.d_tb, k.wtab, bt->lmax, k.sb.Y1, st);
+  void* Y[2] = {k.sb.Y0, k.sb.Y1};
   for (int l = 1; l < bt->lmax && rc == KF_OK; ++l)
-    rc = launch_leapfrog_batch(bt->A, bk, bt->d_sp, bt->d_tb, bt->wtab, bt->lmax, l, Y[l & 1], Y[(l + 1) & 1],
-                               Y[(l + 1) & 1], bt->sb.R, bt->prefix[(size_t)l], bt->remap, st);
+    rc = launch_leapfrog_batch(k.A, bk, bt->d_sp, k.d_tb, k.wtab, bt->lmax, l, Y[l & 1], Y[(l + 1) & 1],
+                               Y[(l + 1) & 1], k.sb.R, bt->prefix[(size_t)l], k.remap, st);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);
   if (rc != KF_OK) {
@@ -3045,16 +3067,29 @@ int ensure_batch_graph(kf_batch* bt, int bk) {
     return rc;
   }
   if (e != hipSuccess) return fail(KF_EHIP, std::string("kf_batch: graph capture failed: ") + hipGetErrorString(e));
-  bt->graph = g;
-  KF_HIP(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
-  bt->graph_bk = bk;
+  k.graph = g;
+  KF_HIP(hipGraphInstantiate(&k.exec, k.graph, nullptr, nullptr, 0));
+  k.graph_bk = bk;
   return KF_OK;
 }
 
-int run_batch_filter(kf_batch* bt, int bk) {
-  KF_TRY(ensure_batch_graph(bt, bk));
-  KF_HIP(hipMemcpyAsync(bt->d_tb, &bt->h_tb, sizeof(BatchTables), hipMemcpyHostToDevice, bt->st));
-  KF_HIP(hipGraphLaunch(bt->exec, bt->st));
+int run_batch_filter(kf_batch* bt, BatchStack& k, int bk) {
+  KF_TRY(ensure_batch_graph(bt, k, bk));
+  KF_HIP(hipMemcpyAsync(k.d_tb, &k.h_tb, sizeof(BatchTables), hipMemcpyHostToDevice, bt->st));
+  KF_HIP(hipGraphLaunch(k.exec, bt->st));
+  return KF_OK;
+}
+
+// Weights of member q in a stack's table (its precision).
+int upload_weights(kf_batch* bt, BatchStack& k, int q, const double* w, int L) {
+  const int vb = k.A.val_bytes;
+  char* row = static_cast<char*>(k.wtab) + (size_t)q * bt->lmax * vb;
+  if (vb == 8) {
+    KF_HIP(hipMemcpy(row, w, sizeof(double) * L, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> w32(w, w + L);
+    KF_HIP(hipMemcpy(row, w32.data(), sizeof(float) * L, hipMemcpyHostToDevice));
+  }
   return KF_OK;
 }
 
@@ -3128,6 +3163,7 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     for (int q = 0; q < P; ++q) ord[(size_t)q] = q;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return descs[a].L > descs[b].L; });
     std::vector<int64_t> slices_of((size_t)P, 0);
+    BatchTables& tb0 = bt->stk[0].h_tb;
     for (int32_t oi = 0; oi < P && rc == KF_OK; ++oi) {
       const int q = ord[(size_t)oi];
       const kf_problem_desc& d = descs[q];
@@ -3151,9 +3187,9 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
       for (int64_t i = n; i < padded; ++i) rowptr.push_back((int32_t)col.size());
       for (int64_t s = 0; s < padded / 64; ++s) sp.push_back(q);
       slices_of[(size_t)q] = padded / 64;
-      bt->h_tb.row0[q] = row0;
-      bt->h_tb.n[q] = n;
-      bt->h_tb.L[q] = d.L;
+      tb0.row0[q] = row0;
+      tb0.n[q] = n;
+      tb0.L[q] = d.L;
       bt->lmax = std::max(bt->lmax, (int)d.L);
       row0 += padded;
     }
@@ -3172,30 +3208,42 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
     DevCsr dc;
     rc = upload_csr(hs, (int32_t)bt->rows, (int64_t)hs.col.size(), bt->st, dc);
     if (rc) break;
-    const int vb = o.precision == KF_MIXED ? 4 : 8;
-    rc = build_sell((int32_t)bt->rows, (int64_t)hs.col.size(), dc.rowptr, dc.col, dc.val, nullptr, vb, o.index_bytes,
-                    bt->st, bt->A);
-    if (rc) break;
-    bt->A.nt_loads = o.nt_loads ? 1 : 0;
+    // the stepping precision's stack, and in KF_MIXED the float64 stack of
+    // the members that restart with float64 stepping
+    const bool mixed = o.precision == KF_MIXED;
+    bt->nstk = mixed ? 2 : 1;
     if ((rc = dalloc(&bt->d_sp, sp.size()))) break;
-    if ((rc = dalloc(&bt->d_tb, 1))) break;
     std::vector<double> w64((size_t)P * bt->lmax, 0.0);
     for (int32_t q = 0; q < P; ++q)
       for (size_t l = 0; l < bt->probs[(size_t)q]->w.size(); ++l) w64[(size_t)q * bt->lmax + l] = bt->probs[(size_t)q]->w[l];
-    if (hipMalloc(&bt->wtab, w64.size() * vb) != hipSuccess) {
-      rc = fail(KF_ENOMEM, "kf_create_batch: weight table");
-      break;
+    for (int ks = 0; ks < bt->nstk && rc == KF_OK; ++ks) {
+      BatchStack& k = bt->stk[ks];
+      const int vb = (mixed && ks == 0) ? 4 : 8;
+      rc = build_sell((int32_t)bt->rows, (int64_t)hs.col.size(), dc.rowptr, dc.col, dc.val, nullptr, vb, o.index_bytes,
+                      bt->st, k.A);
+      if (rc) break;
+      k.A.nt_loads = o.nt_loads ? 1 : 0;
+      if ((rc = dalloc(&k.d_tb, 1))) break;
+      if (ks > 0) {
+        // the same member layout; no member is active here before it restarts
+        k.h_tb = tb0;
+        for (int q = 0; q < P; ++q) k.h_tb.active[q] = 0;
+      }
+      if (hipMalloc(&k.wtab, w64.size() * vb) != hipSuccess) {
+        rc = fail(KF_ENOMEM, "kf_create_batch: weight table");
+        break;
+      }
+      if (vb == 8) {
+        if (hipMemcpy(k.wtab, w64.data(), w64.size() * 8, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
+      } else {
+        std::vector<float> w32(w64.begin(), w64.end());
+        if (hipMemcpy(k.wtab, w32.data(), w32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
+      }
+      if (rc) set_error("kf_create_batch: weight table upload failed");
     }
-    if (vb == 8) {
-      if (hipMemcpy(bt->wtab, w64.data(), w64.size() * 8, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
-    } else {
-      std::vector<float> w32(w64.begin(), w64.end());
-      if (hipMemcpy(bt->wtab, w32.data(), w32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = KF_EHIP;
-    }
-    if (rc == KF_OK && hipMemcpy(bt->d_sp, sp.data(), sizeof(int32_t) * sp.size(), hipMemcpyHostToDevice) != hipSuccess)
-      rc = KF_EHIP;
-    if (rc) {
-      set_error("kf_create_batch: table upload failed");
+    if (rc) break;
+    if (hipMemcpy(bt->d_sp, sp.data(), sizeof(int32_t) * sp.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(KF_EHIP, "kf_create_batch: table upload failed");
       break;
     }
     for (hipEvent_t& e : bt->ev)
@@ -3213,14 +3261,7 @@ int kf_batch_set_weights(kf_batch* bt, int32_t q, const double* w, int32_t L) {
   if (!bt || q < 0 || q >= bt->P) return fail(KF_EINVAL, "kf_batch_set_weights: bad handle or member index");
   KF_TRY(kf_set_weights(bt->probs[(size_t)q], w, L));
   KF_HIP(hipStreamSynchronize(bt->st));
-  const int vb = bt->A.val_bytes;
-  char* row = static_cast<char*>(bt->wtab) + (size_t)q * bt->lmax * vb;
-  if (vb == 8) {
-    KF_HIP(hipMemcpy(row, w, sizeof(double) * L, hipMemcpyHostToDevice));
-  } else {
-    std::vector<float> w32(w, w + L);
-    KF_HIP(hipMemcpy(row, w32.data(), sizeof(float) * L, hipMemcpyHostToDevice));
-  }
+  for (int ks = 0; ks < bt->nstk; ++ks) KF_TRY(upload_weights(bt, bt->stk[ks], q, w, L));
   return KF_OK;
 }
 
@@ -3232,17 +3273,18 @@ int kf_destroy_batch(kf_batch* bt) {
 int kf_batch_apply_filter(kf_batch* bt, const double* const* x, double* const* y, int32_t b) {
   if (!bt || !x || !y) return fail(KF_EINVAL, "kf_batch_apply_filter: NULL argument");
   if (b < 1 || b > 16) return fail(KF_EINVAL, "kf_batch_apply_filter: b must lie in [1, 16]");
+  BatchTables& tb = bt->stk[0].h_tb;
   for (int q = 0; q < bt->P; ++q) {
     if (!x[q] || !y[q]) return fail(KF_EINVAL, "kf_batch_apply_filter: NULL block");
-    bt->h_tb.active[q] = 1;
-    bt->h_tb.src[q] = x[q];
-    bt->h_tb.lds[q] = bt->h_tb.n[q];
-    bt->h_tb.bsrc[q] = b;
-    bt->h_tb.dst[q] = y[q];
-    bt->h_tb.ld[q] = bt->h_tb.n[q];
-    bt->h_tb.bout[q] = b;
+    tb.active[q] = 1;
+    tb.src[q] = x[q];
+    tb.lds[q] = tb.n[q];
+    tb.bsrc[q] = b;
+    tb.dst[q] = y[q];
+    tb.ld[q] = tb.n[q];
+    tb.bout[q] = b;
   }
-  KF_TRY(run_batch_filter(bt, pow2ceil(b)));
+  KF_TRY(run_batch_filter(bt, bt->stk[0], pow2ceil(b)));
   KF_HIP(hipStreamSynchronize(bt->st));
   return KF_OK;
 }
@@ -3252,49 +3294,70 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
   if (!bt || !starts || !results) return fail(KF_EINVAL, "kf_solve_batch: NULL argument");
   for (int q = 0; q < bt->P; ++q) results[q] = nullptr;
   std::vector<SolveState> S((size_t)bt->P);
+  // with a float64 stack, members restart with float64 stepping inside the
+  // batched loop; otherwise after it, one after another
+  const bool in_loop = bt->nstk > 1;
   for (int q = 0; q < bt->P; ++q) {
+    S[(size_t)q].in_batch = true;
     int rc = solve_begin(bt->probs[(size_t)q], starts[q], b, m_max, tol, S[(size_t)q]);
     if (rc) {
       set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
       return rc;
     }
-    S[(size_t)q].may_escalate = false;
+    S[(size_t)q].may_escalate = in_loop;
   }
   const int bk = pow2ceil(b);
   double t_lf = 0.0;
+  // KF_PROGRESS set: one line on stderr every 100 batched filter launches
+  const bool progress = std::getenv("KF_PROGRESS") != nullptr;
+  int round = 0;
   while (true) {
-    bool any = false;
+    bool any[2] = {false, false};
     for (int q = 0; q < bt->P; ++q) {
       kf_problem* p = bt->probs[(size_t)q];
       SolveState& s = S[(size_t)q];
       const bool act = solve_wants_filter(p, s);
-      bt->h_tb.active[q] = act ? 1 : 0;
+      const int ks = (in_loop && s.escalated) ? 1 : 0;
+      for (int j = 0; j < bt->nstk; ++j) bt->stk[j].h_tb.active[q] = 0;
       if (!act) continue;
-      any = true;
-      bt->h_tb.src[q] = p->B + (int64_t)s.q0 * p->ldb;
-      bt->h_tb.lds[q] = p->ldb;
-      bt->h_tb.bsrc[q] = s.qn;
-      bt->h_tb.dst[q] = p->B + (int64_t)s.cur * p->ldb;
-      bt->h_tb.ld[q] = p->ldb;
-      bt->h_tb.bout[q] = bk;
+      any[ks] = true;
+      BatchTables& tb = bt->stk[ks].h_tb;
+      tb.active[q] = 1;
+      tb.src[q] = p->B + (int64_t)s.q0 * p->ldb;
+      tb.lds[q] = p->ldb;
+      tb.bsrc[q] = s.qn;
+      tb.dst[q] = p->B + (int64_t)s.cur * p->ldb;
+      tb.ld[q] = p->ldb;
+      tb.bout[q] = bk;
     }
-    if (!any) break;
+    if (!any[0] && !any[1]) break;
+    if (progress && ++round % 100 == 0) {
+      int na = 0, ne = 0;
+      for (int q = 0; q < bt->P; ++q) {
+        na += (bt->stk[0].h_tb.active[q] || (bt->nstk > 1 && bt->stk[1].h_tb.active[q])) ? 1 : 0;
+        ne += S[(size_t)q].escalated ? 1 : 0;
+      }
+      std::fprintf(stderr, "[kf] batch: %d filter launches, %d of %d members stepping, %d restarted in float64\n",
+                   round, na, bt->P, ne);
+      std::fflush(stderr);
+    }
     const bool par = bt->workers > 1;
     if (par) {
       // the filter reads the members' newest basis columns
       for (int q = 0; q < bt->P; ++q) {
-        if (!bt->h_tb.active[q]) continue;
+        if (!bt->stk[0].h_tb.active[q] && !(bt->nstk > 1 && bt->stk[1].h_tb.active[q])) continue;
         kf_problem* p = bt->probs[(size_t)q];
         KF_HIP(hipEventRecord(p->sync_ev, p->st));
         KF_HIP(hipStreamWaitEvent(bt->st, p->sync_ev, 0));
       }
     }
     KF_HIP(hipEventRecord(bt->ev[0], bt->st));
-    KF_TRY(run_batch_filter(bt, bk));
+    for (int ks = 0; ks < bt->nstk; ++ks)
+      if (any[ks]) KF_TRY(run_batch_filter(bt, bt->stk[ks], bk));
     KF_HIP(hipEventRecord(bt->ev[1], bt->st));
     std::vector<int> act;
     for (int q = 0; q < bt->P; ++q)
-      if (bt->h_tb.active[q]) act.push_back(q);
+      if (bt->stk[0].h_tb.active[q] || (bt->nstk > 1 && bt->stk[1].h_tb.active[q])) act.push_back(q);
     if (!par) {
       for (int q : act) {
         int rc = solve_after_filter(bt->probs[(size_t)q], S[(size_t)q]);
@@ -3328,16 +3391,15 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
     }
     KF_TRY(elapsed_acc(bt->ev[0], bt->ev[1], t_lf));
   }
-  // members whose float64 refinement missed the target: their own float64
-  // Krylov loop from the start block (see escalate_restart), one member after
-  // another on its own stream, outside the batched stepping
-  double t_esc = 0.0;
+  // (batches without a float64 stack) members whose float64 refinement
+  // missed the target: their own float64 Krylov loop from the start block
+  // (see escalate_restart), one member after another on its own stream
   for (int q = 0; q < bt->P; ++q) {
     SolveState& s = S[(size_t)q];
     if (!s.wants_escalation) continue;
     kf_problem* p = bt->probs[(size_t)q];
-    const double te = now_s();
     s.may_escalate = true;
+    s.in_batch = false;
     s.t_lf = 0.0;
     int rc = escalate_restart(p, s);
     if (!rc) rc = solve_loop(p, s);
@@ -3346,9 +3408,7 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
       return rc;
     }
     s.t_lf_own = s.t_lf;
-    t_esc += now_s() - te;
   }
-  (void)t_esc;
   for (int q = 0; q < bt->P; ++q) {
     S[(size_t)q].t_lf = t_lf + S[(size_t)q].t_lf_own;  // the batched stepping time, shared by all members
     int rc = solve_finish(bt->probs[(size_t)q], S[(size_t)q], &results[q]);

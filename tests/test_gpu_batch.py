@@ -123,3 +123,33 @@ def test_member_weights_can_be_replaced():
         assert np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max() <= 1e-12
     with pytest.raises(kf.KfError):
         bt.set_weights(1, w_new[:-1])
+
+
+def test_mixed_batch_restarts_cube_members_in_the_float64_stack():
+    """Cube members with eigenvalues of multiplicity 3 and 6 and one start
+    vector: float32 round-off seeds the extra copies, the float64
+    refinement misses the target, and the member restarts with float64
+    stepping inside the batched loop (the batch's float64 stack).  Every
+    member ends with all distinct eigenvalues of its interval, equal to the
+    closed form at the float64 bar."""
+    kf = _kf()
+    spec = [(3, 12, 15.0, 19.0), (3, 14, 12.0, 15.0), (2, 30, 10.0, 16.0), (3, 16, 20.0, 23.0)]
+    members, starts, refs = [], [], []
+    for i, (dim, n, lo, hi) in enumerate(spec):
+        S, m, h = grid_problem(dim, n)
+        lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], i), 30)
+        tau, L = oracle.time_step_rule(lam, lo)
+        tgt, vals, mult = distinct_target(grid_spectrum(dim, n), lo, hi, 1)
+        members.append((S, m, lo, hi, tau, L, tgt))
+        starts.append(start_block(S.shape[0], 1, 70 + i))
+        refs.append(vals)
+    print("case mixed batch with float64 restarts, targets", [x[6] for x in members], flush=True)
+    bt = kf.Batch(members, precision="mixed", check_every=2, check_growth=0.15)
+    got = bt.solve(starts, m_max=600, tol=1e-6)
+    esc = [bool(g.escalated) for g in got]
+    print("escalated", esc, "steps", [g.krylov_steps for g in got])
+    assert any(esc)
+    for g, vals, (S, m, lo, hi, tau, L, tgt) in zip(got, refs, members):
+        assert g.omega2.size == tgt
+        assert np.max(np.abs(g.omega2 - vals) / vals) <= 1e-10
+        assert g.residual.max() <= 1e-6
