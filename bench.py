@@ -387,6 +387,79 @@ def bench_horn(args):
     print(json.dumps(out))
 
 
+def bench_multistep(args):
+    """The time loop with several steps per launch (matrix-powers form for
+    banded operators) against the one-step kernel: seconds per filter
+    application and the scope table's algorithmic bytes per step over that
+    time (the one-step roofline; a kernel that keeps the levels on chip can
+    pass it).  Cases: the 2D square with 63 cells per side (3,969 rows, band
+    63: one workgroup holds the whole problem, the filter is one launch),
+    the square with 255 cells per side (65,025 rows, band 255: workgroups
+    with halo windows), float64 and float32 stepping; grid3d_96 (band 9,216
+    rows) and the horn's block of 16 do not fit a workgroup's LDS and are
+    reported as such."""
+    import numpy as np
+    import torch
+
+    from paper_2402_08515_amd import kf
+    from synth import power_start, start_block, workload
+    from synth.grids import grid_problem
+
+    cases = []
+    P = workload("grid2d_64")
+    cases.append(("grid2d_64", P.S, P.m, P.omega_min, P.omega_max, P.seed))
+    S, m, h = grid_problem(2, 256)
+    cases.append(("grid2d_256", S, m, 30.0, 45.0, 5))
+    out = {}
+    reps = 20
+    for name, S, m, lo, hi, seed in cases:
+        n, nnz = S.shape[0], S.nnz
+        lam = kf.estimate_lambda_max(S, m, 30, power_start(n, seed))
+        tau, L = kf.time_step_rule(lam, lo)
+        x = torch.from_numpy(start_block(n, 1, seed)).cuda()
+        for prec, vb in (("fp64", 8), ("mixed", 4)):
+            row = {}
+            for ms in (0, 2, 4, 8, -1):
+                try:
+                    prob = kf.Problem(S, m, lo, hi, tau, L, precision=prec, multistep=ms)
+                    prob.apply_filter(x)  # set-up and warm-up
+                except kf.KfError as e:
+                    row[str(ms)] = {"error": str(e)}
+                    continue
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    prob.apply_filter(x)
+                e1.record()
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                bstep = scope_bytes_per_step(n, nnz, 1, vb)
+                row[str(ms)] = {"us_per_filter": t * 1e6, "dof_steps_per_s": n * (L - 1) / t,
+                                "scope_gbs": bstep * (L - 1) / t / 1e9,
+                                "frac_of_hbm_peak": bstep * (L - 1) / t / 1e9 / HBM_PEAK_GBS}
+                del prob
+            base = row["0"]["us_per_filter"]
+            for k, v in row.items():
+                if "us_per_filter" in v:
+                    v["speedup_vs_one_step"] = base / v["us_per_filter"]
+            out[f"{name}/{prec}"] = {"n": n, "nnz": int(nnz), "L": L, "steps_per_launch": row}
+            print(f"[bench] multistep {name} {prec} L={L}: " + ", ".join(
+                f"s={k}: {v['us_per_filter']:.1f}us" if "us_per_filter" in v else f"s={k}: n/a"
+                for k, v in row.items()), file=sys.stderr, flush=True)
+    # the benchmark problems whose band does not fit
+    P = workload("grid3d_96")
+    lam = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
+    tau, L = kf.time_step_rule(lam, P.omega_min)
+    try:
+        prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, multistep=2)
+        prob.apply_filter(torch.from_numpy(start_block(P.n, 1, P.seed)).cuda())
+        out["grid3d_96"] = {"fits": True}
+    except kf.KfError as e:
+        out["grid3d_96"] = {"fits": False, "reason": str(e)}
+    print(json.dumps({"metric": METRIC, "workload": "multistep", "cases": out}))
+
+
 def bench_forms(args):
     """The project's forms against the plain method on the same problems:
     the squares of the uneven batch (seed 3; Dirichlet, so every eigenvalue's
@@ -668,6 +741,9 @@ def main():
         return
     if args.workload == "horn_4m":
         bench_horn(args)
+        return
+    if args.workload == "multistep":
+        bench_multistep(args)
         return
     if args.workload == "forms":
         bench_forms(args)

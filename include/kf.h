@@ -188,6 +188,18 @@ typedef struct kf_options {
                             checked, and the filter applications made
                             meanwhile are counted in krylov_steps);
                             0 = every check stops the loop until it ends */
+  int32_t multistep;     /* single vectors, stepper 2: the time loop as a
+                            matrix-powers kernel for banded operators (every
+                            stored entry within a band of rows around the
+                            diagonal, as a natural grid or axial ordering
+                            gives): each workgroup keeps its rows, the rows
+                            the next s steps reach and its part of the
+                            weighted sum in LDS and advances s steps per
+                            launch.  0 = one step per launch (default);
+                            s > 0 = s steps per launch; -1 = the whole filter
+                            in one launch.  KF_EINVAL from the solve or
+                            filter call when the band does not fit;
+                            blocks (b > 1) step one step per launch */
   void* stream;          /* hipStream_t */
 } kf_options;
 

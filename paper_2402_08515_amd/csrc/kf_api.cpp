@@ -42,6 +42,8 @@ struct StepBufs {
   void* Y1 = nullptr;
   void* R = nullptr;
   void* Z = nullptr;  // fourth-order stepper: z = A y
+  void* Y2 = nullptr;  // several steps per launch: the second pair of levels
+  void* Y3 = nullptr;
   int cap = 0;  // block width held
   int vb = 0;   // value bytes
 };
@@ -130,6 +132,10 @@ struct kf_problem {
   // a Rayleigh-Ritz check running on its own stream and host thread while
   // the Krylov loop goes on (kf_solve in float64)
   AsyncCheck* ac = nullptr;
+  // the weights on the device for the several-steps-per-launch kernel
+  double* d_w = nullptr;
+  int d_w_cap = 0;
+  std::vector<double> d_w_host;
 };
 
 // One stacked block-diagonal operator of a batch with its step buffers,
@@ -312,15 +318,19 @@ void dfree(void* p) {
 
 int ensure_step_buffers(kf_problem* p, StepBufs& sb, int bk, int vb) {
   const bool needz = p->opt.stepper == 4;
-  if (sb.cap >= bk && sb.vb == vb && (!needz || sb.Z)) return KF_OK;
+  const bool need23 = p->opt.multistep != 0 && bk == 1;
+  if (sb.cap >= bk && sb.vb == vb && (!needz || sb.Z) && (!need23 || sb.Y3)) return KF_OK;
   dfree(sb.Y0);
   dfree(sb.Y1);
   dfree(sb.R);
   dfree(sb.Z);
+  dfree(sb.Y2);
+  dfree(sb.Y3);
   sb = StepBufs();
   const size_t bytes = (size_t)p->n * bk * vb;
   if (hipMalloc(&sb.Y0, bytes) != hipSuccess || hipMalloc(&sb.Y1, bytes) != hipSuccess ||
-      hipMalloc(&sb.R, bytes) != hipSuccess || (needz && hipMalloc(&sb.Z, bytes) != hipSuccess))
+      hipMalloc(&sb.R, bytes) != hipSuccess || (needz && hipMalloc(&sb.Z, bytes) != hipSuccess) ||
+      (need23 && (hipMalloc(&sb.Y2, bytes) != hipSuccess || hipMalloc(&sb.Y3, bytes) != hipSuccess)))
     return fail(KF_ENOMEM, "kf: time-stepping buffers");
   sb.cap = bk;
   sb.vb = vb;
@@ -379,7 +389,42 @@ void free_step_buffers(StepBufs& sb) {
   dfree(sb.Y1);
   dfree(sb.R);
   dfree(sb.Z);
+  dfree(sb.Y2);
+  dfree(sb.Y3);
   sb = StepBufs();
+}
+
+// LDS a workgroup may use (device attribute, read once per device).
+size_t lds_per_workgroup() {
+  static std::mutex mu;
+  static int cached[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 65536;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cached[dev] = v;
+  }
+  return (size_t)cached[dev];
+}
+
+// The filter weights on the device (float64), uploaded when they change.
+int device_weights(kf_problem* p, const std::vector<double>& w, const double** out) {
+  if (p->d_w_host != w) {
+    if ((int)w.size() > p->d_w_cap) {
+      dfree(p->d_w);
+      p->d_w = nullptr;
+      p->d_w_cap = 0;
+      KF_TRY(dalloc(&p->d_w, w.size()));
+      p->d_w_cap = (int)w.size();
+    }
+    KF_HIP(hipMemcpyAsync(p->d_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, p->st));
+    KF_HIP(hipStreamSynchronize(p->st));
+    p->d_w_host = w;
+  }
+  *out = p->d_w;
+  return KF_OK;
 }
 
 // C applied to bsrc columns of src (strides srs between rows, scs between
@@ -402,6 +447,30 @@ int run_filter(kf_problem* p, const SellOp& A, StepBufs& sb, const double* src, 
   const bool direct = A.val_bytes == 8 && bk == 1 && bsrc == 1 && srs == 1;
   const void* y0 = direct ? static_cast<const void*>(src) : sb.Y1;
   if (!direct) KF_TRY(launch_load_block(A.val_bytes, p->n, bk, bsrc, src, srs, scs, sb.Y1, st));
+  if (p->opt.multistep != 0 && bk == 1 && p->opt.stepper != 4 && sb.Y3) {
+    // several steps per launch (banded operators): levels alternate between
+    // the pairs (Y0, Y1) and (Y2, Y3); the input stays where it was loaded
+    const int s = p->opt.multistep > 0 ? std::min(p->opt.multistep, L - 1) : L - 1;
+    const MultiStepPlan pl = plan_multistep(A, s, lds_per_workgroup());
+    if (!pl.ok)
+      return fail(KF_EINVAL, "kf: multistep: " + std::to_string(s) + " steps of a band of " + std::to_string(A.max_off) +
+                                 " rows do not fit in a workgroup's LDS");
+    const double* dw = nullptr;
+    KF_TRY(device_weights(p, w, &dw));
+    void* P0[2] = {sb.Y0, sb.Y1};
+    void* P1[2] = {sb.Y2, sb.Y3};
+    int l = 0, ping = 0;
+    while (l < L - 1) {
+      const int cnt = std::min(s, L - 1 - l);
+      const bool last = l + cnt == L - 1;
+      void** in = ping ? P1 : P0;
+      void** outp = ping ? P0 : P1;
+      KF_TRY(launch_leapfrog_mp(A, pl, l, cnt, l == 0, last, y0, in[0], in[1], outp[0], outp[1], sb.R, dst, drs, dw, st));
+      l += cnt;
+      ping ^= 1;
+    }
+    return KF_OK;
+  }
   void* Y[2] = {sb.Y0, sb.Y1};
   auto wt = [&](int i) { return i < 0 ? 0.0 : w[(size_t)i]; };
   for (int l = 1; l < L; ++l) {
@@ -1661,7 +1730,7 @@ void free_problem(kf_problem* p) {
   free_sell(p->A64);
   free_sell(p->S);
   void* ptrs[] = {p->d_m, p->B,  p->H,  p->G,  p->T,  p->W,    p->V,      p->SV,
-                  p->small, p->flags, p->Vx, p->Yy, p->Ysel, p->Gm, p->rr_work};
+                  p->small, p->flags, p->Vx, p->Yy, p->Ysel, p->Gm, p->rr_work, p->d_w};
   for (void* q : ptrs) dfree(q);
   free_step_buffers(p->sb);
   free_step_buffers(p->sb64);
@@ -1710,6 +1779,7 @@ void kf_default_options(kf_options* o) {
   o->block_band = 0;
   o->batch_workers = 0;
   o->overlap_checks = 1;
+  o->multistep = 0;
   o->stream = nullptr;
 }
 
@@ -1758,6 +1828,9 @@ int kf_create(const kf_csr* S, const double* m_diag, double omega_min, double om
   if (o.block_band < -1 || o.block_band > 1) return fail(KF_EINVAL, "kf_create: block_band must be -1, 0 or 1");
   if (o.stepper == 0) o.stepper = 2;
   if (o.stepper != 2 && o.stepper != 4) return fail(KF_EINVAL, "kf_create: stepper must be 2 or 4");
+  if (o.multistep < -1) return fail(KF_EINVAL, "kf_create: multistep must be -1, 0 or a step count");
+  if (o.multistep != 0 && o.stepper == 4)
+    return fail(KF_EINVAL, "kf_create: several steps per launch need the second-order scheme (stepper 2)");
   HostCsr h;
   KF_TRY(fetch_csr(S, m_diag, h));
 

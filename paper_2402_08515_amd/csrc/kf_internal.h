@@ -109,6 +109,30 @@ int launch_leapfrog4(const SellOp& A, int b, int mode, const void* cur, const vo
                      double* rout, int64_t rs, int64_t cs, int bout, double wp, double wc, double wn, int xcd_remap,
                      hipStream_t st);
 
+// Several leapfrog steps per launch for banded operators (every stored
+// entry within A.max_off rows of the diagonal), single vectors: each
+// workgroup owns `own` row slices and keeps them, the s*max_off rows on either
+// side and its part of the weighted sum in LDS.  plan_multistep picks `own`
+// for s steps per launch within lds_bytes (ok = false: the band does not
+// fit).  A launch advances y_{l0} to y_{l0+s} and adds w_{l+1} y_{l+1} for
+// each step; first: y_{-1} = y_0 = ysrc and the sum starts at w_0 y_0, else
+// the levels y_{l0-1}, y_{l0} are read from i0, i1; last: the sum goes to
+// rout (float64, row stride rs), else the levels y_{l0+s-1}, y_{l0+s} go to
+// o0, o1 (distinct from i0, i1: halo rows are read while their owners write)
+// and the sum to acc; vectors are n long in the stepping precision, w holds
+// the L weights (float64, device).
+struct MultiStepPlan {
+  bool ok = false;
+  bool reg = false;  // one workgroup, the operator's entries and the sums in registers
+  int own = 0;  // owned row slices per workgroup
+  int hb = 0;   // the band in slices
+  int s = 0;
+};
+MultiStepPlan plan_multistep(const SellOp& A, int s, size_t lds_bytes);
+int launch_leapfrog_mp(const SellOp& A, const MultiStepPlan& pl, int l0, int s, bool first, bool last, const void* ysrc,
+                       const void* i0, const void* i1, void* o0, void* o1, void* acc, double* rout, int64_t rs,
+                       const double* w, hipStream_t st);
+
 // The accumulation schedule of one filter application (L - 1 steps): for
 // step l, the mode and the weights (wp, wc, wn) of prev, cur and nxt.  Every
 // y_j enters once: y_0 and y_1 at step 1, then three at a time at steps

@@ -572,6 +572,208 @@ int launch_lf4_t(const SellOp& A, int b, int mode, const void* cur, const void* 
   }
 }
 
+// ------------------------------------------- several steps per launch (bands)
+// Communication-avoiding form of the time loop for operators whose stored
+// entries lie within max_off rows of the diagonal (banded orderings): a
+// workgroup owns a range of row slices and advances y_l -> y_{l+s} for it in
+// one launch, keeping y_{l-1}, y_l of its rows and of the s*max_off rows on
+// either side in LDS.  Step j updates the rows within (s-1-j)*max_off of the
+// owned range (those the later steps still read), each from the previous
+// level's values in LDS; the weighted sum of the owned rows stays in LDS for
+// the s steps.  HBM traffic per step and row falls from five vector streams
+// (plus the operator) to 6/s of a vector (plus the operator, whose band is
+// read from the caches at every step); the cost is the halo rows computed
+// more than once (s*max_off/own of the work) and the workgroup's LDS.  With
+// the whole problem in one workgroup the filter is one launch.
+//   first: y_{-1} = y_0 = x (x in ysrc), acc = w_0 x;  else i0, i1 hold
+//          y_{l0-1}, y_{l0} and accg the weighted sum so far
+//   last:  the weighted sum goes to rout (float64, row stride rs) instead
+//          of accg; otherwise y_{l0+s-1}, y_{l0+s} go to o0, o1
+// The levels are read from one pair of buffers and written to another (a
+// workgroup's halo rows are another workgroup's owned rows, written in the
+// same launch); the sum is read and written by its owner only.
+// Every step adds w_{l+1} y_{l+1} (one term per step, in step order).
+template <typename T, typename IT>
+__global__ __launch_bounds__(1024) void k_leapfrog_mp(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                      const T* __restrict__ val, const IT* __restrict__ idx,
+                                                      const T* __restrict__ ysrc, const T* __restrict__ i0,
+                                                      const T* __restrict__ i1, T* __restrict__ o0g,
+                                                      T* __restrict__ o1g, T* accg, double* __restrict__ rout,
+                                                      int64_t rs, const double* __restrict__ w, int l0, int s, int own,
+                                                      int hb, int first, int last) {
+  constexpr bool relative = sizeof(IT) == 2;
+  extern __shared__ __align__(16) unsigned char mp_raw[];
+  const int o0 = blockIdx.x * own;                  // owned slices [o0, o1)
+  const int o1 = min(nslices, o0 + own);
+  const int w0 = max(0, o0 - s * hb);               // window slices [w0, w1)
+  const int w1 = min(nslices, o1 + s * hb);
+  const int wrows = (w1 - w0) * 64, orows = (o1 - o0) * 64;
+  const int r0 = w0 * 64;                           // first row of the window
+  T* Yp = reinterpret_cast<T*>(mp_raw);
+  T* Yc = Yp + wrows;
+  T* Ra = Yc + wrows;                               // weighted sum of the owned rows
+  const int own0 = o0 * 64 - r0;                    // owned rows in window coordinates
+  for (int i = threadIdx.x; i < wrows; i += blockDim.x) {
+    const int g = r0 + i;
+    T a = (T)0, b = (T)0;
+    if (g < n) {
+      if (first) {
+        a = ysrc[g];
+        b = a;
+      } else {
+        a = i0[g];
+        b = i1[g];
+      }
+    }
+    Yp[i] = a;
+    Yc[i] = b;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < orows; i += blockDim.x) {
+    const int g = o0 * 64 + i;
+    Ra[i] = g < n ? (first ? (T)w[0] * Yc[own0 + i] : accg[g]) : (T)0;
+  }
+  for (int j = 0; j < s; ++j) {
+    const int l = l0 + j;  // this step forms y_{l+1}
+    const T wn = (T)w[l + 1];
+    const int a0 = max(w0, o0 - (s - 1 - j) * hb), a1 = min(w1, o1 + (s - 1 - j) * hb);
+    const int nrow = (a1 - a0) * 64;
+    for (int t = threadIdx.x; t < nrow; t += blockDim.x) {
+      const int g = a0 * 64 + t;
+      if (g >= n) continue;
+      const int slice = g >> 6, lane = g & 63;
+      const int64_t base = sptr[slice];
+      const int width = (int)((sptr[slice + 1] - base) >> 6);
+      const T* __restrict__ vp = val + base + lane;
+      const IT* __restrict__ ip = idx + base + lane;
+      T sum = (T)0;
+      for (int q = 0; q < width; ++q) {
+        const T a = vp[(int64_t)q * 64];
+        const IT ci = ip[(int64_t)q * 64];
+        const int c = relative ? g + (int)ci : (int)ci;
+        sum = fma(a, Yc[c - r0], sum);
+      }
+      const int i = g - r0;
+      const T nx = (T)2 * Yc[i] - Yp[i] - sum;
+      Yp[i] = nx;  // y_{l+1} replaces y_{l-1}; the other rows read only Yc
+      const int oi = i - own0;
+      if (oi >= 0 && oi < orows) Ra[oi] = fma(wn, nx, Ra[oi]);
+    }
+    __syncthreads();
+    T* tmp = Yp;
+    Yp = Yc;
+    Yc = tmp;
+  }
+  for (int i = threadIdx.x; i < orows; i += blockDim.x) {
+    const int g = o0 * 64 + i;
+    if (g >= n) continue;
+    if (!last) {
+      o0g[g] = Yp[own0 + i];
+      o1g[g] = Yc[own0 + i];
+      accg[g] = Ra[i];
+    } else {
+      rout[(int64_t)g * rs] = (double)Ra[i];
+    }
+  }
+}
+
+// The same for a whole small problem in one workgroup whose rows and stored
+// entries fit in registers (at most MAXR rows per thread, slices at most
+// MAXW entries wide): thread t keeps rows t, t + 1024, ... with their entries
+// and weighted sums in registers for all s steps, the two levels in LDS, so a
+// step reads nothing but LDS.
+template <typename T, typename IT, int MAXR, int MAXW>
+__global__ __launch_bounds__(1024) void k_leapfrog_mp_reg(int32_t n, int32_t nslices, const int64_t* __restrict__ sptr,
+                                                          const T* __restrict__ val, const IT* __restrict__ idx,
+                                                          const T* __restrict__ ysrc, const T* __restrict__ i0,
+                                                          const T* __restrict__ i1, T* __restrict__ o0g,
+                                                          T* __restrict__ o1g, T* accg, double* __restrict__ rout,
+                                                          int64_t rs, const double* __restrict__ w, int l0, int s,
+                                                          int first, int last) {
+  constexpr bool relative = sizeof(IT) == 2;
+  extern __shared__ __align__(16) unsigned char mpr_raw[];
+  const int rows = nslices * 64;
+  T* Yp = reinterpret_cast<T*>(mpr_raw);
+  T* Yc = Yp + rows;
+  T a[MAXR][MAXW];
+  int c[MAXR][MAXW];
+  T racc[MAXR];
+  int wdt[MAXR];
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k) {
+    const int g = threadIdx.x + 1024 * k;
+    wdt[k] = 0;
+    racc[k] = (T)0;
+    if (g < n) {
+      const int slice = g >> 6, lane = g & 63;
+      const int64_t base = sptr[slice];
+      wdt[k] = min(MAXW, (int)((sptr[slice + 1] - base) >> 6));
+#pragma unroll
+      for (int q = 0; q < MAXW; ++q) {
+        if (q < wdt[k]) {
+          a[k][q] = val[base + (int64_t)q * 64 + lane];
+          const IT ci = idx[base + (int64_t)q * 64 + lane];
+          c[k][q] = relative ? g + (int)ci : (int)ci;
+        } else {
+          a[k][q] = (T)0;
+          c[k][q] = g;
+        }
+      }
+    }
+  }
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+    T x0 = (T)0, x1 = (T)0;
+    if (i < n) {
+      if (first) {
+        x0 = ysrc[i];
+        x1 = x0;
+      } else {
+        x0 = i0[i];
+        x1 = i1[i];
+      }
+    }
+    Yp[i] = x0;
+    Yc[i] = x1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k) {
+    const int g = threadIdx.x + 1024 * k;
+    if (g < n) racc[k] = first ? (T)w[0] * Yc[g] : accg[g];
+  }
+  for (int j = 0; j < s; ++j) {
+    const T wn = (T)w[l0 + j + 1];
+#pragma unroll
+    for (int k = 0; k < MAXR; ++k) {
+      const int g = threadIdx.x + 1024 * k;
+      if (g < n) {
+        T sum = (T)0;
+#pragma unroll
+        for (int q = 0; q < MAXW; ++q) sum = fma(a[k][q], Yc[c[k][q]], sum);
+        const T nx = (T)2 * Yc[g] - Yp[g] - sum;
+        Yp[g] = nx;
+        racc[k] = fma(wn, nx, racc[k]);
+      }
+    }
+    __syncthreads();
+    T* tmp = Yp;
+    Yp = Yc;
+    Yc = tmp;
+  }
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k) {
+    const int g = threadIdx.x + 1024 * k;
+    if (g >= n) continue;
+    if (!last) {
+      o0g[g] = Yp[g];
+      o1g[g] = Yc[g];
+      accg[g] = racc[k];
+    } else {
+      rout[(int64_t)g * rs] = (double)racc[k];
+    }
+  }
+}
+
 }  // namespace
 
 
@@ -685,6 +887,101 @@ int launch_leapfrog(const SellOp& A, int b, int mode, const void* cur, const voi
   if (A.idx_bytes == 2)
     return launch_lf_t<float, int16_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
   return launch_lf_t<float, int32_t>(A, b, mode, cur, prev, out, acc, rout, rs, cs, bout, wp, wc, wn, xcd_remap, st);
+}
+
+MultiStepPlan plan_multistep(const SellOp& A, int s, size_t lds_bytes) {
+  MultiStepPlan pl;
+  const int vb = A.val_bytes;
+  const int hb = (A.max_off + 63) / 64;  // the band in slices
+  pl.hb = hb;
+  // the whole problem in one workgroup: with its stored entries in registers
+  // when every thread holds at most 4 rows of at most 8 entries, else reading
+  // them from the caches at every step (no halo either way)
+  if ((size_t)A.nslices * 64 <= 4 * 1024 && A.max_width <= 8 && (size_t)A.nslices * 64 * 2 * vb <= lds_bytes) {
+    pl.own = A.nslices;
+    pl.s = s;
+    pl.ok = true;
+    pl.reg = true;
+    return pl;
+  }
+  if ((size_t)A.nslices * 64 * 3 * vb <= lds_bytes) {
+    pl.own = A.nslices;
+    pl.s = s;
+    pl.ok = true;
+    return pl;
+  }
+  // largest owned range whose window (own + 2 s hb slices, two levels) and
+  // weighted sum fit
+  const size_t per_slice = (size_t)64 * vb;
+  const size_t halo = (size_t)2 * s * hb;
+  const size_t cap = lds_bytes / per_slice;  // slices of one level
+  if (2 * halo + 3 > cap) return pl;         // not even one owned slice
+  pl.own = (int)std::min<size_t>((cap - 2 * halo) / 3, (size_t)A.nslices);
+  pl.s = s;
+  pl.ok = pl.own >= 1;
+  return pl;
+}
+
+int launch_leapfrog_mp(const SellOp& A, const MultiStepPlan& pl, int l0, int s, bool first, bool last, const void* ysrc,
+                       const void* i0, const void* i1, void* o0, void* o1, void* acc, double* rout, int64_t rs,
+                       const double* w, hipStream_t st) {
+  if (!pl.ok || s < 1) {
+    set_error("multi-step leapfrog: the band does not fit in LDS");
+    return KF_EINVAL;
+  }
+  if (pl.reg) {
+    // the whole problem in one workgroup, operator and sums in registers
+    const size_t lds = (size_t)2 * A.nslices * 64 * A.val_bytes;
+#define KF_MPR(T, IT)                                                                                              \
+  do {                                                                                                             \
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leapfrog_mp_reg<T, IT, 4, 8>),                       \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                                \
+    hipLaunchKernelGGL((k_leapfrog_mp_reg<T, IT, 4, 8>), dim3(1), dim3(1024), lds, st, A.n, A.nslices, A.slice_ptr, \
+                       static_cast<const T*>(A.val), static_cast<const IT*>(A.idx), static_cast<const T*>(ysrc),      \
+                       static_cast<const T*>(i0), static_cast<const T*>(i1), static_cast<T*>(o0),                      \
+                       static_cast<T*>(o1), static_cast<T*>(acc), rout, rs, w, l0, s, first ? 1 : 0, last ? 1 : 0);  \
+  } while (0)
+    if (A.val_bytes == 8) {
+      if (A.idx_bytes == 2)
+        KF_MPR(double, int16_t);
+      else
+        KF_MPR(double, int32_t);
+    } else {
+      if (A.idx_bytes == 2)
+        KF_MPR(float, int16_t);
+      else
+        KF_MPR(float, int32_t);
+    }
+#undef KF_MPR
+    KF_HIP(hipGetLastError());
+    return KF_OK;
+  }
+  const int grid = ceil_div64(A.nslices, pl.own);
+  const int wsl = std::min(A.nslices, pl.own + 2 * s * pl.hb);
+  const size_t lds = ((size_t)2 * wsl + pl.own) * 64 * A.val_bytes;
+#define KF_MP(T, IT)                                                                                               \
+  do {                                                                                                             \
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leapfrog_mp<T, IT>),                                   \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                                  \
+  hipLaunchKernelGGL((k_leapfrog_mp<T, IT>), dim3(grid), dim3(1024), lds, st, A.n, A.nslices, A.slice_ptr,         \
+                     static_cast<const T*>(A.val), static_cast<const IT*>(A.idx), static_cast<const T*>(ysrc),        \
+                     static_cast<const T*>(i0), static_cast<const T*>(i1), static_cast<T*>(o0), static_cast<T*>(o1), \
+                     static_cast<T*>(acc), rout, rs, w, l0, s, pl.own, pl.hb, first ? 1 : 0, last ? 1 : 0);    \
+  } while (0)
+  if (A.val_bytes == 8) {
+    if (A.idx_bytes == 2)
+      KF_MP(double, int16_t);
+    else
+      KF_MP(double, int32_t);
+  } else {
+    if (A.idx_bytes == 2)
+      KF_MP(float, int16_t);
+    else
+      KF_MP(float, int32_t);
+  }
+#undef KF_MP
+  KF_HIP(hipGetLastError());
+  return KF_OK;
 }
 
 int launch_leapfrog4(const SellOp& A, int b, int mode, const void* cur, const void* prev, void* out, void* acc, void* z,

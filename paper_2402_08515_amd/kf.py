@@ -66,6 +66,7 @@ class OptionsT(C.Structure):
         ("block_band", C.c_int32),
         ("stepper", C.c_int32),
         ("overlap_checks", C.c_int32),
+        ("multistep", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -386,7 +387,7 @@ def _take_result(res, n: int) -> SolveResult:
 def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=False, target=0, max_iters=0,
              drop_tol=1e-10, refine=None, want_vectors=False, index_bytes=0, xcd_remap=True, nt_loads=False,
              autotune=False, reorth_tol=None, lanes_per_row=0, batch_workers=0, proj_every=None, gather_unroll=0,
-             block_band=0, escalate=None, stepper=2, overlap_checks=None):
+             block_band=0, escalate=None, stepper=2, overlap_checks=None, multistep=0):
     opt = OptionsT()
     lib().kf_default_options(C.byref(opt))
     opt.precision = _PREC[precision]
@@ -415,6 +416,7 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
     opt.stepper = int(stepper)
     if overlap_checks is not None:
         opt.overlap_checks = int(overlap_checks)
+    opt.multistep = int(multistep)
     opt.batch_workers = int(batch_workers)
     opt.stream = _stream_handle()
     return opt

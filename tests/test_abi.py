@@ -108,7 +108,7 @@ def test_default_options_fill_the_bindings_structure():
     want = {"precision": 0, "check_every": 1, "check_growth": 0.3, "full_reorth": 0, "target": 0, "max_iters": 0,
             "drop_tol": 1e-10, "reorth_tol": 1e-9, "proj_every": 12, "refine": 8, "escalate": 1, "want_vectors": 0,
             "index_bytes": 0, "xcd_remap": 1, "nt_loads": 0, "autotune": 0, "batch_workers": 0, "lanes_per_row": 0,
-            "gather_unroll": 0, "block_band": 0, "stepper": 2, "overlap_checks": 1, "stream": None}
+            "gather_unroll": 0, "block_band": 0, "stepper": 2, "overlap_checks": 1, "multistep": 0, "stream": None}
     assert got == want
 
 
