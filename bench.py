@@ -179,10 +179,11 @@ def bench_batch(args):
         return int(found), max(errs) if errs else None
 
     opts = dict(check_every=2, check_growth=0.15)
+    bopts = dict(opts, batch_workers=args.batch_workers)
     runs = {}
     # mixed, batched (the slices' problems and the stacked operator are built,
     # and the batched step variant timed, before the timed region)
-    bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **opts)
+    bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **bopts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = bt.solve(starts, m_max=args.m_max, tol=args.tol)
@@ -215,6 +216,19 @@ def bench_batch(args):
           file=sys.stderr, flush=True)
     bt.close()
     del bt
+    # the plain method batched: float64 stepping in one stacked operator
+    bt = kf.Batch([m for m in members], precision="fp64", autotune=True, **bopts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_b64 = bt.solve(starts, m_max=args.m_max, tol=args.tol)
+    torch.cuda.synchronize()
+    wb64 = time.perf_counter() - t0
+    fb64, eb64 = count(res_b64)
+    runs["fp64_batched"] = {"seconds": wb64, "pairs": fb64, "max_rel_err": eb64,
+                            "batched_leapfrog_s": res_b64[0].t_leapfrog, "incomplete": short(res_b64)}
+    print(f"[bench] fp64 batched: {wb64:.2f}s, {fb64}/{total} pairs", file=sys.stderr, flush=True)
+    bt.close()
+    del bt
     # learned weights where the gate takes them, mixed, batched
     if not args.no_learned:
         train = filter_samples(args.mlp_samples, stream=0)
@@ -222,7 +236,7 @@ def bench_batch(args):
         rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
         order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
         net.train(train, order, args.mlp_epochs, 256, 1e-3)
-        bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **opts)
+        bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **bopts)
         used = 0
         for q, ((S, m, lo, hi, tau, L, tgt), (_, _, _, _, _, lam)) in enumerate(zip(members, meta)):
             w, u, jl, jf = net.weights(lo, hi, tau, lam, L)
@@ -711,6 +725,8 @@ def main():
     ap.add_argument("--slice-target", type=int, default=150,
                     help="batch: intervals with more pairs are cut into slices of at most this many")
     ap.add_argument("--no-learned", action="store_true", help="batch: skip the learned-weights run")
+    ap.add_argument("--batch-workers", type=int, default=0,
+                    help="batch: host threads driving the members' projection work (0: min(8, members))")
     ap.add_argument("--mlp-samples", type=int, default=50000)
     ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--learned-n", type=int, default=128)

@@ -171,6 +171,11 @@ struct kf_batch {
   // stepping own the first prefix[ell] row slices
   std::vector<int> prefix;
   int autotune = 0;
+  // members passed the same operator arrays (slices of one problem's
+  // spectrum) share a group: they share the operator's eigenvalue
+  // multiplicities, so when float32 stepping fails for one of them the
+  // others restart with float64 stepping at once
+  std::vector<int> group;
 };
 
 namespace {
@@ -2374,11 +2379,13 @@ struct SolveState {
   double t_lf_own = 0.0;  // a batch member's own stepping time after an escalation
   // checks beside the Krylov loop (kf_options.overlap_checks)
   bool async_ok = false;
+  bool async_all = false;  // batch members: every check beside the loop
   int async_checks = 0;
   double t_rr_async = 0.0;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
+  KF_HIP(hipEventSynchronize(b));
   float ms = 0.f;
   KF_HIP(hipEventElapsedTime(&ms, a, b));
   acc += ms * 1e-3;
@@ -2548,6 +2555,11 @@ int load_start(kf_problem* p, SolveState& s, int* kept_out) {
 // of this basis removes them.  The loop starts again from the start block
 // with float64 stepping (no further refinement).
 int escalate_restart(kf_problem* p, SolveState& s) {
+  if (async_running(p)) {
+    // a check of the float32 basis still running: its result is not needed
+    KF_TRY(async_wait(p));
+    p->ac->state.store(0);
+  }
   s.escalated = true;
   s.Aop = &p->A64;
   s.sbop = &p->sb64;
@@ -2629,14 +2641,56 @@ int solve_check_now(kf_problem* p, SolveState& s) {
 // end the check runs in line, so that no filter application is spent past
 // the basis that meets the target.
 bool check_overlaps(const kf_problem* p, const SolveState& s) {
-  if (!s.async_ok || async_running(p)) return false;
+  if (!(s.async_ok || s.async_all) || async_running(p)) return false;
+  // batch members: every check (the batched filter does not wait for it)
+  if (s.async_all) return true;
   const int missing = s.checked_at < 0 ? s.target : s.target - distinct_count(s.chk.acc_theta, s.b);
   return missing > std::max(3, s.target / 8);
 }
 
+int escalate_restart(kf_problem* p, SolveState& s);
+
+// After a check at the current basis size: the target reached at the loop's
+// tolerance ends the solve (float64 stepping) or starts the float64
+// refinement (mixed), which ends it, restarts with float64 stepping
+// (escalate), or lets the loop go on.
+int decide_after_check(kf_problem* p, SolveState& s) {
+  if (!(s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target)) return KF_OK;
+  if (!s.refine) {
+    s.done = true;
+  } else if (s.cur >= s.next_refine) {
+    // the loop reached the target at its own tolerance: refine now, and
+    // keep iterating (up to kMaxRefines refinements) if some pairs
+    // still miss the requested tolerance
+    KF_TRY(solve_refine_now(p, s));
+    s.next_refine = (int)std::ceil(s.cur * 1.1);
+    const bool met = distinct_count(s.fin.acc_theta, s.b) >= s.target;
+    if (met) {
+      s.done = true;
+    } else if (p->opt.escalate) {
+      // missed: float32 round-off left pollution no refinement of this
+      // basis removes (see escalate_restart); a batch without a float64
+      // stack defers it
+      if (s.may_escalate) {
+        KF_TRY(escalate_restart(p, s));
+      } else {
+        s.wants_escalation = true;
+        s.done = true;
+      }
+    } else if (s.refines >= kMaxRefines) {
+      s.done = true;
+    }
+  }
+  return KF_OK;
+}
+
 // Takes the result of a check that ran beside the loop.  When it meets the
-// target the basis is cut back to the columns it checked: the columns added
-// meanwhile are dropped and the solve ends there.
+// target the basis is cut back to the columns it checked (the columns added
+// meanwhile are dropped) and the decision is taken there: the solve ends,
+// or in mixed mode the refinement runs on that basis and either ends the
+// solve or restarts it with float64 stepping (overlapped checks in mixed
+// mode are used only with escalate, so the loop never continues from a cut
+// basis).
 int solve_take_overlapped(kf_problem* p, SolveState& s) {
   CheckOut c;
   int k = 0;
@@ -2646,9 +2700,14 @@ int solve_take_overlapped(kf_problem* p, SolveState& s) {
   s.chk = std::move(c);
   s.next_check = next_check_at(p, s, k);
   if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
-    s.done = true;
     s.cur = k;
     s.checked_at = k;
+    s.next_refine = 0;
+    KF_TRY(decide_after_check(p, s));
+    if (!s.done && !s.escalated && s.refine) {
+      // (refinement missed without escalation: end with what was refined)
+      s.done = true;
+    }
   }
   return KF_OK;
 }
@@ -2661,9 +2720,11 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   ++s.iters;
   s.lf_steps += (int64_t)s.qn * (p->L - 1);
   if (async_ready(p)) {
+    const bool was_escalated = s.escalated;
     KF_TRY(solve_take_overlapped(p, s));
-    if (s.done) {
-      // the filtered block just formed is not needed
+    if (s.done || s.escalated != was_escalated) {
+      // the filtered block just formed is not needed (the solve ended, or
+      // restarted from the start block with float64 stepping)
       s.ahead_ready = false;
       if (s.timed_filter) {
         KF_HIP(hipEventSynchronize(p->ev[1]));
@@ -2750,33 +2811,9 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   } else if (s.iters % p->opt.check_every == 0 && s.cur >= s.next_check) {
     KF_TRY(solve_check_now(p, s));
     s.next_check = next_check_at(p, s, s.cur);
-    if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
-      if (!s.refine) {
-        s.done = true;
-      } else if (s.cur >= s.next_refine) {
-        // the loop reached the target at its own tolerance: refine now, and
-        // keep iterating (up to kMaxRefines refinements) if some pairs
-        // still miss the requested tolerance
-        KF_TRY(solve_refine_now(p, s));
-        s.next_refine = (int)std::ceil(s.cur * 1.1);
-        const bool met = distinct_count(s.fin.acc_theta, s.b) >= s.target;
-        if (met) {
-          s.done = true;
-        } else if (p->opt.escalate) {
-          // missed: float32 round-off left pollution no refinement of this
-          // basis removes (see escalate_restart); the batch defers it
-          if (s.may_escalate) {
-            KF_TRY(escalate_restart(p, s));
-          } else {
-            s.wants_escalation = true;
-            s.done = true;
-          }
-        } else if (s.refines >= kMaxRefines) {
-          s.done = true;
-        }
-      }
-    }
+    KF_TRY(decide_after_check(p, s));
   }
+  if (!s.done && async_running(p) && s.cur + s.bk > s.m_max) KF_TRY(solve_take_overlapped(p, s));
   // mixed precision: the float32 loop ran out of basis before it reached
   // the target at its own tolerance; refine what it has, and when pairs are
   // still missing restart with float64 stepping (the same budget)
@@ -3230,6 +3267,18 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
       }
     }
     if (rc) break;
+    bt->group.assign((size_t)P, 0);
+    for (int q = 0; q < P; ++q) {
+      bt->group[(size_t)q] = q;
+      for (int r = 0; r < q; ++r) {
+        const kf_csr &a = descs[q].S, &c = descs[r].S;
+        if (a.n == c.n && a.nnz == c.nnz && a.rowptr == c.rowptr && a.col == c.col && a.val == c.val &&
+            descs[q].m_diag == descs[r].m_diag) {
+          bt->group[(size_t)q] = bt->group[(size_t)r];
+          break;
+        }
+      }
+    }
     // members stacked by decreasing L (stable): the members still stepping
     // at step ell own a prefix of the stacked rows
     std::vector<int> ord((size_t)P);
@@ -3378,12 +3427,18 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
       return rc;
     }
     S[(size_t)q].may_escalate = in_loop;
+    // checks beside the batched loop (the next batched filter does not wait
+    // for them); in mixed mode only where a missed refinement restarts
+    kf_problem* pq = bt->probs[(size_t)q];
+    S[(size_t)q].async_all = pq->opt.overlap_checks != 0 && S[(size_t)q].target > 0 &&
+                             (!S[(size_t)q].refine || (pq->opt.escalate && in_loop));
   }
   const int bk = pow2ceil(b);
   double t_lf = 0.0;
   // KF_PROGRESS set: one line on stderr every 100 batched filter launches
   const bool progress = std::getenv("KF_PROGRESS") != nullptr;
   int round = 0;
+  double host_filter = 0.0, host_members = 0.0;  // wall seconds: launching and waiting for the filter, member work
   while (true) {
     bool any[2] = {false, false};
     for (int q = 0; q < bt->P; ++q) {
@@ -3410,8 +3465,10 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
         na += (bt->stk[0].h_tb.active[q] || (bt->nstk > 1 && bt->stk[1].h_tb.active[q])) ? 1 : 0;
         ne += S[(size_t)q].escalated ? 1 : 0;
       }
-      std::fprintf(stderr, "[kf] batch: %d filter launches, %d of %d members stepping, %d restarted in float64\n",
-                   round, na, bt->P, ne);
+      std::fprintf(stderr,
+                   "[kf] batch: %d filter launches, %d of %d members stepping, %d restarted in float64; "
+                   "%.2f s batched filter, %.2f s member Gram-Schmidt/Rayleigh-Ritz\n",
+                   round, na, bt->P, ne, host_filter, host_members);
       std::fflush(stderr);
     }
     const bool par = bt->workers > 1;
@@ -3424,10 +3481,16 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
         KF_HIP(hipStreamWaitEvent(bt->st, p->sync_ev, 0));
       }
     }
+    const double th0 = now_s();
     KF_HIP(hipEventRecord(bt->ev[0], bt->st));
     for (int ks = 0; ks < bt->nstk; ++ks)
       if (any[ks]) KF_TRY(run_batch_filter(bt, bt->stk[ks], bk));
     KF_HIP(hipEventRecord(bt->ev[1], bt->st));
+    if (progress) {
+      KF_HIP(hipEventSynchronize(bt->ev[1]));
+      host_filter += now_s() - th0;
+    }
+    const double th1 = now_s();
     std::vector<int> act;
     for (int q = 0; q < bt->P; ++q)
       if (bt->stk[0].h_tb.active[q] || (bt->nstk > 1 && bt->stk[1].h_tb.active[q])) act.push_back(q);
@@ -3462,6 +3525,26 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
           return rcs[i];
         }
     }
+    host_members += now_s() - th1;
+    if (in_loop) {
+      // a member that restarted with float64 stepping: its siblings on the
+      // same operator follow now (their float32 refinement would miss too)
+      for (int q : act) {
+        if (!S[(size_t)q].escalated) continue;
+        for (int r = 0; r < bt->P; ++r) {
+          SolveState& sr = S[(size_t)r];
+          if (r == q || bt->group[(size_t)r] != bt->group[(size_t)q] || sr.escalated || sr.done || !sr.refine)
+            continue;
+          int rc = escalate_restart(bt->probs[(size_t)r], sr);
+          if (rc) {
+            set_error("kf_solve_batch: problem " + std::to_string(r) + " (float64 restart): " + kf_last_error());
+            return rc;
+          }
+        }
+      }
+    }
+    // (members whose solve ended at this step did not wait for the filter)
+    KF_HIP(hipEventSynchronize(bt->ev[1]));
     KF_TRY(elapsed_acc(bt->ev[0], bt->ev[1], t_lf));
   }
   // (batches without a float64 stack) members whose float64 refinement

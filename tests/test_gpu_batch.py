@@ -70,16 +70,21 @@ def test_batched_solve_equals_member_solves(workers):
         starts.append(start_block(S.shape[0], b, 50 + i))
         targets.append(tgt)
     print(f"case batch solve targets={targets}", flush=True)
-    bt = kf.Batch(members, check_every=1, batch_workers=workers)
+    # checks in line in the batch and in the single solves: the same steps
+    bt = kf.Batch(members, check_every=1, batch_workers=workers, overlap_checks=False)
     got = bt.solve(starts, m_max=200, tol=1e-9)
-    for (S, m, lo, hi, tau, L, tgt), V0, g, (dim, n, _, _) in zip(members, starts, got, spec):
-        # (a batch checks in line: so does the single solve compared with it)
+    # the default: every member's checks beside the batched loop
+    bo = kf.Batch(members, check_every=1, batch_workers=workers)
+    gov = bo.solve(starts, m_max=200, tol=1e-9)
+    for (S, m, lo, hi, tau, L, tgt), V0, g, go, (dim, n, _, _) in zip(members, starts, got, gov, spec):
         single = kf.Problem(S, m, lo, hi, tau, L, target=tgt, overlap_checks=False).solve(V0, m_max=200, tol=1e-9)
-        assert g.omega2.size == single.omega2.size == tgt
+        assert g.omega2.size == single.omega2.size == go.omega2.size == tgt
         np.testing.assert_allclose(g.omega2, single.omega2, rtol=1e-12)
         tg, vals, mult = distinct_target(grid_spectrum(dim, n), lo, hi, b)
         np.testing.assert_allclose(g.omega2, np.repeat(vals, np.minimum(mult, b)), rtol=1e-10)
+        np.testing.assert_allclose(go.omega2, np.repeat(vals, np.minimum(mult, b)), rtol=1e-10)
         assert g.krylov_steps == single.krylov_steps
+        assert g.overlapped_checks == 0 and go.overlapped_checks >= 1
 
 
 def test_batched_solve_mixed_on_jittered_members():
@@ -153,3 +158,36 @@ def test_mixed_batch_restarts_cube_members_in_the_float64_stack():
         assert g.omega2.size == tgt
         assert np.max(np.abs(g.omega2 - vals) / vals) <= 1e-10
         assert g.residual.max() <= 1e-6
+
+
+def test_slices_of_one_operator_restart_together():
+    """Three slices of one cube's interval (the same operator arrays) and a
+    square: once float32 stepping fails for one slice, the others restart
+    with float64 stepping too; every slice ends complete at the float64
+    bar."""
+    kf = _kf()
+    S, m, h = grid_problem(3, 16)
+    lam = oracle.power_lambda_max(S, m, power_start(S.shape[0], 0), 30)
+    members, starts, refs = [], [], []
+    for i, (lo, hi) in enumerate([(20.0, 21.0), (21.0, 22.0), (22.0, 23.0)]):
+        tau, L = oracle.time_step_rule(lam, lo)
+        tgt, vals, mult = distinct_target(grid_spectrum(3, 16), lo, hi, 1)
+        members.append((S, m, lo, hi, tau, L, tgt))
+        starts.append(start_block(S.shape[0], 1, 80 + i))
+        refs.append(vals)
+    S2, m2, h2 = grid_problem(2, 30)
+    lam2 = oracle.power_lambda_max(S2, m2, power_start(S2.shape[0], 1), 30)
+    tau2, L2 = oracle.time_step_rule(lam2, 10.0)
+    tgt2, vals2, mult2 = distinct_target(grid_spectrum(2, 30), 10.0, 16.0, 1)
+    members.append((S2, m2, 10.0, 16.0, tau2, L2, tgt2))
+    starts.append(start_block(S2.shape[0], 1, 83))
+    refs.append(vals2)
+    print("case mixed batch, three slices of one cube and a square, targets", [x[6] for x in members], flush=True)
+    got = kf.Batch(members, precision="mixed", check_every=2, check_growth=0.15).solve(starts, m_max=600, tol=1e-6)
+    esc = [bool(g.escalated) for g in got]
+    print("escalated", esc, "steps", [g.krylov_steps for g in got])
+    # the slices of the cube restart together
+    assert esc[0] and esc[1] and esc[2]
+    for g, vals, mem in zip(got, refs, members):
+        assert g.omega2.size == mem[6]
+        assert np.max(np.abs(g.omega2 - vals) / vals) <= 1e-10
