@@ -156,6 +156,7 @@ def bench_batch(args):
     os.environ.setdefault("KF_PROGRESS", "1")  # the library reports the batched loop's progress on stderr
     slices = batch64_slices(args.slice_target, args.batch_count)
     lam_of, members, starts, meta = {}, [], [], []
+    multiple = []  # the slice holds an eigenvalue of multiplicity above the block width
     for (i, P, lo, hi, tgt) in slices:
         if i not in lam_of:
             lam_of[i] = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
@@ -164,6 +165,8 @@ def bench_batch(args):
         members.append((P.S, P.m, lo, hi, tau, L, tgt))
         starts.append(start_block(P.n, P.block, P.seed))
         meta.append((i, P, lo, hi, tgt, lam_of[i]))
+        t_, vals_, mult_ = distinct_target(grid_spectrum(P.meta["dim"], P.meta["n"]), lo, hi, P.block)
+        multiple.append(bool(mult_.size and mult_.max() > P.block))
     total = sum(m[6] for m in members)
     print(f"[bench] batch: {args.batch_count} members in {len(members)} slices, L in "
           f"[{min(m[5] for m in members)}, {max(m[5] for m in members)}], {total} pairs", file=sys.stderr, flush=True)
@@ -216,6 +219,26 @@ def bench_batch(args):
           file=sys.stderr, flush=True)
     bt.close()
     del bt
+    # mixed, batched, with the members whose slice holds eigenvalues of
+    # multiplicity above the block width stepping in float64 from the start
+    # (the remedy for what float32 stepping cannot resolve; the closed-form
+    # spectrum tells which slices they are)
+    mem_fp64 = [m + (f,) for m, f in zip(members, multiple)]
+    bt = kf.Batch(mem_fp64, precision="mixed", autotune=True, **bopts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_mf = bt.solve(starts, m_max=args.m_max, tol=args.tol)
+    torch.cuda.synchronize()
+    wmf = time.perf_counter() - t0
+    fmf, emf = count(res_mf)
+    runs["mixed_batched_fp64_members"] = {"seconds": wmf, "pairs": fmf, "max_rel_err": emf,
+                                          "fp64_members": int(sum(multiple)),
+                                          "escalated_slices": int(sum(r.escalated for r in res_mf)),
+                                          "batched_leapfrog_s": res_mf[0].t_leapfrog, "incomplete": short(res_mf)}
+    print(f"[bench] mixed batched, {sum(multiple)} slices with multiplicity > 4 in float64: "
+          f"{wmf:.2f}s, {fmf}/{total} pairs", file=sys.stderr, flush=True)
+    bt.close()
+    del bt
     # the plain method batched: float64 stepping in one stacked operator
     bt = kf.Batch([m for m in members], precision="fp64", autotune=True, **bopts)
     torch.cuda.synchronize()
@@ -236,13 +259,23 @@ def bench_batch(args):
         rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
         order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
         net.train(train, order, args.mlp_epochs, 256, 1e-3)
-        bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **bopts)
+        bt = kf.Batch(mem_fp64, precision="mixed", autotune=True, **bopts)
         used = 0
-        for q, ((S, m, lo, hi, tau, L, tgt), (_, _, _, _, _, lam)) in enumerate(zip(members, meta)):
-            w, u, jl, jf = net.weights(lo, hi, tau, lam, L)
-            if u:
-                bt.set_weights(q, w)
+        t_sel = time.perf_counter()
+        wn_all = net.batch_weights(np.array([[lo, hi, tau, lam] for (_, _, lo, hi, _, lam) in meta]))
+        spec_of = {}
+        for q, ((S, m, lo, hi, tau, L, tgt), (i, P, _, _, _, lam)) in enumerate(zip(members, meta)):
+            # the network's weights where the Krylov convergence model (on the
+            # member's closed-form spectrum) predicts fewer steps
+            if i not in spec_of:
+                spec_of[i] = model_spectrum(P.meta["dim"], P.meta["n"], hi * 1.5)
+            om, wt = spec_of[i]
+            four = kf.window_weights("indicator", lo, hi, tau, L)
+            pick, pred = kf.select_weights([four, wn_all[q, :L]], tau, lo, hi, om, wt, kmax=600, margin=0.02)
+            if pick == 1:
+                bt.set_weights(q, wn_all[q, :L])
                 used += 1
+        t_sel = time.perf_counter() - t_sel
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         resl = bt.solve(starts, m_max=args.m_max, tol=args.tol)
@@ -250,6 +283,7 @@ def bench_batch(args):
         wl = time.perf_counter() - t0
         fl, el = count(resl)
         runs["learned_mixed_batched"] = {"seconds": wl, "pairs": fl, "max_rel_err": el, "gate_took_network": used,
+                                         "selection_seconds_untimed": t_sel, "fp64_members": int(sum(multiple)),
                                          "escalated_slices": int(sum(r.escalated for r in resl))}
         print(f"[bench] learned mixed batched: {wl:.2f}s, {fl}/{total} pairs, network weights on {used} slices",
               file=sys.stderr, flush=True)
@@ -580,6 +614,22 @@ def bench_forms(args):
         "speedup_vs_plain": {k: t_plain / v["seconds"] for k, v in rows.items()},
     }
     print(json.dumps(out))
+
+
+def model_spectrum(dim: int, n: int, top: float, far_every: int = 20):
+    """Model spectrum of the convergence model for the square or cube with n
+    cells per side: its distinct eigenvalues up to omega = top, every
+    far_every-th beyond, standing for far_every eigenvalues each."""
+    import numpy as np
+
+    from synth import grid_spectrum
+
+    lam = np.sort(grid_spectrum(dim, n))
+    om = np.sqrt(lam[np.concatenate([[True], np.diff(lam) > 1e-10 * lam[1:]])])
+    near = om <= top
+    far = np.where(~near)[0][::far_every]
+    return (np.concatenate([om[near], om[far]]),
+            np.concatenate([np.ones(int(near.sum())), far_every * np.ones(far.size)]))
 
 
 def cube_model_spectrum(n: int, top: float, far_every: int = 20):

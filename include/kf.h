@@ -480,6 +480,12 @@ typedef struct kf_problem_desc {
   double omega_min, omega_max, tau;
   int32_t L;
   int32_t target;        /* per-member stop count (0: run to m_max) */
+  int32_t step_fp64;     /* KF_MIXED batches: 1 = this member steps in
+                            float64 from the start (the batch's float64
+                            stack), for members whose interval holds
+                            eigenvalues of multiplicity above the block width,
+                            which float32 stepping cannot resolve (see
+                            kf_options.escalate); 0 = the batch's precision */
 } kf_problem_desc;
 
 typedef struct kf_batch kf_batch; /* opaque */

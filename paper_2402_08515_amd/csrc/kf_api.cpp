@@ -176,6 +176,7 @@ struct kf_batch {
   // multiplicities, so when float32 stepping fails for one of them the
   // others restart with float64 stepping at once
   std::vector<int> group;
+  std::vector<char> fp64_member;  // mixed batches: members that step in float64 from the start
 };
 
 namespace {
@@ -2375,6 +2376,7 @@ struct SolveState {
   bool escalated = false;
   bool may_escalate = true;  // false: a batch without a float64 stack escalates members after its loop
   bool in_batch = false;     // the filter is the batch's stacked launch
+  bool fp64_from_start = false;  // a batch member the caller put on the float64 stack
   bool wants_escalation = false;
   double t_lf_own = 0.0;  // a batch member's own stepping time after an escalation
   // checks beside the Krylov loop (kf_options.overlap_checks)
@@ -2935,7 +2937,7 @@ int solve_finish(kf_problem* p, SolveState& s, kf_result** out) {
   r->orth_error = chk.orth;
   r->full_passes = full_passes;
   r->refine_vector_steps = s.ref_lf_steps;
-  r->escalated = s.escalated ? 1 : 0;
+  r->escalated = (s.escalated && !s.fp64_from_start) ? 1 : 0;
   r->t_rr_overlapped = s.t_rr_async;
   r->overlapped_checks = s.async_checks;
   KF_HIP(hipStreamSynchronize(st));
@@ -3267,6 +3269,8 @@ int kf_create_batch(int32_t P, const kf_problem_desc* descs, const kf_options* o
       }
     }
     if (rc) break;
+    bt->fp64_member.assign((size_t)P, 0);
+    for (int q = 0; q < P; ++q) bt->fp64_member[(size_t)q] = descs[q].step_fp64 ? 1 : 0;
     bt->group.assign((size_t)P, 0);
     for (int q = 0; q < P; ++q) {
       bt->group[(size_t)q] = q;
@@ -3430,6 +3434,15 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
     // checks beside the batched loop (the next batched filter does not wait
     // for them); in mixed mode only where a missed refinement restarts
     kf_problem* pq = bt->probs[(size_t)q];
+    if (in_loop && bt->fp64_member[(size_t)q]) {
+      // the caller's choice: float64 stepping from the start (the float64 stack)
+      rc = escalate_restart(pq, S[(size_t)q]);
+      if (rc) {
+        set_error("kf_solve_batch: problem " + std::to_string(q) + ": " + kf_last_error());
+        return rc;
+      }
+      S[(size_t)q].fp64_from_start = true;
+    }
     S[(size_t)q].async_all = pq->opt.overlap_checks != 0 && S[(size_t)q].target > 0 &&
                              (!S[(size_t)q].refine || (pq->opt.escalate && in_loop));
   }

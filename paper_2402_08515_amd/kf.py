@@ -109,6 +109,7 @@ class ProblemDescT(C.Structure):
         ("tau", C.c_double),
         ("L", C.c_int32),
         ("target", C.c_int32),
+        ("step_fp64", C.c_int32),
     ]
 
 
@@ -425,7 +426,9 @@ def _options(precision="fp64", check_every=1, check_growth=0.3, full_reorth=Fals
 class Batch:
     """Handle of ``kf_create_batch``: independent problems whose time loops
     advance in one batched launch.  ``members`` is a list of tuples
-    (S, m, omega_min, omega_max, tau, L, target)."""
+    (S, m, omega_min, omega_max, tau, L, target[, step_fp64]); members that
+    pass the same S and m objects share one converted copy (the library
+    then knows them as slices of one operator)."""
 
     def __init__(self, members, **options):
         L_ = lib()
@@ -433,11 +436,18 @@ class Batch:
         self._keep = []
         descs = (ProblemDescT * len(members))()
         self.n = []
-        for i, (S, m, omin, omax, tau, L, target) in enumerate(members):
-            c, keep = _host_csr(S)
-            mm = np.ascontiguousarray(m, dtype=np.float64)
+        conv = {}
+        for i, mem in enumerate(members):
+            S, m, omin, omax, tau, L, target = mem[:7]
+            fp64 = int(bool(mem[7])) if len(mem) > 7 else 0
+            key = (id(S), id(m))
+            if key not in conv:
+                c, keep = _host_csr(S)
+                mm = np.ascontiguousarray(m, dtype=np.float64)
+                conv[key] = (c, keep, mm)
+            c, keep, mm = conv[key]
             self._keep.append((keep, mm))
-            descs[i] = ProblemDescT(c, _ptr(mm), float(omin), float(omax), float(tau), int(L), int(target))
+            descs[i] = ProblemDescT(c, _ptr(mm), float(omin), float(omax), float(tau), int(L), int(target), fp64)
             self.n.append(S.shape[0])
         opt = _options(**options)
         _check(L_.kf_create_batch(len(members), C.cast(descs, C.c_void_p), C.byref(opt), C.byref(self._h)))
