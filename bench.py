@@ -184,6 +184,7 @@ def bench_batch(args):
     opts = dict(check_every=2, check_growth=0.15)
     bopts = dict(opts, batch_workers=args.batch_workers)
     runs = {}
+    sel_runs = set(args.batch_runs.split(","))
     # mixed, batched (the slices' problems and the stacked operator are built,
     # and the batched step variant timed, before the timed region)
     bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **bopts)
@@ -224,37 +225,43 @@ def bench_batch(args):
     # (the remedy for what float32 stepping cannot resolve; the closed-form
     # spectrum tells which slices they are)
     mem_fp64 = [m + (f,) for m, f in zip(members, multiple)]
-    bt = kf.Batch(mem_fp64, precision="mixed", autotune=True, **bopts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res_mf = bt.solve(starts, m_max=args.m_max, tol=args.tol)
-    torch.cuda.synchronize()
-    wmf = time.perf_counter() - t0
-    fmf, emf = count(res_mf)
-    runs["mixed_batched_fp64_members"] = {"seconds": wmf, "pairs": fmf, "max_rel_err": emf,
-                                          "fp64_members": int(sum(multiple)),
-                                          "escalated_slices": int(sum(r.escalated for r in res_mf)),
-                                          "batched_leapfrog_s": res_mf[0].t_leapfrog, "incomplete": short(res_mf)}
-    print(f"[bench] mixed batched, {sum(multiple)} slices with multiplicity > 4 in float64: "
-          f"{wmf:.2f}s, {fmf}/{total} pairs", file=sys.stderr, flush=True)
-    bt.close()
-    del bt
-    # the plain method batched: float64 stepping in one stacked operator
-    bt = kf.Batch([m for m in members], precision="fp64", autotune=True, **bopts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res_b64 = bt.solve(starts, m_max=args.m_max, tol=args.tol)
-    torch.cuda.synchronize()
-    wb64 = time.perf_counter() - t0
-    fb64, eb64 = count(res_b64)
-    runs["fp64_batched"] = {"seconds": wb64, "pairs": fb64, "max_rel_err": eb64,
-                            "batched_leapfrog_s": res_b64[0].t_leapfrog, "incomplete": short(res_b64)}
-    print(f"[bench] fp64 batched: {wb64:.2f}s, {fb64}/{total} pairs", file=sys.stderr, flush=True)
-    bt.close()
-    del bt
+    if "fp64members" in sel_runs:
+        bt = kf.Batch(mem_fp64, precision="mixed", autotune=True, **bopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res_mf = bt.solve(starts, m_max=args.m_max, tol=args.tol)
+        torch.cuda.synchronize()
+        wmf = time.perf_counter() - t0
+        fmf, emf = count(res_mf)
+        runs["mixed_batched_fp64_members"] = {"seconds": wmf, "pairs": fmf, "max_rel_err": emf,
+                                              "fp64_members": int(sum(multiple)),
+                                              "escalated_slices": int(sum(r.escalated for r in res_mf)),
+                                              "batched_leapfrog_s": res_mf[0].t_leapfrog, "incomplete": short(res_mf)}
+        print(f"[bench] mixed batched, {sum(multiple)} slices with multiplicity > 4 in float64: "
+              f"{wmf:.2f}s, {fmf}/{total} pairs", file=sys.stderr, flush=True)
+        bt.close()
+        del bt
+    if "fp64batched" in sel_runs:
+        # the plain method batched: float64 stepping in one stacked operator
+        bt = kf.Batch([m for m in members], precision="fp64", autotune=True, **bopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res_b64 = bt.solve(starts, m_max=args.m_max, tol=args.tol)
+        torch.cuda.synchronize()
+        wb64 = time.perf_counter() - t0
+        fb64, eb64 = count(res_b64)
+        runs["fp64_batched"] = {"seconds": wb64, "pairs": fb64, "max_rel_err": eb64,
+                                "batched_leapfrog_s": res_b64[0].t_leapfrog, "incomplete": short(res_b64)}
+        print(f"[bench] fp64 batched: {wb64:.2f}s, {fb64}/{total} pairs", file=sys.stderr, flush=True)
+        bt.close()
+        del bt
     # learned weights where the gate takes them, mixed, batched
     if not args.no_learned:
-        train = filter_samples(args.mlp_samples, stream=0)
+        # trained on the batch's own spectral range (the members' lambda_max),
+        # intervals from the evaluation law (omega_min ~ U[5, 50], width ~ U[5, 20])
+        lams = [lam for (_, _, _, _, _, lam) in meta]
+        lam_rng = (0.9 * min(lams), 1.1 * max(lams))
+        train = filter_samples(args.mlp_samples, stream=0, lam_range=lam_rng)
         net = kf.Mlp(init_params(4).astype(np.float32))
         rng = np.random.default_rng(np.random.SeedSequence(4).spawn(3)[2])
         order = np.concatenate([rng.permutation(len(train)) for _ in range(args.mlp_epochs)]).astype(np.int32)
@@ -270,9 +277,16 @@ def bench_batch(args):
             if i not in spec_of:
                 spec_of[i] = model_spectrum(P.meta["dim"], P.meta["n"], hi * 1.5)
             om, wt = spec_of[i]
+            # only inputs inside the range the network was trained on (its
+            # samples' interval widths; the slices cut from wide intervals are
+            # narrower), and only a prediction that resolves the slice within
+            # the model's step limit
+            if not (lam_rng[0] <= lam <= lam_rng[1] and 5.0 <= hi - lo <= 20.0):
+                continue
             four = kf.window_weights("indicator", lo, hi, tau, L)
-            pick, pred = kf.select_weights([four, wn_all[q, :L]], tau, lo, hi, om, wt, kmax=600, margin=0.02)
-            if pick == 1:
+            kmax = 1500
+            pick, pred = kf.select_weights([four, wn_all[q, :L]], tau, lo, hi, om, wt, kmax=kmax, margin=0.02)
+            if pick == 1 and pred[1] < kmax:
                 bt.set_weights(q, wn_all[q, :L])
                 used += 1
         t_sel = time.perf_counter() - t_sel
@@ -775,6 +789,9 @@ def main():
     ap.add_argument("--slice-target", type=int, default=150,
                     help="batch: intervals with more pairs are cut into slices of at most this many")
     ap.add_argument("--no-learned", action="store_true", help="batch: skip the learned-weights run")
+    ap.add_argument("--batch-runs", default="mixed,fp64members,fp64batched",
+                    help="batch: which batched forms to time (mixed, fp64members, fp64batched; the learned form "
+                         "and the one-by-one float64 run have their own switches)")
     ap.add_argument("--batch-workers", type=int, default=0,
                     help="batch: host threads driving the members' projection work (0: min(8, members))")
     ap.add_argument("--mlp-samples", type=int, default=50000)

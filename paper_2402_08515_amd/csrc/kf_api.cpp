@@ -2566,6 +2566,8 @@ int escalate_restart(kf_problem* p, SolveState& s) {
   s.Aop = &p->A64;
   s.sbop = &p->sb64;
   s.refine = false;
+  // from here on a float64 solve: its early checks may run beside the loop
+  if (!s.in_batch && p->opt.overlap_checks != 0 && s.target > 0) s.async_ok = true;
   s.tol_loop = s.tol;
   s.margin = 0.0;
   s.proj_every = std::min(p->opt.proj_every, 15);

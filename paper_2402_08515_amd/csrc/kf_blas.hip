@@ -511,13 +511,21 @@ __global__ __launch_bounds__(256) void k_spmv_cols(int32_t n, int32_t nslices, c
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  // every column's gather is issued unconditionally (columns past ncols read
+  // column ncols-1 again and are not stored), so all NC loads of an entry are
+  // in flight together
+  const double* __restrict__ xc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) xc[c] = X + (int64_t)(c < ncols ? c : ncols - 1) * ldx;
   for (int q = 0; q < width; ++q) {
     const double a = val[base + (int64_t)q * 64 + lane];
     const IT ci = idx[base + (int64_t)q * 64 + lane];
     const int64_t col = relative ? row + (int)ci : (int)ci;
+    double xv[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < ncols) acc[c] = fma(a, X[col + (int64_t)c * ldx], acc[c]);
+    for (int c = 0; c < NC; ++c) xv[c] = xc[c][col];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = fma(a, xv[c], acc[c]);
   }
   const double sc = rscale ? rscale[row] : 1.0;
 #pragma unroll
@@ -1097,6 +1105,12 @@ int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t 
       else if (nc <= 4)
         hipLaunchKernelGGL((k_spmv_cols<int16_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
                            (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 8)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 8>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 12)
+        hipLaunchKernelGGL((k_spmv_cols<int16_t, 12>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
       else
         hipLaunchKernelGGL((k_spmv_cols<int16_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
                            (const double*)S.val, (const int16_t*)S.idx, x, ldx, y, ldy, nc, rscale);
@@ -1106,6 +1120,9 @@ int spmv_cols(const SellOp& S, const double* X, int64_t ldx, double* Y, int64_t 
                            (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
       else if (nc <= 4)
         hipLaunchKernelGGL((k_spmv_cols<int32_t, 4>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
+                           (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
+      else if (nc <= 8)
+        hipLaunchKernelGGL((k_spmv_cols<int32_t, 8>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
                            (const double*)S.val, (const int32_t*)S.idx, x, ldx, y, ldy, nc, rscale);
       else
         hipLaunchKernelGGL((k_spmv_cols<int32_t, 16>), dim3(grid), dim3(256), 0, st, S.n, S.nslices, S.slice_ptr,
