@@ -778,6 +778,8 @@ def main():
     ap.add_argument("--check-growth", type=float, default=0.3)
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--proj-every", type=int, default=12,
+                    help="single vectors: steps between projections onto the whole basis")
     ap.add_argument("--no-overlap", action="store_true",
                     help="every Rayleigh-Ritz check stops the Krylov loop (no check on a second stream)")
     ap.add_argument("--gather-unroll", type=int, default=0,
@@ -848,7 +850,8 @@ def main():
     print(f"[bench] lambda_est={lam:.6g} tau={tau:.6g} L={L}", file=sys.stderr, flush=True)
     prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, precision=P.precision, target=target,
                       check_every=args.check_every, check_growth=args.check_growth, autotune=not args.no_autotune,
-                      gather_unroll=args.gather_unroll, overlap_checks=not args.no_overlap)
+                      gather_unroll=args.gather_unroll, overlap_checks=not args.no_overlap,
+                      proj_every=args.proj_every)
     tuning = prob.tuning()
     print(f"[bench] fused-step variant {tuning}", file=sys.stderr, flush=True)
     V0 = start_block(P.n, P.block, P.seed)

@@ -61,7 +61,10 @@ def test_window_filter_on_gpu_matches_oracle_and_solves(kind, width):
     lam = oracle.power_lambda_max(P.S, P.m, power_start(P.n, P.seed), 30)
     tau, L = oracle.time_step_rule(lam, P.omega_min)
     w = kf.window_weights(kind, P.omega_min, P.omega_max, tau, L, width)
-    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, target=11)
+    # checks in line: the solve stops where the oracle's does (a check beside
+    # the loop reports a later basis, where second copies of the square's
+    # double eigenvalues may also have converged)
+    prob = kf.Problem(P.S, P.m, P.omega_min, P.omega_max, tau, L, target=11, overlap_checks=False)
     prob.set_weights(w)
     x = torch.from_numpy(start_block(P.n, 3, 12)).cuda()
     y = prob.apply_filter(x).cpu().numpy()
