@@ -161,7 +161,7 @@ def bench_batch(args):
         if i not in lam_of:
             lam_of[i] = kf.estimate_lambda_max(P.S, P.m, 30, power_start(P.n, P.seed))
         tau, L_rule = kf.time_step_rule(lam_of[i], lo)
-        L = max(L_rule, int(math.ceil(2 * math.pi / (3.0 * (hi - lo) * tau))))
+        L = max(L_rule, int(math.ceil(2 * math.pi / (args.slice_transition * (hi - lo) * tau))))
         members.append((P.S, P.m, lo, hi, tau, L, tgt))
         starts.append(start_block(P.n, P.block, P.seed))
         meta.append((i, P, lo, hi, tgt, lam_of[i]))
@@ -791,6 +791,9 @@ def main():
     ap.add_argument("--slice-target", type=int, default=150,
                     help="batch: intervals with more pairs are cut into slices of at most this many")
     ap.add_argument("--no-learned", action="store_true", help="batch: skip the learned-weights run")
+    ap.add_argument("--slice-transition", type=float, default=3.0,
+                    help="batch: a slice of width d gets L >= 2 pi / (this * d * tau), i.e. a filter transition "
+                         "of at most this many slice widths")
     ap.add_argument("--batch-runs", default="mixed,fp64members,fp64batched",
                     help="batch: which batched forms to time (mixed, fp64members, fp64batched; the learned form "
                          "and the one-by-one float64 run have their own switches)")
