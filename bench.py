@@ -805,14 +805,10 @@ def main():
     ap.add_argument("--learned-count", type=int, default=32)
     ap.add_argument("--learned-max-target", type=int, default=200)
     ap.add_argument("--learned-precision", default="mixed", choices=("mixed", "fp64"))
-    ap.add_argument("--batch-iters", type=int, default=24,
-                    help="Krylov iterations per member in the batch benchmark (the full targets need thousands)")
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--forms-count", type=int, default=16, help="squares in the forms comparison")
     ap.add_argument("--horn-interval", type=float, nargs=2, default=(200.0, 220.0),
                     help="horn sub-interval solved to completion (ends must be keys of the stored inertia counts)")
-    ap.add_argument("--horn-iters", type=int, default=24,
-                    help="block Krylov iterations of the horn benchmark (its interval holds thousands of pairs)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a few filter applications and a plain copy of known size")
     args = ap.parse_args()
