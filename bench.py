@@ -187,7 +187,8 @@ def bench_batch(args):
     sel_runs = set(args.batch_runs.split(","))
     # mixed, batched (the slices' problems and the stacked operator are built,
     # and the batched step variant timed, before the timed region)
-    bt = kf.Batch([m for m in members], precision="mixed", autotune=True, **bopts)
+    bt = kf.Batch([m for m in members], precision="mixed", autotune=True,
+                  **(dict(bopts, escalate=False) if args.batch_no_restart else bopts))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = bt.solve(starts, m_max=args.m_max, tol=args.tol)
@@ -797,6 +798,9 @@ def main():
     ap.add_argument("--batch-runs", default="mixed,fp64members,fp64batched",
                     help="batch: which batched forms to time (mixed, fp64members, fp64batched; the learned form "
                          "and the one-by-one float64 run have their own switches)")
+    ap.add_argument("--batch-no-restart", action="store_true",
+                    help="batch: in the first (mixed) form a member whose float64 refinement misses ends there "
+                         "instead of restarting with float64 stepping (the float32 stack alone)")
     ap.add_argument("--batch-workers", type=int, default=0,
                     help="batch: host threads driving the members' projection work (0: min(8, members))")
     ap.add_argument("--mlp-samples", type=int, default=50000)

@@ -103,15 +103,18 @@ typedef struct kf_options {
                             of proj_every the basis stays M-orthonormal to
                             about 1e-7 (reported as kf_result.orth_error);
                             0 = always subtract */
-  int32_t proj_every;    /* KF_FP64, single-vector blocks, full_reorth 0: the
+  int32_t proj_every;    /* float64 stepping, full_reorth 0: the
                             projection onto the whole basis (which forms the
                             new columns of B^T S B and B^T M B and the
                             orthogonalisation coefficients) runs every
-                            proj_every steps; in between a step is
-                            orthogonalised against the last two columns only
-                            (three-term form).  A projection cleans the new
-                            column and the last column of the previous
-                            interval (both feed the next step).  Columns found
+                            proj_every steps, and at the latest when 16
+                            columns would be pending; in between a step is
+                            orthogonalised against the last two columns or
+                            blocks only (three-term form; a block is then
+                            orthonormalised by Cholesky QR twice).  For a
+                            single vector a projection cleans the new column
+                            and the last column of the previous interval
+                            (both feed the next step).  Columns found
                             more than 1e-7 off M-orthogonal at a projection
                             are orthogonalised
                             again and proj_every is halved from then on (a

@@ -603,6 +603,13 @@ int ensure_misc(kf_problem* p) {
 // projection (the block sits right after its left operand in B: X is column
 // kb = c0), so the norms before each pass cost no launch of their own.
 //
+// monitor = false (three-term form, between the periodic projections): the
+// window pass is the only pass over the basis; a single vector is normalised
+// from the window's Gram matrix, a block by Cholesky QR twice.  Columns
+// formed this way stay pending until the next projection (pn > 0), which
+// forms their pencil entries and checks their drift from M-orthogonality with
+// the older basis (*pending_loose; drifted columns are repaired).
+//
 // carried != null (one vector, three-term form, pending columns): the
 // periodic projection also cleans the last pending column, column kb - 1,
 // against the rest of the basis, in the same subtraction as the new column.
@@ -839,16 +846,62 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       if (done) KF_HIP(hipEventRecord(done, st));
     }
   } else if (kb > 0) {
-    KF_TRY(full_pass(true));
-    KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
     std::vector<double> hg1((size_t)ldc * nb), hg2((size_t)nb * nb);
-    KF_TRY(fetch(coef + (int64_t)(2 * pn) * ldc, (size_t)ldc * nb, hg1.data()));
-    KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
-    KF_HIP(hipStreamSynchronize(st));
-    rb.land();
     bool again = false;
-    for (int j = 0; j < nb; ++j)
-      if (hg2[(size_t)j * nb + j] < 0.25 * hg1[(size_t)kb + j + (size_t)j * ldc]) again = true;
+    bool between = local && !monitor;
+    const bool hv_read = between;  // hv holds T1 (read with the Gram matrix)
+    if (between) {
+      // a block between projections (three-term form): the window pass above
+      // is its only pass over the basis; Cholesky QR within the block when
+      // no column lost more than all but 1e-4 of its squared M-norm to the
+      // window (else the cancellation calls for the full pass below)
+      KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+      KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
+      KF_TRY(fetch(T1, (size_t)ld1 * nb, hv.data()));
+      KF_HIP(hipStreamSynchronize(st));
+      rb.land();
+      for (int j = 0; j < nb; ++j)
+        if (!(hg2[(size_t)j * nb + j] >= 1e-4 * hv[(size_t)lw + j + (size_t)j * ld1])) between = false;
+      if (!between) {
+        // (the columns formed since the last projection stay pending)
+        KF_TRY(full_pass(false));
+        KF_TRY(full_pass(false));
+        KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+        KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
+        KF_HIP(hipStreamSynchronize(st));
+        rb.land();
+      }
+    } else {
+      KF_TRY(full_pass(true));
+      int32_t* loose = p->flags + 33;
+      int32_t lh = 0;
+      const bool gate_pending = pending_loose && pn > 0 && local;
+      // columns formed since the previous projection were orthogonalised
+      // against their window only: their drift from M-orthogonality with the
+      // older basis is checked here (as for single vectors)
+      if (gate_pending) KF_TRY(block_gate(kb, kb - pn, pn, coef + (int64_t)pn * ldc, ldc, kPendingTol, loose, st));
+      KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+      KF_TRY(fetch(coef + (int64_t)(2 * pn) * ldc, (size_t)ldc * nb, hg1.data()));
+      KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
+      if (gate_pending) KF_TRY(rb.get(&lh, loose, sizeof(int32_t)));
+      KF_HIP(hipStreamSynchronize(st));
+      rb.land();
+      if (pending_loose) *pending_loose = lh != 0;
+      if (lh) {
+        // repair the drifted columns, then orthogonalise the block against
+        // the repaired basis twice
+        KF_TRY(repair_block(p, kb - pn, pn));
+        KF_TRY(full_pass(false));
+        KF_TRY(full_pass(false));
+        KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
+        KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
+        KF_HIP(hipStreamSynchronize(st));
+        rb.land();
+      } else {
+        for (int j = 0; j < nb; ++j)
+          if (hg2[(size_t)j * nb + j] < 0.25 * hg1[(size_t)kb + j + (size_t)j * ldc]) again = true;
+      }
+    }
     if (again) KF_TRY(full_pass(false));
     // within the block: Cholesky QR twice (four launches per pass, and no
     // column can be dropped: the full pass kept >= 1/4 of every norm and each
@@ -878,6 +931,11 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       KF_TRY(chol_orthonormalise(n, nb, X, ldb, g2, Rinv, p->flags, post, st));
       KF_TRY(gemv_t(n, nb, X, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, g2, nb, p->gw, st));
       KF_TRY(chol_orthonormalise(n, nb, X, ldb, g2, Rinv, p->flags, post, st));
+      if (hv_read) {
+        // every column kept: nothing more to read back
+        for (int j = 0; j < nb; ++j) fl[(size_t)j] = 1;
+        have = true;
+      }
     } else {
       KF_TRY(finish_cols(Tref, ld1));
     }
@@ -2738,11 +2796,12 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
     }
   }
   int kept = 0;
-  // single vectors in the three-term form project onto the whole basis every
-  // proj_every steps (the new column and the last pending one are cleaned);
+  // in the three-term form the projection onto the whole basis runs every
+  // proj_every steps (single vectors: the new column and the last pending one
+  // are cleaned; blocks: the new block), and at most 15 columns are pending;
   // columns that drifted beyond kPendingTol are repaired and the interval
   // halved
-  const bool three = !p->opt.full_reorth && s.bk == 1 && s.cur > 0;
+  const bool three = !p->opt.full_reorth && s.cur > 0;
   const bool monitor = !three || s.proj_every <= 1 || s.since_proj + 1 >= s.proj_every ||
                        s.pending + s.bk > 15;
   bool loose = false;
@@ -2752,7 +2811,7 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
   const int it1 = s.iters, cur1 = s.cur + s.bk;
   const bool check_next = it1 % p->opt.check_every == 0 && cur1 >= s.next_check;
   const bool go_on = !(p->opt.max_iters > 0 && it1 >= p->opt.max_iters) && cur1 < s.m_max;
-  const bool ahead_ok = s.ahead_ok && three && !monitor && !check_next && go_on;
+  const bool ahead_ok = s.ahead_ok && three && s.bk == 1 && !monitor && !check_next && go_on;
   const int64_t ldb = p->ldb;
   const std::function<int()> ahead = [&]() -> int {
     KF_HIP(hipEventRecord(p->ev[5], st));

@@ -113,9 +113,12 @@ def test_block_start_recovers_multiplicities(b):
     np.testing.assert_allclose(got.omega2, expect, rtol=1e-10)
     np.testing.assert_allclose(got.omega2, ref.omega2, rtol=1e-10)
     # b = 3 runs in blocks of 4 whose fourth column is zero: it must be dropped
-    # (the basis stays M-orthonormal and grows by at most b per step after the
-    # start block)
-    assert got.orth_error < 1e-8
+    # (the basis grows by at most b per step after the start block).  Between
+    # the periodic projections a block is orthogonalised against the last two
+    # blocks only (three-term form of Algorithm 2.5, C being M-self-adjoint by
+    # Lemma 2.3); a projection repairs columns more than 1e-7 off
+    # M-orthogonal, so the basis stays M-orthonormal to that level
+    assert got.orth_error < 1e-6
     assert got.basis_size <= b * (got.krylov_steps + 1)
 
 
