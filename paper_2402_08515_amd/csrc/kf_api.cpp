@@ -2442,6 +2442,9 @@ struct SolveState {
   bool async_all = false;  // batch members: every check beside the loop
   int async_checks = 0;
   double t_rr_async = 0.0;
+  // host wall seconds (batch progress report): orthogonalisation, checks and
+  // refinement (taken results included)
+  double h_orth = 0.0, h_check = 0.0;
 };
 
 int elapsed_acc(hipEvent_t a, hipEvent_t b, double& acc) {
@@ -2821,9 +2824,12 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
     return KF_OK;
   };
   bool ahead_kept = false, carried = false;
+  const double h0 = now_s();
   KF_TRY(orth_block(p, s.cur, s.cur, s.bk, &kept, s.ref, p->ev[2], monitor ? s.pending : 0,
                     p->opt.full_reorth ? -1 : s.prev0, &s.full_passes, monitor, &loose, ahead_ok ? &ahead : nullptr,
                     &ahead_kept, s.proj_every > 1 ? &carried : nullptr));  // synchronises with the step's readback
+  const double h1 = now_s();
+  s.h_orth += h1 - h0;
   if (loose) s.proj_every = std::max(1, s.proj_every / 2);
   if (monitor) {
     // the last pending column, cleaned with the new one, stays pending (with
@@ -2892,6 +2898,7 @@ int solve_after_filter(kf_problem* p, SolveState& s) {
       s.done = true;
     }
   }
+  s.h_check += now_s() - h1;
   (void)st;
   return KF_OK;
 }
@@ -3535,14 +3542,18 @@ int kf_solve_batch(kf_batch* bt, const double* const* starts, int32_t b, int32_t
     if (!any[0] && !any[1]) break;
     if (progress && ++round % 100 == 0) {
       int na = 0, ne = 0;
+      double ho = 0.0, hc = 0.0;
       for (int q = 0; q < bt->P; ++q) {
         na += (bt->stk[0].h_tb.active[q] || (bt->nstk > 1 && bt->stk[1].h_tb.active[q])) ? 1 : 0;
         ne += S[(size_t)q].escalated ? 1 : 0;
+        ho += S[(size_t)q].h_orth;
+        hc += S[(size_t)q].h_check;
       }
       std::fprintf(stderr,
                    "[kf] batch: %d filter launches, %d of %d members stepping, %d restarted in float64; "
-                   "%.2f s batched filter, %.2f s member Gram-Schmidt/Rayleigh-Ritz\n",
-                   round, na, bt->P, ne, host_filter, host_members);
+                   "%.2f s batched filter, %.2f s member Gram-Schmidt/Rayleigh-Ritz (summed over members: "
+                   "%.2f s orthogonalisation, %.2f s checks and refinement)\n",
+                   round, na, bt->P, ne, host_filter, host_members, ho, hc);
       std::fflush(stderr);
     }
     const bool par = bt->workers > 1;
