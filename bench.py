@@ -713,7 +713,8 @@ def bench_learned(args):
                  kf.window_weights("triangle", lo, hi, tau, L, 2.0)]
         omod, wmod = cube_model_spectrum(n, 3.0 * hi)
         t1 = time.perf_counter()
-        pick, pred = kf.select_weights(cands, tau, lo, hi, omod, wmod, eps=args.tol, kmax=1500, margin=0.02)
+        pick, pred = kf.select_weights(cands, tau, lo, hi, omod, wmod, eps=args.tol, kmax=args.learned_m_max,
+                                       margin=0.02)
         t_sel = time.perf_counter() - t1
         rec = {"interval": [lo, hi], "target": tgt, "L": L, "selected": names[pick],
                "predicted_steps": dict(zip(names, [int(x) for x in pred])), "select_seconds": t_sel}
@@ -727,7 +728,7 @@ def bench_learned(args):
             prob.set_weights(w)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            r = prob.solve(V0, m_max=1024, tol=args.tol)
+            r = prob.solve(V0, m_max=args.learned_m_max, tol=args.tol)
             dt = time.perf_counter() - t1
             err = None
             if r.omega2.size:
@@ -751,7 +752,8 @@ def bench_learned(args):
         "unit": "s",
         "n_gpus": 1,
         "config": {"workload": f"grid3d_{n} learned-vs-Fourier", "intervals": len(rows), "tol": args.tol,
-                   "precision": args.learned_precision, "max_target": args.learned_max_target},
+                   "precision": args.learned_precision, "max_target": args.learned_max_target,
+                   "m_max": args.learned_m_max},
         "train_seconds": t_train,
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
         "fourier_seconds": tot("fourier", "seconds"),
@@ -807,7 +809,10 @@ def main():
     ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--learned-n", type=int, default=128)
     ap.add_argument("--learned-count", type=int, default=32)
-    ap.add_argument("--learned-max-target", type=int, default=200)
+    ap.add_argument("--learned-max-target", type=int, default=450,
+                    help="learned: intervals holding more distinct eigenvalues are skipped (three of the 32 hold "
+                         "538-618, beyond what a 2048-column basis resolves with one start vector)")
+    ap.add_argument("--learned-m-max", type=int, default=2048, help="learned: basis columns per solve")
     ap.add_argument("--learned-precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--forms-count", type=int, default=16, help="squares in the forms comparison")
