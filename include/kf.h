@@ -134,10 +134,13 @@ typedef struct kf_options {
                             step, directions of eigenspaces of multiplicity
                             above b that pollute the Ritz vectors of other
                             eigenvalues where the filter cannot tell them
-                            apart), 1 = the Krylov loop starts again from the
-                            start block with float64 stepping
-                            (kf_result.escalated), so the target is still
-                            met; 0 = up to 4 further refinements instead */
+                            apart), or as soon as a check of the float32 loop
+                            accepts more than b copies of one eigenvalue (the
+                            symptom of that seeding), 1 = the Krylov loop
+                            starts again from the start block with float64
+                            stepping (kf_result.escalated), so the target is
+                            still met; 0 = up to 4 further refinements
+                            instead */
   int32_t want_vectors;  /* kf_result.vectors is filled when nonzero */
   int32_t index_bytes;   /* column-index width of the device operator:
                             0 = automatic (2 when every |col - row| < 32768),

@@ -1649,6 +1649,20 @@ int distinct_count(const std::vector<double>& acc, int b) {
   return cnt;
 }
 
+// More than b accepted Ritz values within 1e-8 of each other (ascending acc):
+// a block of b start vectors reaches at most b directions of an eigenspace in
+// exact arithmetic, so the extra copies were seeded by round-off.
+bool copies_beyond_block(const std::vector<double>& acc, int b) {
+  size_t i = 0;
+  while (i < acc.size()) {
+    size_t j = i + 1;
+    while (j < acc.size() && acc[j] - acc[j - 1] <= 1e-8 * std::fabs(acc[j])) ++j;
+    if (j - i > (size_t)b) return true;
+    i = j;
+  }
+  return false;
+}
+
 // Time `reps` fused steps of operator A for a block of bk vectors with the
 // given XCD mapping; returns microseconds per step.
 int time_variant(kf_problem* p, const SellOp& A, StepBufs& sb, int remap, int reps, double* us, int bk = 1) {
@@ -2718,8 +2732,21 @@ int escalate_restart(kf_problem* p, SolveState& s);
 // After a check at the current basis size: the target reached at the loop's
 // tolerance ends the solve (float64 stepping) or starts the float64
 // refinement (mixed), which ends it, restarts with float64 stepping
-// (escalate), or lets the loop go on.
+// (escalate), or lets the loop go on.  A float32 loop whose check accepted
+// more copies of one eigenvalue than the block width restarts with float64
+// stepping at once (escalate): those copies come from float32 round-off along
+// an eigenspace of multiplicity above b, the case no refinement of this basis
+// resolves, and every further float32 step would be lost work.
 int decide_after_check(kf_problem* p, SolveState& s) {
+  if (s.refine && p->opt.escalate && !s.escalated && s.target > 0 && copies_beyond_block(s.chk.acc_theta, s.b)) {
+    if (s.may_escalate) {
+      KF_TRY(escalate_restart(p, s));
+    } else {
+      s.wants_escalation = true;
+      s.done = true;
+    }
+    return KF_OK;
+  }
   if (!(s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target)) return KF_OK;
   if (!s.refine) {
     s.done = true;
@@ -2764,6 +2791,10 @@ int solve_take_overlapped(kf_problem* p, SolveState& s) {
   s.t_rr_async += secs;
   s.chk = std::move(c);
   s.next_check = next_check_at(p, s, k);
+  if (s.refine && p->opt.escalate && s.target > 0 && copies_beyond_block(s.chk.acc_theta, s.b)) {
+    // (see decide_after_check: float32 round-off copies, restart now)
+    return decide_after_check(p, s);
+  }
   if (s.target > 0 && distinct_count(s.chk.acc_theta, s.b) >= s.target) {
     s.cur = k;
     s.checked_at = k;
