@@ -122,6 +122,32 @@ def test_block_start_recovers_multiplicities(b):
     assert got.basis_size <= b * (got.krylov_steps + 1)
 
 
+def test_block_three_term_form_matches_projection_at_every_step():
+    # blocks of 4 between periodic projections (window pass + Cholesky QR)
+    # against the same solve projecting at every step (proj_every = 1), the
+    # oracle and the closed form; the periodic mode must have skipped passes
+    kf = _kf()
+    S, m, h = grid_problem(2, 40)
+    lam = grid_spectrum(2, 40)
+    tau, L = oracle.time_step_rule(lam.max(), 20.0)
+    w = oracle.discrete_weights(20.0, 30.0, tau, L)
+    tgt, vals, mult = distinct_target(lam, 20.0, 30.0, 4)
+    V0 = start_block(S.shape[0], 4, 21)
+    print(f"case block three-term b=4 target={tgt} L={L}", flush=True)
+    ref = oracle.krylov_solve(S, m, tau, w, V0, 20.0, 30.0, tol=1e-9, m_max=400, target=tgt)
+    every = kf.Problem(S, m, 20.0, 30.0, tau, L, target=tgt, proj_every=1).solve(V0, m_max=400, tol=1e-9)
+    three = kf.Problem(S, m, 20.0, 30.0, tau, L, target=tgt).solve(V0, m_max=400, tol=1e-9)
+    expect = np.repeat(vals, np.minimum(mult, 4))
+    for got in (every, three):
+        assert got.omega2.size == tgt == ref.omega2.size
+        np.testing.assert_allclose(got.omega2, expect, rtol=1e-10)
+        np.testing.assert_allclose(got.omega2, ref.omega2, rtol=1e-10)
+        assert got.residual.max() <= 1e-9
+    assert every.full_passes >= every.krylov_steps - 1
+    assert three.full_passes < every.full_passes
+    assert three.orth_error < 1e-6
+
+
 def test_unstructured_neumann_matches_oracle():
     kf = _kf()
     S, m = jittered_problem(2, 14, 0.2, seed=11)
