@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_gemv_t_mfma_a(
     int32_t n, int k, const double* __restrict__ Bk, int64_t ldb, const double* __restrict__ X1, int n1, int64_t ldx1,
     const double* __restrict__ X2, int n2, int64_t ldx2, const double* __restrict__ m, double* __restrict__ partial,
     int TCH) {
-  constexpr int NA = NX > 16 ? 2 : 1;
+  constexpr int NA = (NX + 15) / 16;
   constexpr int G = 64 * kMfmaWaves / SUB;
   constexpr int CPT = NX / G;
   static_assert(G * SUB == 64 * kMfmaWaves && CPT * G == NX, "staging layout");
@@ -833,10 +833,11 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
   // of 32 along the grid's z, chunks of 2048 rows (the sums over rows stay
   // in the accumulators)
   const bool mfma = nrhs > 3;
+  const int vec = ((uintptr_t)Bk % 32 == 0 && ldb % 4 == 0) ? 1 : 0;
   // row chunks of 2048 (1024 on the vector path), halved down to 256 while
   // the grid would leave the chip mostly idle (small problems, few columns)
   const int cols_per_wg = mfma ? 16 * kMfmaWaves : 64;
-  const int zgroups = !mfma ? 1 : (nrhs <= 16 ? 1 : ceil_div64(nrhs, 32));
+  const int zgroups = !mfma ? 1 : (nrhs <= 16 || (vec && nrhs <= 48) ? 1 : ceil_div64(nrhs, 32));
   int CH = mfma ? 2048 : 1024;
   while (CH > 256 && (int64_t)ceil_div64(n, CH) * ceil_div64(k, cols_per_wg) * zgroups < 1024) CH /= 2;
   const int nchunks = ceil_div64(n, CH);
@@ -868,7 +869,12 @@ int gemv_t(int32_t n, int k, const double* Bk, int64_t ldb, const double* X1, in
     const int vec = ((uintptr_t)Bk % 32 == 0 && ldb % 4 == 0 && CH % 64 == 0) ? 1 : 0;
     const int cols = 16 * kMfmaWaves;
     const dim3 block(64 * kMfmaWaves);
-    if (vec && nrhs <= 8)
+    if (vec && nrhs > 32 && nrhs <= 48)
+      // (a block of 16 with its pending block's S- and M-products: one pass
+      // over the basis instead of two groups of 32)
+      hipLaunchKernelGGL((k_gemv_t_mfma_a<48, 128, 2>), dim3(nchunks, ceil_div64(k, cols), 1), block, 0, st, n, k, Bk,
+                         ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH);
+    else if (vec && nrhs <= 8)
       hipLaunchKernelGGL((k_gemv_t_mfma_a<8, 256, 2>), dim3(nchunks, ceil_div64(k, cols), 1), block, 0, st, n, k, Bk,
                          ldb, X1, n1, ldx1, X2, n2, ldx2, m, wk.partial, CH);
     else if (vec && nrhs <= 16)
