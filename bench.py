@@ -181,7 +181,7 @@ def bench_batch(args):
                 errs.append(float(np.max(np.abs(r.omega2 - near) / near)))
         return int(found), max(errs) if errs else None
 
-    opts = dict(check_every=2, check_growth=0.15)
+    opts = dict(check_every=2, check_growth=args.batch_check_growth)
     bopts = dict(opts, batch_workers=args.batch_workers)
     runs = {}
     sel_runs = set(args.batch_runs.split(","))
@@ -335,7 +335,7 @@ def bench_batch(args):
         "dtype": "f32-step/f64-proj",
         "data": "synthetic",
         "config": {"workload": f"batch64[:{args.batch_count}]", "slices": len(members), "block": 4,
-                   "tol": args.tol, "m_max": args.m_max, "slice_target": args.slice_target,
+                   "tol": args.tol, "m_max": args.m_max, "slice_target": args.slice_target, "check_growth": args.batch_check_growth,
                    "target_pairs": int(total), "parallelism": "1 GPU"},
         "s_to_all_eigenpairs": wall if found >= total else None,
         "pairs_accepted": found,
@@ -800,6 +800,9 @@ def main():
     ap.add_argument("--batch-runs", default="mixed,fp64members,fp64batched",
                     help="batch: which batched forms to time (mixed, fp64members, fp64batched; the learned form "
                          "and the one-by-one float64 run have their own switches)")
+    ap.add_argument("--batch-check-growth", type=float, default=0.75,
+                    help="batch: basis growth between Rayleigh-Ritz checks of a member (their tridiagonalisation and "
+                         "inverse iteration dominate the members' device time at small growth)")
     ap.add_argument("--batch-no-restart", action="store_true",
                     help="batch: in the first (mixed) form a member whose float64 refinement misses ends there "
                          "instead of restarting with float64 stepping (the float32 stack alone)")
