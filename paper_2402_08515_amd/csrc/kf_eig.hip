@@ -390,8 +390,12 @@ __global__ __launch_bounds__(256) void k_bisect(int m, const double* __restrict_
   if (lane == 0) theta[i] = 0.5 * (lo + hi);
 }
 
-// Inverse iteration, one lane per cluster of selected eigenvalues; the
-// recurrences carry their running values in registers.  The lane's work
+// Inverse iteration, one lane per selected eigenvalue; the recurrences carry
+// their running values in registers.  Within a cluster of (nearly) equal
+// values the shifts are kept 10 eps apart and each member starts from its own
+// vector (its position in the cluster sets the phase), so the members
+// converge to different directions of the eigenspace; k_cluster_orth then
+// orthonormalises each cluster's vectors.  The lane's work
 // arrays (LU factors and the iterate) are interleaved across lanes, element i
 // of lane c at [i * ldw + c], so that at every step the lanes of a wavefront
 // touch consecutive addresses.  Finished vectors go to Z (m x nsel).
@@ -407,22 +411,31 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
                                               double* __restrict__ Z, double* __restrict__ scratch, int ldw) {
   extern __shared__ double ivs[];
   if (LDS && (int)threadIdx.x >= ldw) return;
-  const int cl = LDS ? blockIdx.x * ldw + threadIdx.x : blockIdx.x * blockDim.x + threadIdx.x;
-  if (cl >= ncl) return;
+  const int s = LDS ? blockIdx.x * ldw + threadIdx.x : blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsel = cstart[ncl];
+  if (s >= nsel) return;
   const double tn = fmax(fabs(bounds[0]), fabs(bounds[1]));
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
   const int64_t blk = (int64_t)m * ldw;
-  double* __restrict__ rinv = LDS ? ivs + threadIdx.x : scratch + cl;
+  double* __restrict__ rinv = LDS ? ivs + threadIdx.x : scratch + s;
   double* __restrict__ u1 = rinv + blk;
   double* __restrict__ u2 = u1 + blk;
   double* __restrict__ lm = u2 + blk;
   double* __restrict__ pv = lm + blk;
   double* __restrict__ z = pv + blk;
-  double prev_lam = -INFINITY;
-  for (int s = cstart[cl]; s < cstart[cl + 1]; ++s) {
-    double lam = sel[s];
-    if (s > cstart[cl] && lam - prev_lam < 10.0 * tiny) lam = prev_lam + 10.0 * tiny;
-    prev_lam = lam;
+  {
+    // the cluster holding s (cstart ascending, cstart[0] = 0)
+    int lo = 0, hi = ncl;  // cstart[lo] <= s < cstart[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (cstart[mid] <= s) lo = mid;
+      else hi = mid;
+    }
+    const int c0 = cstart[lo];
+    // shifts of the cluster's members up to s, each at least 10 eps above the last
+    double lam = sel[c0];
+    for (int t = c0 + 1; t <= s; ++t) lam = sel[t] - lam < 10.0 * tiny ? lam + 10.0 * tiny : sel[t];
+    const int pos = s - c0;
     // LU of T - lam I with partial pivoting; row i is (a, b, c) at columns
     // (i, i+1, i+2) while it is being eliminated.  The recurrences below load
     // kIvB rows ahead of the running values (the loads do not depend on them).
@@ -476,7 +489,7 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
     u1[ol] = 0.0;
     u2[ol] = 0.0;
     if (m >= 2) u2[ol - ldw] = 0.0;
-    for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * (s - cstart[cl]) + 0.1);
+    for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * pos + 0.1);
     for (int it = 0; it < 3; ++it) {
       // forward: row swaps and elimination, running value in a register
       double y = z[0];
@@ -533,12 +546,6 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
       }
       const double r = mx > 0.0 ? 1.0 / mx : 0.0;
       for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] *= r;
-      for (int q = cstart[cl]; q < s; ++q) {
-        const double* zq = Z + (int64_t)q * m;
-        double dot = 0.0;
-        for (int i = 0; i < m; ++i) dot = fma(zq[i], z[(int64_t)i * ldw], dot);
-        for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] -= dot * zq[i];
-      }
       double nrm = 0.0;
       for (int i = 0; i < m; ++i) nrm = fma(z[(int64_t)i * ldw], z[(int64_t)i * ldw], nrm);
       const double rn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
@@ -546,6 +553,46 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
     }
     double* __restrict__ zs = Z + (int64_t)s * m;
     for (int i = 0; i < m; ++i) zs[i] = z[(int64_t)i * ldw];
+  }
+}
+
+// The vectors of each cluster with more than one member (Z columns
+// cstart[c] .. cstart[c+1]-1): classical Gram-Schmidt twice against the
+// cluster's earlier members, then normalisation; one workgroup per cluster.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_cluster_orth(int m, int ncl, const int32_t* __restrict__ cstart,
+                                                      double* __restrict__ Z) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  if (c >= ncl) return;
+  const int c0 = cstart[c], c1 = cstart[c + 1];
+  if (c1 - c0 < 2) return;
+  for (int j = c0; j < c1; ++j) {
+    double* zj = Z + (int64_t)j * m;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = c0; q < j; ++q) {
+        const double* zq = Z + (int64_t)q * m;
+        double dot = 0.0;
+        for (int i = threadIdx.x; i < m; i += 256) dot = fma(zq[i], zj[i], dot);
+        dot = block_sum256(dot, red);
+        for (int i = threadIdx.x; i < m; i += 256) zj[i] -= dot * zq[i];
+        __syncthreads();
+      }
+    }
+    double nrm = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) nrm = fma(zj[i], zj[i], nrm);
+    nrm = block_sum256(nrm, red);
+    const double rn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) zj[i] *= rn;
+    __syncthreads();
   }
 }
 
@@ -678,14 +725,18 @@ int eig_vectors(EigWork& w, int k, const double* theta_sel, const int32_t* clust
   const int lds_lanes = std::min(64, kIvLdsBytes / (6 * 8 * k));
   if (lds_lanes >= 1) {
     const size_t lds = sizeof(double) * 6 * (size_t)k * lds_lanes;
-    hipLaunchKernelGGL(k_invit<true>, dim3(cdiv(nclusters, lds_lanes)), dim3(64), lds, st, k, w.d, w.e, w.bounds,
+    hipLaunchKernelGGL(k_invit<true>, dim3(cdiv(nsel, lds_lanes)), dim3(64), lds, st, k, w.d, w.e, w.bounds,
                        nclusters, w.cl, w.sel, w.Z, w.scratch, lds_lanes);
   } else {
-    const int ldw = cdiv(nclusters, 64) * 64;  // <= nsel + 63
-    hipLaunchKernelGGL(k_invit<false>, dim3(cdiv(nclusters, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters,
+    const int ldw = cdiv(nsel, 64) * 64;  // <= nsel + 63
+    hipLaunchKernelGGL(k_invit<false>, dim3(cdiv(nsel, 64)), dim3(64), 0, st, k, w.d, w.e, w.bounds, nclusters,
                        w.cl, w.sel, w.Z, w.scratch, ldw);
   }
   KF_HIP(hipGetLastError());
+  if (nclusters < nsel) {
+    hipLaunchKernelGGL(k_cluster_orth, dim3(nclusters), dim3(256), 0, st, k, nclusters, w.cl, w.Z);
+    KF_HIP(hipGetLastError());
+  }
   const int grid = cdiv(nsel, 4);
   const int mt = cdiv(k, 64);
   if (mt <= 1)

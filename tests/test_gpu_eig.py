@@ -43,6 +43,34 @@ def test_eigenvalues_and_vectors(k):
         assert np.abs(Y.T @ Y - np.eye(sel.size)).max() <= 1e-10
 
 
+@pytest.mark.parametrize("k", [40, 300, 900])
+def test_large_clusters_get_orthonormal_vectors(k):
+    # an 8-fold and a 4-fold eigenvalue and three exact pairs inside the
+    # selected range: every member of a cluster is found from its own start
+    # vector, then the cluster's vectors are orthonormalised
+    kf = _kf()
+    print(f"case sym_eig clusters k={k}", flush=True)
+    rng = np.random.default_rng(500 + k)
+    lam = np.sort(rng.uniform(-3.0, 5.0, size=k))
+    i0 = k // 3
+    lam[i0 : i0 + 8] = lam[i0]
+    lam[i0 + 10 : i0 + 14] = lam[i0 + 10]
+    for j in (i0 + 16, i0 + 19, i0 + 22):
+        lam[j + 1] = lam[j]
+    lam = np.sort(lam)
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    A = (Q * lam) @ Q.T
+    lo, hi = lam[max(i0 - 3, 0)] - 1e-3, lam[min(i0 + 30, k - 1)] + 1e-3
+    theta, Y = kf.sym_eig(A, lo, hi, vectors=True)
+    scale = np.abs(lam).max()
+    assert np.abs(theta - lam).max() <= 1e-12 * scale * max(1.0, np.sqrt(k) / 8)
+    sel = theta[(theta >= lo) & (theta <= hi)]
+    assert sel.size >= 20
+    R = A @ Y - Y * sel
+    assert np.abs(R).max() <= 1e-11 * scale
+    assert np.abs(Y.T @ Y - np.eye(sel.size)).max() <= 1e-10
+
+
 def test_values_only_and_asymmetric_input_is_averaged():
     kf = _kf()
     A, lam = _matrix(200, 7, clusters=False)
