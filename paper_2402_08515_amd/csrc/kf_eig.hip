@@ -489,7 +489,18 @@ __global__ __launch_bounds__(64) void k_invit(int m, const double* __restrict__ 
     u1[ol] = 0.0;
     u2[ol] = 0.0;
     if (m >= 2) u2[ol - ldw] = 0.0;
-    for (int i = 0; i < m; ++i) z[(int64_t)i * ldw] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * pos + 0.1);
+    // start vector: 1 + 0.5 u, u in [-1, 1) from an integer hash of (row,
+    // position in the cluster), so that the members of a cluster start from
+    // linearly independent vectors
+    for (int i = 0; i < m; ++i) {
+      uint32_t h = (uint32_t)i * 0x9E3779B1u ^ ((uint32_t)pos + 1u) * 0x85EBCA77u;
+      h ^= h >> 16;
+      h *= 0x7FEB352Du;
+      h ^= h >> 15;
+      h *= 0x846CA68Bu;
+      h ^= h >> 16;
+      z[(int64_t)i * ldw] = 1.0 + 0.5 * ((double)h * (2.0 / 4294967296.0) - 1.0);
+    }
     for (int it = 0; it < 3; ++it) {
       // forward: row swaps and elimination, running value in a register
       double y = z[0];
