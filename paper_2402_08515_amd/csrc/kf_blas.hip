@@ -1066,14 +1066,17 @@ int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* ga
 int gemv_n_sub(int32_t n, int k, const double* Bk, int64_t ldb, const double* H, int64_t ldh, double* X,
                int64_t ldx, int nrhs, hipStream_t st, const int32_t* gate) {
   if (k <= 0 || nrhs <= 0) return KF_OK;
-  const int NR = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8);
+  // (up to 16 right-hand sides in one pass over the basis)
+  const int NR = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : (nrhs <= 8 ? 8 : 16));
   const dim3 grid(ceil_div64(n, 256), ceil_div64(nrhs, NR));
   if (NR == 1)
     hipLaunchKernelGGL((k_gemv_n<1, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
   else if (NR == 4)
     hipLaunchKernelGGL((k_gemv_n<4, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
-  else
+  else if (NR == 8)
     hipLaunchKernelGGL((k_gemv_n<8, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
+  else
+    hipLaunchKernelGGL((k_gemv_n<16, true>), grid, dim3(256), 0, st, n, k, Bk, ldb, H, ldh, X, ldx, nrhs, gate);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
