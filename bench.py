@@ -724,7 +724,7 @@ def bench_learned(args):
                 continue
             # set-up (operator, autotuned step) outside the timed region, for every weight set alike
             prob = kf.Problem(S, m, lo, hi, tau, L, precision=args.learned_precision, target=tgt, check_every=2,
-                              check_growth=0.1, autotune=True)
+                              check_growth=args.learned_check_growth, autotune=True)
             prob.set_weights(w)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -753,7 +753,7 @@ def bench_learned(args):
         "n_gpus": 1,
         "config": {"workload": f"grid3d_{n} learned-vs-Fourier", "intervals": len(rows), "tol": args.tol,
                    "precision": args.learned_precision, "max_target": args.learned_max_target,
-                   "m_max": args.learned_m_max},
+                   "m_max": args.learned_m_max, "check_growth": args.learned_check_growth},
         "train_seconds": t_train,
         "train_loss_first_last": [float(hist[0]), float(hist[-1])],
         "fourier_seconds": tot("fourier", "seconds"),
@@ -816,6 +816,8 @@ def main():
                     help="learned: intervals holding more distinct eigenvalues are skipped (three of the 32 hold "
                          "538-618, beyond what a 2048-column basis resolves with one start vector)")
     ap.add_argument("--learned-m-max", type=int, default=2048, help="learned: basis columns per solve")
+    ap.add_argument("--learned-check-growth", type=float, default=0.1,
+                    help="learned: basis growth between Rayleigh-Ritz checks")
     ap.add_argument("--learned-precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--forms-count", type=int, default=16, help="squares in the forms comparison")
