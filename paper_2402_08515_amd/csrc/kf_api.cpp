@@ -707,7 +707,8 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
     } else {
       KF_TRY(gemv_t(n, ldc, p->B, ldb, nullptr, 0, 0, X, nb, ldb, p->d_m, coef, ldc, p->gw, st));
     }
-    if (gated) KF_TRY(reorth_gate(kb, cx, cx + kb, p->opt.reorth_tol, gate, st));
+    if (gated && nb == 1) KF_TRY(reorth_gate(kb, cx, cx + kb, p->opt.reorth_tol, gate, st));
+    if (gated && nb > 1) KF_TRY(reorth_gate_block(kb, nb, cx, ldc, p->opt.reorth_tol, gate, st));
     if (carried && local && with_pending && pn > 0 && nb == 1) {
       // columns kb - 1 and kb in one pass over the basis: the coefficients of
       // column kb - 1 (without its own row) beside those of the new column
@@ -872,9 +873,13 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
         rb.land();
       }
     } else {
-      KF_TRY(full_pass(true));
+      // (the window pass was the first pass: this one subtracts only where a
+      // coefficient exceeds reorth_tol times its column's M-norm, as for
+      // single vectors)
+      const bool gated = p->opt.reorth_tol > 0.0;
+      KF_TRY(full_pass(true, gated));
       int32_t* loose = p->flags + 33;
-      int32_t lh = 0;
+      int32_t lh = 0, gh = 1;
       const bool gate_pending = pending_loose && pn > 0 && local;
       // columns formed since the previous projection were orthogonalised
       // against their window only: their drift from M-orthogonality with the
@@ -884,9 +889,11 @@ int orth_block(kf_problem* p, int kb, int c0, int nb, int* kept, std::vector<dou
       KF_TRY(fetch(coef + (int64_t)(2 * pn) * ldc, (size_t)ldc * nb, hg1.data()));
       KF_TRY(fetch(g2, (size_t)nb * nb, hg2.data()));
       if (gate_pending) KF_TRY(rb.get(&lh, loose, sizeof(int32_t)));
+      if (gated) KF_TRY(rb.get(&gh, gate, sizeof(int32_t)));
       KF_HIP(hipStreamSynchronize(st));
       rb.land();
       if (pending_loose) *pending_loose = lh != 0;
+      if (full_passes && gated && gh) ++*full_passes;
       if (lh) {
         // repair the drifted columns, then orthogonalise the block against
         // the repaired basis twice

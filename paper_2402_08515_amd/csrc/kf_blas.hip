@@ -982,6 +982,27 @@ __global__ __launch_bounds__(256) void k_reorth_gate(int k, const double* __rest
   }
 }
 
+// Block form: *gate = 0 when every column j < nb of c (rows < k, leading
+// dimension ldc) has max_i |c[i, j]| <= tol * sqrt(c[k + j, j]) (its squared
+// M-norm sits in row k + j), else 1.
+__global__ __launch_bounds__(256) void k_reorth_gate_block(int k, int nb, const double* __restrict__ c, int64_t ldc,
+                                                           double tol, int32_t* __restrict__ gate) {
+  __shared__ int red[4];
+  int over = 0;
+  for (int64_t t = threadIdx.x; t < (int64_t)k * nb; t += blockDim.x) {
+    const int j = (int)(t / k), i = (int)(t - (int64_t)j * k);
+    const double v = fabs(c[i + (int64_t)j * ldc]);
+    const double nrm = sqrt(fmax(c[k + j + (int64_t)j * ldc], 0.0));
+    // (a non-finite coefficient or norm always subtracts)
+    if (!(v <= tol * nrm)) over = 1;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) over |= __shfl_xor(over, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = over;
+  __syncthreads();
+  if (threadIdx.x == 0) *gate = (red[0] | red[1] | red[2] | red[3]) ? 1 : 0;
+}
+
 // Orthogonality of np basis columns p0.. against the whole basis: G[:, c]
 // (c < np, leading dimension ldg, rows < k) against the identity.
 __global__ __launch_bounds__(256) void k_block_gate(int k, int p0, int np, const double* __restrict__ G, int64_t ldg,
@@ -1059,6 +1080,12 @@ int nonfinite_flag(int64_t cnt, const double* x, int32_t* flag, hipStream_t st) 
 
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st) {
   hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(256), 0, st, k, c, g, tol, gate);
+  KF_HIP(hipGetLastError());
+  return KF_OK;
+}
+
+int reorth_gate_block(int k, int nb, const double* c, int64_t ldc, double tol, int32_t* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_gate_block, dim3(1), dim3(256), 0, st, k, nb, c, ldc, tol, gate);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }

@@ -223,6 +223,9 @@ int nonfinite_flag(int64_t cnt, const double* x, int32_t* flag, hipStream_t st);
 
 // *gate = 1 if max_j |c[j]| (j < k) > tol * sqrt(*g), else 0 (device values)
 int reorth_gate(int k, const double* c, const double* g, double tol, int32_t* gate, hipStream_t st);
+// *gate = 1 if some column j < nb of c (rows < k, leading dimension ldc) has
+// max_i |c[i, j]| > tol * sqrt(c[k + j, j]), else 0 (device values)
+int reorth_gate_block(int k, int nb, const double* c, int64_t ldc, double tol, int32_t* gate, hipStream_t st);
 
 // out[:, 0] = c_last with row kb-1 set to 0, out[:, 1] = cx (rows < kb,
 // leading dimension ldo); *gate = 1 if some |c_last[j]| (j < kb-1) > tol,
