@@ -95,11 +95,10 @@ typedef struct kf_options {
                             is <= drop_tol times its M-norm before is dropped
                             (breakdown test of Algorithm 2.5 with a tolerance);
                             0 selects 1e-10 */
-  double reorth_tol;     /* single-vector blocks with full_reorth 0: the
-                            coefficients against the whole basis are always
-                            computed (they are needed for B^T S B), but
-                            subtracted only when one exceeds reorth_tol times
-                            the column's M-norm; with the pending-column check
+  double reorth_tol;     /* full_reorth 0: at a projection onto the whole
+                            basis the coefficients are always computed (they
+                            are needed for B^T S B), but subtracted only when
+                            one exceeds reorth_tol times its column's M-norm; with the pending-column check
                             of proj_every the basis stays M-orthonormal to
                             about 1e-7 (reported as kf_result.orth_error);
                             0 = always subtract */
@@ -238,7 +237,7 @@ typedef struct kf_result {
                              residuals */
   double t_refine;        /* seconds in the mixed-mode refinement */
   double orth_error;      /* max |B^T M B - I| over the columns checked */
-  int32_t full_passes;    /* Gram-Schmidt passes over the whole basis */
+  int32_t full_passes;    /* Gram-Schmidt subtractions over the whole basis */
   int64_t refine_vector_steps; /* vector time steps of the float64 refinement
                                   (KF_MIXED), not in leapfrog_vector_steps for
                                   kf_solve; included in it for
