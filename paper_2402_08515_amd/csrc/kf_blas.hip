@@ -700,26 +700,43 @@ __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const do
   const int rows = (int)std::min<int64_t>(kWinCH, (int64_t)n - r0);
   const double* __restrict__ x = L + (int64_t)lw * ldl;
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-    const int64_t i = r0 + r;
-    const double mi = m[i];
-    const double xm = x[i] * mi;
-    const double l0 = lw > 0 ? L[i] : 0.0;
-    const double l1 = lw > 1 ? L[i + ldl] : 0.0;
+  auto add = [&](double xi, double mi, double l0, double l1) {
+    const double xm = xi * mi;
     if (lw == 2) {
       s[0] = fma(l0, xm, s[0]);
       s[1] = fma(l1, xm, s[1]);
-      s[2] = fma(x[i], xm, s[2]);
+      s[2] = fma(xi, xm, s[2]);
       const double l0m = l0 * mi;
       s[3] = fma(l0, l0m, s[3]);
       s[4] = fma(l1, l0m, s[4]);
       s[5] = fma(l1, l1 * mi, s[5]);
     } else if (lw == 1) {
       s[0] = fma(l0, xm, s[0]);
-      s[1] = fma(x[i], xm, s[1]);
+      s[1] = fma(xi, xm, s[1]);
       s[2] = fma(l0, l0 * mi, s[2]);
     } else {
-      s[0] = fma(x[i], xm, s[0]);
+      s[0] = fma(xi, xm, s[0]);
+    }
+  };
+  if (rows == kWinCH) {
+    // a full chunk: every load of the thread's four rows issued before the
+    // sums (same order of summation as the loop below)
+    constexpr int U = kWinCH / 256;
+    double xv[U], mv[U], l0v[U], l1v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = r0 + threadIdx.x + 256 * u;
+      xv[u] = x[i];
+      mv[u] = m[i];
+      l0v[u] = lw > 0 ? L[i] : 0.0;
+      l1v[u] = lw > 1 ? L[i + ldl] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) add(xv[u], mv[u], l0v[u], l1v[u]);
+  } else {
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+      const int64_t i = r0 + r;
+      add(x[i], m[i], lw > 0 ? L[i] : 0.0, lw > 1 ? L[i + ldl] : 0.0);
     }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -738,13 +755,14 @@ __global__ __launch_bounds__(256) void k_window_dots(int32_t n, int lw, const do
 // g < 1e-4 x^T M x that rounding is no longer small: status 2 tells the caller
 // to normalise explicitly (x is then only subtracted).  Writes T = [c, x^T M x],
 // coef = {c_0, c_1, scale} for k_window_scale and rec = {T[0..lw], g, status}.
-__global__ __launch_bounds__(256) void k_window_reduce(int lw, const double* __restrict__ partial, int nchunks,
+__global__ __launch_bounds__(512) void k_window_reduce(int lw, const double* __restrict__ partial, int nchunks,
                                                        double* __restrict__ T, double* __restrict__ coef,
                                                        double* __restrict__ rec, double* __restrict__ hrec) {
   __shared__ double ds[6];
   const int nd = window_dot_count(lw);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = wave; d < nd; d += 4) {
+  // (a wavefront per sum: at most six sums, eight wavefronts)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int d = wave; d < nd; d += nw) {
     const double v = wave_strided_sum(partial + (int64_t)d * nchunks, nchunks, 1, lane);
     if (lane == 0) ds[d] = v;
   }
@@ -808,7 +826,7 @@ int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, Gemv
   }
   hipLaunchKernelGGL(k_window_dots, dim3(nchunks), dim3(256), 0, st, n, lw, L, ldl, m, wk.partial);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec, host_rec);
+  hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(512), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec, host_rec);
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_window_scale, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, lw, L, ldl, rec + 8);
   KF_HIP(hipGetLastError());
