@@ -792,15 +792,31 @@ __global__ __launch_bounds__(512) void k_window_reduce(int lw, const double* __r
 }
 
 // x <- (x - c_0 L_0 - c_1 L_1) * scale with the coefficients of k_window_reduce
+// (four rows per thread, 256 apart: every load issued before the stores)
 __global__ __launch_bounds__(256) void k_window_scale(int32_t n, int lw, double* __restrict__ L, int64_t ldl,
                                                       const double* __restrict__ coef) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  constexpr int U = 4;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x;
   double* x = L + (int64_t)lw * ldl;
-  double v = x[i];
-  if (lw > 0) v = fma(-coef[0], L[i], v);
-  if (lw > 1) v = fma(-coef[1], L[i + ldl], v);
-  x[i] = v * coef[2];
+  const double c0 = lw > 0 ? coef[0] : 0.0, c1 = lw > 1 ? coef[1] : 0.0, sc = coef[2];
+  double v[U], a[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = i0 + 256 * u;
+    const bool ok = i < n;
+    v[u] = ok ? x[i] : 0.0;
+    a[u] = ok && lw > 0 ? L[i] : 0.0;
+    b[u] = ok && lw > 1 ? L[i + ldl] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = i0 + 256 * u;
+    if (i >= n) break;
+    double t = v[u];
+    if (lw > 0) t = fma(-c0, a[u], t);
+    if (lw > 1) t = fma(-c1, b[u], t);
+    x[i] = t * sc;
+  }
 }
 
 }  // namespace
@@ -828,7 +844,7 @@ int window_step(int32_t n, int lw, double* L, int64_t ldl, const double* m, Gemv
   KF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(512), 0, st, lw, wk.partial, nchunks, T, rec + 8, rec, host_rec);
   KF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_window_scale, dim3(ceil_div64(n, 256)), dim3(256), 0, st, n, lw, L, ldl, rec + 8);
+  hipLaunchKernelGGL(k_window_scale, dim3(ceil_div64(n, 1024)), dim3(256), 0, st, n, lw, L, ldl, rec + 8);
   KF_HIP(hipGetLastError());
   return KF_OK;
 }
