@@ -338,7 +338,37 @@ __global__ __launch_bounds__(256) void k_leapfrog_batch(int32_t nslices, const i
   T sum[B];
 #pragma unroll
   for (int j = 0; j < B; ++j) sum[j] = (T)0;
-  for (int q = 0; q < width; ++q) {
+  int q = 0;
+  if constexpr (B <= 4) {
+    // four entries at a time: their values, indices and gathers all in flight
+    // before the sums (the same order of summation as the loop below)
+    constexpr int U = 8;
+    for (; q < width; q += U) {
+      // (entries past the row's width: value 0 and the row's own index, whose
+      // products add exactly nothing)
+      T av[U];
+      IT cv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = q + u < width;
+        const int64_t o = (int64_t)(ok ? q + u : q) * 64;
+        av[u] = ok ? (NT ? __builtin_nontemporal_load(vp + o) : vp[o]) : (T)0;
+        cv[u] = ok ? (NT ? __builtin_nontemporal_load(ip + o) : ip[o]) : (IT)(relative ? 0 : row);
+      }
+      Row<T, B> xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = relative ? row + (int)cv[u] : (int)cv[u];
+        xv[u] = *reinterpret_cast<const Row<T, B>*>(cur + (int64_t)c * B);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) sum[j] = fma(av[u], xv[u].v[j], sum[j]);
+      }
+    }
+  }
+  for (; q < width; ++q) {
     const T a = NT ? __builtin_nontemporal_load(vp + (int64_t)q * 64) : vp[(int64_t)q * 64];
     const IT ci = NT ? __builtin_nontemporal_load(ip + (int64_t)q * 64) : ip[(int64_t)q * 64];
     const int c = relative ? row + (int)ci : (int)ci;
