@@ -827,7 +827,7 @@ def main():
                     help="for hardware-counter runs: a few filter applications and a plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not part of it",
+        print("bench.py: one GPU only (--gpus 1); runs on several GPUs are not supported",
               file=sys.stderr)
         sys.exit(2)
 
