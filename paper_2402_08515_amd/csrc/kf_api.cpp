@@ -1,6 +1,6 @@
-// C ABI and host driver of the filtered time-domain Krylov eigensolver.
+// C ABI and host-side control of the filtered time-domain Krylov eigensolver.
 //
-// The driver follows Algorithm 2.5 (Krylov loop around the time loop) with
+// The solve follows Algorithm 2.5 (Krylov loop around the time loop) with
 // the readings adopted for this library: block of b start vectors, M-inner
 // classical Gram-Schmidt applied twice, a relative drop test instead of an
 // exact zero (breakdown), and Rayleigh-Ritz on the projected pencil of eq.
